@@ -1,0 +1,225 @@
+/*
+ * mpbjac -- mixed-precision block-Jacobi preconditioned conjugate gradient
+ * for one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libmpbjac.so. Every entry point takes plain pointers
+ * and sizes; "device" pointers are HIP device memory (the caller may obtain it
+ * from any allocator), "host" pointers are ordinary host memory. No entry
+ * point allocates device memory: the caller passes workspaces whose sizes the
+ * *_query calls report. Work is enqueued on the caller's HIP stream (passed
+ * as void*, NULL = the default stream); calls return after it is enqueued
+ * unless stated otherwise. No C++ exception crosses this boundary. Handles
+ * are not thread-safe; distinct handles may be used from distinct threads.
+ *
+ * Method (arXiv 2407.15973, "Mixed Precision Block-Jacobi Preconditioner"):
+ *   Sec. 3.1, eq. 3-1 with one outer step: M^-1 = D_b^-1, the inverse of the
+ *     block-diagonal part of A on a partition into contiguous row blocks;
+ *   Sec. 3.2, Algorithm 3.1 (fMP): each block inverse is formed in FP64 and
+ *     stored in a lower precision; r is converted to FP32, multiplied in the
+ *     low format with FP32 accumulation, the result widened to FP64;
+ *   Algorithms 3.2 / 3.3 (aMP hl / lh): per application, the all-FP64 or the
+ *     low map is chosen by comparing the recursive relative residual with
+ *     adp_tol; the first application sees relres = +infinity;
+ *   PCG (Sec. 3.2, Hestenes-Stiefel) runs entirely in FP64 with x0 = 0 and
+ *     stops when ||r_j|| / ||r_0|| <= tol (Sec. 4.2).
+ * Per-block precision maps beyond the paper: a condition/dominance rule and a
+ * learned selector (16 block features -> MLP 16-64-64-3).
+ */
+#ifndef MPBJAC_H
+#define MPBJAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPBJAC_ABI_VERSION 1
+#define BJAC_MAX_BLOCK 64        /* largest diagonal block (rows) */
+#define BJAC_NFEAT 16            /* block features per block */
+#define BJAC_MLP_NPARAM 5443     /* W1[64,16] b1[64] W2[64,64] b2[64] W3[3,64] b3[3] */
+#define BJAC_MLP_NBLOB (BJAC_MLP_NPARAM + 2 * BJAC_NFEAT)  /* + feature mean, std */
+
+/* ---- return codes ---------------------------------------------------- */
+enum {
+  BJAC_OK = 0,
+  BJAC_NOT_CONVERGED = 1,   /* maxit reached; x holds the last iterate      */
+  BJAC_EINVAL = -1,         /* bad argument (null pointer, size, partition) */
+  BJAC_ENOTSPD = -2,        /* a diagonal block had a non-positive pivot    */
+  BJAC_EBREAKDOWN = -3,     /* p^T A p <= 0, (r, z) <= 0, or non-finite     */
+  BJAC_EHIP = -4,           /* a HIP runtime call failed                    */
+  BJAC_ENOMEM = -5          /* workspace smaller than the query reported    */
+};
+
+/* ---- storage precisions of a block inverse ---------------------------- */
+typedef enum { BJAC_FP64 = 0, BJAC_FP32 = 1, BJAC_BF16 = 2, BJAC_FP16 = 3 } bjac_prec;
+
+/* ---- how the per-block precision map is chosen ------------------------ */
+typedef enum {
+  BJAC_UNIFORM = 0,   /* every block FP64 (uniform-BJAC of Sec. 4.2)          */
+  BJAC_FIXED = 1,     /* every block in policy.low (fMP-BJAC, Algorithm 3.1)  */
+  BJAC_RULE = 2,      /* lowest of FP16/FP32/FP64 with kappa_1(A_ii) u <= theta,
+                         FP16 also needing row dominance >= d16               */
+  BJAC_LEARNED = 3,   /* argmax of the selector MLP on the block features     */
+  BJAC_EXPLICIT = 4   /* policy.explicit_tags                                 */
+} bjac_mode;
+
+/* ---- temporal switch between the all-FP64 map and the chosen map ------ */
+typedef enum {
+  BJAC_TEMPORAL_NONE = 0,
+  BJAC_TEMPORAL_HL = 1,   /* Algorithm 3.2: FP64 while relres >= adp_tol */
+  BJAC_TEMPORAL_LH = 2    /* Algorithm 3.3: low map while relres >= adp_tol */
+} bjac_temporal;
+
+/* Square CSR matrix, all arrays device memory, caller-owned, read-only.
+ * row_ptr[n+1] (row_ptr[0] = 0, non-decreasing), col_idx[nnz] in [0, n),
+ * val[nnz] FP64. Columns need not be sorted. A must be symmetric positive
+ * definite for PCG; the setup only needs SPD diagonal blocks. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *val;
+} bjac_csr;
+
+typedef struct {
+  int32_t mode;                  /* bjac_mode                                  */
+  int32_t low;                   /* bjac_prec used by BJAC_FIXED               */
+  int32_t temporal;              /* bjac_temporal                              */
+  int32_t reserved;
+  double adp_tol;                /* threshold of the temporal switch           */
+  double theta;                  /* RULE: kappa_1 * u <= theta (default 1e-2)  */
+  double d16;                    /* RULE: min row dominance for FP16 (1.0)     */
+  const float *mlp_blob;         /* LEARNED: device, BJAC_MLP_NBLOB floats     */
+  const uint8_t *explicit_tags;  /* EXPLICIT: host, nb entries of bjac_prec    */
+} bjac_policy;
+
+typedef struct bjac_handle bjac_handle;
+
+typedef struct {
+  int64_t n;
+  int32_t nb;
+  int32_t max_block;
+  int32_t blocks_per_prec[4];    /* low map histogram, indexed by bjac_prec    */
+  int64_t low_bytes;             /* bytes of the stored low map                */
+  int64_t high_bytes;            /* bytes of the all-FP64 map (temporal only)  */
+  int32_t temporal;
+  int32_t mode;
+  int32_t ntiles;                /* apply tiles (whole blocks, <= 256 padded rows) */
+  int32_t reserved;
+} bjac_info;
+
+typedef struct {
+  double tol;                    /* stop when ||r|| / ||b|| <= tol             */
+  int32_t maxit;
+  int32_t chunk;                 /* iterations per captured graph launch (0 = 16) */
+  double *relres_hist;           /* optional device buffer [maxit]: relres after
+                                    each x update                              */
+  uint8_t *high_hist;            /* optional device buffer [maxit + 1]: 1 where
+                                    the application used the FP64 map          */
+  int32_t profile;               /* 1: launch without graphs, time every kernel
+                                    with HIP events on the stream (stats.*_ms) */
+  int32_t reserved;
+} bjac_solve_opts;
+
+typedef struct {
+  int32_t iters;                 /* x updates performed                        */
+  int32_t status;                /* BJAC_OK, BJAC_NOT_CONVERGED, BJAC_EBREAKDOWN */
+  double relres;                 /* recursive ||r|| / ||b|| at exit            */
+  double rnorm0;                 /* ||b||                                      */
+  int32_t high_applications;     /* applications that used the FP64 map       */
+  int32_t graph_launches;
+  double solve_ms;               /* wall time of the solve on the stream       */
+  /* profile mode only: summed kernel durations over the iterations that ran */
+  double spmv_ms, apply_ms, update_ms;
+  int32_t n_spmv, n_apply, n_update;
+  int32_t reserved;
+} bjac_stats;
+
+/* ---- library ------------------------------------------------------------ */
+int bjac_abi_version(void);
+const char *bjac_strerror(int code);
+
+/* ---- block-Jacobi setup (Sec. 3.1 D_b, Algorithm 3.1 storage) -----------
+ * block_ptr: HOST array of nb+1 row offsets, block_ptr[0] = 0,
+ * block_ptr[nb] = n, 1 <= block size <= BJAC_MAX_BLOCK.
+ * bjac_setup_query reports the workspace the setup needs (an upper bound
+ * valid for any precision map the policy can produce).
+ * bjac_setup extracts every diagonal block from the CSR rows, inverts it in
+ * FP64 (Gauss-Jordan without pivoting, valid for SPD blocks), computes the 16
+ * block features, selects the block precisions, scales and rounds (correctly
+ * rounded from FP64, ties to even) and stores them in *workspace, which must
+ * stay alive and untouched until bjac_destroy. It synchronises the stream
+ * once when the policy's map depends on the data (RULE, LEARNED) and once at
+ * its end. A is only read during the call. On error no handle is returned. */
+int bjac_setup_query(const bjac_csr *A, const int32_t *block_ptr, int32_t nb,
+                     const bjac_policy *policy, size_t *workspace_bytes);
+int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t nb,
+               const bjac_policy *policy, void *workspace, size_t workspace_bytes,
+               void *stream, bjac_handle **out);
+void bjac_destroy(bjac_handle *h);
+int bjac_get_info(const bjac_handle *h, bjac_info *info);
+/* Copies to HOST memory: tags[nb] (bjac_prec of the low map),
+ * features[nb * 16] (FP32, row-major), synchronising the handle's stream. */
+int bjac_get_tags(const bjac_handle *h, uint8_t *tags);
+int bjac_get_features(const bjac_handle *h, float *features);
+/* Copies one stored block to HOST memory as FP64 values of the stored
+ * numbers (b x b, row-major) and its scale s (the block represents s * out).
+ * which = 0: low map, 1: all-FP64 map (temporal handles only). */
+int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block, double *out, double *scale);
+
+/* ---- z = M^-1 r (eq. 3-1, k = 1; Algorithm 3.1) --------------------------
+ * r, z: device FP64 vectors of length n (distinct). which = 0 applies the
+ * low map, 1 the all-FP64 map (temporal handles; for others both are the
+ * low map). Reduced blocks use the FP32 copy of r and FP32 accumulation. */
+int bjac_apply(const bjac_handle *h, int32_t which, const double *r, double *z, void *stream);
+
+/* ---- q = A p, the FP64 CSR product used by PCG ------------------------- */
+int bjac_spmv(const bjac_csr *A, const double *p, double *q, void *stream);
+
+/* ---- correctly rounded conversion (the storage step of Algorithm 3.1) ---
+ * out[i] = RNE_prec(in[i] / scale), with scale a power of two; out is FP32,
+ * BF16 or FP16 bits (2 or 4 bytes per element), device memory. */
+int bjac_round(const double *in, void *out, int64_t count, int32_t prec, double scale, void *stream);
+
+/* ---- PCG (Sec. 3.2; Sec. 4.2 stopping test, x0 = 0) ---------------------
+ * pcg_workspace_query: bytes of the solver workspace for n rows.
+ * pcg_solve: solves A x = b; b, x device FP64 [n] (x is overwritten). The
+ * iterations run as captured HIP graphs of opts->chunk iterations with all
+ * scalars on the device; the host reads one status word per graph launch.
+ * Returns BJAC_OK, BJAC_NOT_CONVERGED, BJAC_EBREAKDOWN or an error; stats may
+ * be NULL. The call synchronises the stream before it returns. */
+int pcg_workspace_query(int64_t n, size_t *workspace_bytes);
+int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *x,
+              const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes,
+              bjac_stats *stats, void *stream);
+
+/* ---- learned per-block precision selector -------------------------------
+ * Network: standardised 16 block features -> 64 ReLU -> 64 ReLU -> 3 logits
+ * (class 0 = FP64, 1 = FP32, 2 = FP16), FP32 throughout. blob: device
+ * BJAC_MLP_NBLOB floats = the 5443 parameters (layout in BJAC_MLP_NPARAM's
+ * comment, row-major out x in) followed by the feature mean[16] and std[16].
+ * feat: device [n * 16] FP32. Block features correlate with the mixed-
+ * precision convergence delay (Sec. 4.5: multiscale strength, eq. 4-5, and
+ * diagonal dominance); the network learns that relation from labels
+ * produced by the solver's own runs. */
+/* logits: device [n * 3] (may be NULL); tags: device [n] bjac_prec of the
+ * argmax class, ties to the higher precision (may be NULL). */
+int bjac_mlp_forward(const float *blob, const float *feat, int32_t n, float *logits, uint8_t *tags, void *stream);
+int bjac_mlp_workspace_query(int32_t n, size_t *workspace_bytes);
+/* grad: device [BJAC_MLP_NPARAM], overwritten with the gradient of the mean
+ * softmax cross-entropy over the n samples (labels: device int32 classes);
+ * loss: device scalar or NULL. Deterministic for a given n. */
+int bjac_mlp_backward(const float *blob, const float *feat, const int32_t *labels, int32_t n, float *grad,
+                      float *loss, void *workspace, size_t workspace_bytes, void *stream);
+/* One Adam step on the parameter part of blob (m, v: device moment buffers
+ * [BJAC_MLP_NPARAM]; t >= 1 the step number for bias correction). */
+int bjac_mlp_adam(float *blob, const float *grad, float *m, float *v, int32_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPBJAC_H */

@@ -26,12 +26,11 @@ FEATURE_NAMES = (
     "size_over_64", "log10_min_dom", "log10_mean_dom", "log10_min_dom_inblock",
     "offin_over_diag_fro", "offout_over_diag_fro", "max_log10_tau", "mean_log10_tau",
     "log10_coef_contrast", "gersh_lo_over_maxdiag", "gersh_hi_over_maxdiag",
-    "log10_gersh_cond", "log10_diag_ratio", "log10_kappa1", "log10_inv_range",
+    "log10_gersh_cond", "log10_diag_ratio", "log10_kappa1", "log10_inv_diag_ratio",
     "frac_inv_below_2m24",
 )
 DOM_CAP = 1e8          # dominance ratios are capped at 1e8 (no off-diagonals)
 GERSH_FLOOR = 1e-16    # Gershgorin condition estimate capped at 1e16
-RANGE_CAP = 300.0      # log10 dynamic range of H capped at 300
 
 
 class NotSPD(ValueError):
@@ -190,8 +189,7 @@ def block_features(A, block_ptr, H):
         normH1 = np.max(np.sum(aH, axis=0))
         normA1 = gu            # ||A_ii||_1 = max row sum of |A_ii| for symmetric A_ii with d > 0
         hmax = np.max(aH)
-        hnz = aH[aH > 0]
-        hmin = np.min(hnz) if hnz.size else hmax
+        hdiag = np.diag(Hk)
         F[k, 0] = b / 64.0
         F[k, 1] = np.log10(np.min(dom))
         F[k, 2] = np.log10(np.mean(dom))
@@ -206,7 +204,7 @@ def block_features(A, block_ptr, H):
         F[k, 11] = np.log10(gu / max(gl, gu * GERSH_FLOOR))
         F[k, 12] = np.log10(dmax / np.min(d))
         F[k, 13] = np.log10(normA1 * normH1)
-        F[k, 14] = min(np.log10(hmax / hmin), RANGE_CAP)
+        F[k, 14] = np.log10(np.max(hdiag) / np.min(hdiag))
         F[k, 15] = np.count_nonzero(aH < np.ldexp(hmax, -24)) / float(b * b)
         raw["kappa1"][k] = normA1 * normH1
         raw["min_dom"][k] = np.min(dom)

@@ -1,0 +1,118 @@
+// Host-side internals of libmpbjac: the handle, the device PCG state and the
+// workspace carving shared by the setup and solver translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mpbjac.h"
+
+namespace mpb {
+
+constexpr int kWaveRows = 64;       // padded rows of one apply wave tile
+constexpr int kSpmvRows = 64;       // rows of one SpMV wave tile
+constexpr int kSpmvNnzCap = 448;    // CSR entries staged in LDS per SpMV wave tile
+constexpr int kMaxGrid = 2048;      // persistent workgroups (multiple of 8)
+
+// Device-resident PCG scalars. Written only by the last workgroup of each
+// kernel (ticket pattern) and by the init kernel.
+struct alignas(64) PcgState {
+  double rho;        // (r, z) of the current direction
+  double pq;         // (p, A p)
+  double alpha, beta;
+  double rr;         // ||r||^2 after the last update
+  double rz;
+  double rnorm0;     // ||r_0|| = ||b||
+  double relres;     // ||r|| / ||r_0|| seen by the next preconditioner application
+  double tol, adp_tol;
+  int32_t iter;      // x updates done; -1 before the first application
+  int32_t maxit;
+  int32_t status;    // 0 running, 1 converged, 2 maxit, -3 breakdown
+  int32_t use_high;  // map for the next application (temporal switch)
+  int32_t temporal;
+  int32_t n_high;    // applications that used the FP64 map
+  uint32_t ticket_a, ticket_b, ticket_c;
+  int32_t pad_;
+  double *relres_hist;
+  uint8_t *high_hist;
+};
+
+enum StateStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREAKDOWN = -3, ST_SYNC_FAIL = -4 };
+
+// One stored precision map: byte offsets (from the workspace base) and scale
+// of every block.
+struct DevMap {
+  const uint8_t *base;
+  const int64_t *off;
+  const double *scale;
+  const uint8_t *tag;
+};
+
+}  // namespace mpb
+
+struct bjac_handle {
+  int64_t n = 0;
+  int32_t nb = 0;
+  int32_t max_block = 0;
+  int32_t ntiles = 0;
+  bjac_policy policy{};
+  hipStream_t stream = nullptr;
+  uint8_t *ws = nullptr;
+  size_t ws_bytes = 0;
+  // device arrays inside the workspace
+  int32_t *blk_row = nullptr;    // [nb+1]
+  int32_t *tile_blk = nullptr;   // [ntiles+1] first block of each wave tile
+  uint8_t *bpad = nullptr;       // [nb] padded block sizes
+  int32_t uniform_b = 0;         // common padded size or 0
+  int32_t uprec_lo = -1;         // common precision of the low map or -1
+  // fast path: every block but the last has exactly uniform_b rows, the map
+  // has one precision and stores block k at off0 + k * uniform_b^2 * bytes
+  bool rows_uniform = false;
+  bool fast_lo = false, fast_hi = false;
+  int64_t lo_off0 = 0, hi_off0 = 0;
+  int64_t *off_lo = nullptr, *off_hi = nullptr;
+  double *scale_lo = nullptr, *scale_hi = nullptr;
+  uint8_t *tag_lo = nullptr, *tag_hi = nullptr;
+  float *feat = nullptr;         // [nb*16]
+  int32_t *flags = nullptr;      // [nb] non-SPD marks
+  // host copies
+  std::vector<int32_t> h_blk_row;
+  std::vector<uint8_t> h_bpad;
+  std::vector<uint8_t> h_tag_lo;
+  std::vector<int64_t> h_off_lo, h_off_hi;
+  std::vector<double> h_scale_lo;
+  int32_t hist[4] = {0, 0, 0, 0};
+  int64_t low_bytes = 0, high_bytes = 0;
+  // cached PCG graph
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uintptr_t> gkey;
+};
+
+namespace mpb {
+
+// Bump allocator over a caller workspace; every piece 256-byte aligned.
+struct Carver {
+  uint8_t *base;
+  size_t used = 0;
+  explicit Carver(void *b) : base((uint8_t *)b) {}
+  template <class T>
+  T *take(size_t count) {
+    used = (used + 255) & ~size_t(255);
+    T *p = base ? (T *)(base + used) : nullptr;
+    used += count * sizeof(T);
+    return p;
+  }
+};
+
+#define MPB_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return BJAC_EHIP;             \
+  } while (0)
+
+// launchers implemented in solve.hip, used by setup and api
+int launch_round(const double *in, void *out, int64_t count, int prec, double scale, hipStream_t s);
+
+}  // namespace mpb

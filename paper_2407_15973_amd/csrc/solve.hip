@@ -1,0 +1,1036 @@
+// PCG hot path: q = A p fused with the p update and (p, q); the x / r update
+// fused with the block-Jacobi application z = M^-1 r and the dots (r, r),
+// (r, z); all scalars on the device, iterations replayed as HIP graphs.
+// arXiv 2407.15973: Sec. 3.2 (PCG with M^-1_bjac), Algorithm 3.1 (fMP
+// application), Algorithms 3.2 / 3.3 (adaptive switch), Sec. 4.2 (stopping
+// test on the relative residual, x0 = 0).
+//
+// Work is split into wave tiles: each wave64 owns up to 64 consecutive rows
+// (the SpMV) or up to 64 padded rows of whole diagonal blocks (the
+// application) and runs every phase of its tile without workgroup barriers.
+// A persistent grid of at most kMaxGrid workgroups walks the tiles; with the
+// grid a multiple of 8 the workgroups the hardware puts on one XCD walk one
+// contiguous eighth of the rows, so the neighbour rows of a CSR row stay in
+// that XCD's L2.
+#include <math.h>
+
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace mpb {
+
+struct WaveIter {
+  int t, step, end;
+  __device__ explicit WaveIter(int T) {
+    const int G = gridDim.x, g = blockIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (G >= 8 && (G & 7) == 0) {
+      const int x = g & 7, j = g >> 3;
+      const int lo = (int)(((int64_t)T * x) >> 3), hi = (int)(((int64_t)T * (x + 1)) >> 3);
+      t = lo + j * 4 + wv;
+      step = (G >> 3) * 4;
+      end = hi;
+    } else {
+      t = g * 4 + wv;
+      step = G * 4;
+      end = T;
+    }
+  }
+};
+
+// Workgroups of a persistent grid for T wave tiles: no more than one resident
+// round of the kernel (occupancy x compute units), at most kMaxGrid, a
+// multiple of 8 when possible.
+static int grid_for_waves(int T, const void *kernel) {
+  static std::unordered_map<const void *, int> cap;
+  auto it = cap.find(kernel);
+  if (it == cap.end()) {
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1 ||
+        cus < 1) {
+      per_cu = 1;
+      cus = 256;
+    }
+    it = cap.emplace(kernel, per_cu * cus).first;
+  }
+  int G = (T + 3) / 4;
+  if (G > it->second) G = it->second;
+  if (G > kMaxGrid) G = kMaxGrid;
+  if (G >= 8) G &= ~7;
+  return G < 1 ? 1 : G;
+}
+
+// LDS written by one lane and read by another lane of the same wave: the
+// hardware keeps a wave's LDS operations in order; this keeps the compiler
+// from moving them across the exchange point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over a 256-thread workgroup; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Cross-workgroup reduction without cache maintenance. Each workgroup
+// publishes its partial with a device-scope atomic store into a slot that
+// holds kEmpty, then takes a ticket with a device-scope atomic add; device-
+// scope atomics are coherent across the XCDs' L2 caches, so no write-back or
+// invalidate fence is needed. The workgroup with the last ticket reads every
+// slot with device-scope atomic loads, waiting for slots whose store is still
+// in flight (every writer issued its store before its ticket, so the wait
+// ends; kSpinCap bounds it regardless), and resets each slot to kEmpty for the
+// next launch. kEmpty is a signalling-NaN pattern that no arithmetic result
+// can take (arithmetic only produces quiet NaNs).
+constexpr uint64_t kEmpty = 0x7FF4D1CE0000BEEFull;
+constexpr int kSpinCap = 1 << 22;
+
+__device__ __forceinline__ void publish(double *slot, double v) {
+  __hip_atomic_store((uint64_t *)slot, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double collect(double *slot, bool &ok) {
+  uint64_t u;
+  int spins = 0;
+  do {
+    u = __hip_atomic_load((uint64_t *)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } while (u == kEmpty && ++spins < kSpinCap);
+  ok = ok && u != kEmpty;
+  __hip_atomic_store((uint64_t *)slot, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)u);
+}
+
+// Returns true in every thread of the workgroup that took the last ticket.
+__device__ __forceinline__ bool last_workgroup(uint32_t *ticket, int *sh_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *sh_flag = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  return *sh_flag != 0;
+}
+
+// Deterministic fixed-order sum of the n published partials (stride `stride`)
+// by the last workgroup; result valid in thread 0. ok_out (thread 0) turns
+// false if a slot never filled.
+__device__ __forceinline__ double sum_partials(double *p, int n, int stride, double *sh, int *ok_out) {
+  double s = 0.0;
+  bool ok = true;
+  for (int i = threadIdx.x; i < n; i += 256) s += collect(p + (int64_t)i * stride, ok);
+  if (!ok) atomicAnd(ok_out, 0);
+  return block_sum(s, sh);
+}
+
+__global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) ((uint64_t *)p)[i] = kEmpty;
+}
+
+// ------------------------------------------------------------------- SpMV
+enum SpmvMode { SPMV_PLAIN = 0, SPMV_PCG = 1 };
+
+struct SpmvArgs {
+  int32_t n, ntiles;
+  const int32_t *rp, *ci;
+  const double *v;
+  const double *z;      // PCG: preconditioned residual; PLAIN: the vector p
+  const double *pold;
+  double *pnew, *q;
+  PcgState *st;
+  double *part;
+};
+
+// Dot product of one CSR row with p_new = z + beta p_old (the p update of PCG
+// folded into the product; PLAIN mode reads p = z). Eight entries at a time
+// with every load in flight before the first multiply: indices past the row
+// end are clamped to its last entry and their values replaced by zero, so
+// there is no branch inside a group. Also returns p_new of the row itself
+// when the row stores its diagonal.
+template <bool PCG, bool STAGED>
+__device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
+                                          const int *__restrict__ cidx, const double *__restrict__ vals, double beta,
+                                          int base, int len, int row, double &prow, bool &found) {
+  constexpr int U = 8;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < len; k0 += U) {
+    int cs[U];
+    double vs[U], g[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int idx = base + min(k0 + k, len - 1);
+      cs[k] = cidx[idx];
+      const double v = vals[idx];
+      vs[k] = (k0 + k < len) ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) g[k] = PCG ? fma(beta, pold[cs[k]], z[cs[k]]) : z[cs[k]];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      acc = fma(vs[k], g[k], acc);
+      if (PCG && cs[k] == row) {
+        prow = g[k];
+        found = true;
+      }
+    }
+  }
+  return acc;
+}
+
+template <bool PCG>
+__global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
+  constexpr int CAP = kSpmvNnzCap;
+  constexpr int NL = CAP / 64;
+  __shared__ double svs[4][CAP];
+  __shared__ int scs[4][CAP];
+  __shared__ double sh[4];
+  __shared__ int flag, ok;
+  const int32_t *__restrict__ rp = a.rp;
+  const int32_t *__restrict__ ci = a.ci;
+  const double *__restrict__ vv_g = a.v;
+  const double *__restrict__ z = a.z;
+  const double *__restrict__ pold = a.pold;
+  if (PCG && a.st->status != ST_RUNNING) return;
+  const double beta = PCG ? a.st->beta : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *sv = svs[wv];
+  int *sc = scs[wv];
+  double dot = 0.0;
+  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+    const int r0 = it.t * 64;
+    const int r1 = min(a.n, r0 + 64);
+    const int row = r0 + lane;
+    const bool has = row < r1;
+    const int rowc = min(row, r1 - 1);
+    const int s = rp[rowc], e = rp[rowc + 1];
+    const int e0 = __builtin_amdgcn_readfirstlane(rp[r0]);
+    const int cnt = __builtin_amdgcn_readfirstlane(rp[r1]) - e0;
+    const int len = has ? e - s : 0;
+    double acc = 0.0, prow = 0.0;
+    bool found = false;
+    if (cnt > 0 && cnt <= CAP) {
+      // coalesced staging of the tile's CSR entries into this wave's LDS
+      double vv[NL];
+      int cc[NL];
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const int i = min(lane + 64 * k, cnt - 1);
+        vv[k] = vv_g[e0 + i];
+        cc[k] = ci[e0 + i];
+      }
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const int i = lane + 64 * k;
+        if (i < cnt) {
+          sv[i] = vv[k];
+          sc[i] = cc[k];
+        }
+      }
+      wave_lds_sync();
+      acc = row_dot<PCG, true>(z, pold, sc, sv, beta, s - e0, len, row, prow, found);
+      wave_lds_sync();
+    } else {
+      acc = row_dot<PCG, false>(z, pold, ci, vv_g, beta, s, len, row, prow, found);
+    }
+    if (has) {
+      a.q[row] = acc;
+      if (PCG) {
+        const double pr = found ? prow : fma(beta, pold[row], z[row]);
+        a.pnew[row] = pr;
+        dot = fma(pr, acc, dot);
+      }
+    }
+  }
+  if (!PCG) return;
+  const double bs = block_sum(dot, sh);
+  if (threadIdx.x == 0) {
+    publish(a.part + blockIdx.x, bs);
+    ok = 1;
+  }
+  if (last_workgroup(&a.st->ticket_a, &flag)) {
+    const double pq = sum_partials(a.part, gridDim.x, 1, sh, &ok);
+    if (threadIdx.x == 0) {
+      PcgState *st = a.st;
+      st->pq = pq;
+      if (!ok) {
+        st->status = ST_SYNC_FAIL;
+      } else if (!(pq > 0.0)) {
+        st->status = ST_BREAKDOWN;
+      } else {
+        st->alpha = st->rho / pq;
+      }
+      __hip_atomic_store(&st->ticket_a, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ------------------------------------------------- block-Jacobi application
+// Launch modes: x/r update fused with the application (PCG), update only
+// (adaptive switch, first half), application of the map the device-side
+// switch chose (second half), standalone application z = M^-1 rin.
+enum ApplyMode { M_FUSED = 0, M_UPD = 1, M_APPDEV = 2, M_APP = 3 };
+
+struct ApplyArgs {
+  int32_t ntiles, nb, n, want_high;
+  const int32_t *tile_blk, *blk_row;
+  const uint8_t *bpad;
+  DevMap map;
+  int64_t off0;  // fast path: block k of the map starts at base + off0 + k * B^2 * bytes
+  double *x, *r, *z;
+  const double *p, *q, *rin;
+  PcgState *st;
+  double *part;
+};
+
+// The fragment one lane holds of one 16-row tile of a stored block, and its
+// contribution to z: lane l owns row l % 16 and the columns congruent to
+// l / 16 mod 4; the four column classes are summed across lanes at the end.
+template <int B, int P>
+struct Frag {
+  static constexpr int K = B / 4;
+  static constexpr int BY = prec_bytes(P);
+  static constexpr int V = 16 / BY;
+  static constexpr int G = (K + V - 1) / V;
+  uint4 h[G];
+
+  __device__ __forceinline__ void load(const uint8_t *blk, int mt, int lane) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int vg = layout_vg(B, V, g);
+      const uint8_t *src = blk + (layout_group_base(B, V, mt, g) + (int64_t)lane * vg) * BY;
+      if (vg * BY == 16) {
+        h[g] = *(const uint4 *)src;
+      } else {
+        const uint2 t = *(const uint2 *)src;
+        h[g] = make_uint4(t.x, t.y, 0u, 0u);
+      }
+    }
+  }
+
+  // sum over this lane's columns, then over the four column classes; the row
+  // total is valid in lanes 0..15
+  __device__ __forceinline__ double dot(const float *r32, const double *r64, int lane) const {
+    const int kq = lane >> 4;
+    if constexpr (P == P64) {
+      double acc = 0.0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        acc = fma(__hiloint2double((int)h[g].y, (int)h[g].x), r64[4 * (2 * g) + kq], acc);
+        acc = fma(__hiloint2double((int)h[g].w, (int)h[g].z), r64[4 * (2 * g + 1) + kq], acc);
+      }
+      acc += __shfl_xor(acc, 16, kWave);
+      acc += __shfl_xor(acc, 32, kWave);
+      return acc;
+    } else {
+      float acc = 0.0f;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int vg = layout_vg(B, V, g);
+        const uint32_t w[4] = {h[g].x, h[g].y, h[g].z, h[g].w};
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          if (e < vg) {
+            float hv;
+            if constexpr (P == P32) hv = __uint_as_float(w[e]);
+            else if constexpr (P == PBF16) hv = (e & 1) ? bf16_hi(w[e >> 1]) : bf16_lo(w[e >> 1]);
+            else hv = (e & 1) ? f16_hi(w[e >> 1]) : f16_lo(w[e >> 1]);
+            acc = fmaf(hv, r32[4 * (g * V + e) + kq], acc);
+          }
+        }
+      }
+      acc += __shfl_xor(acc, 16, kWave);
+      acc += __shfl_xor(acc, 32, kWave);
+      return (double)acc;
+    }
+  }
+};
+
+__device__ __forceinline__ void record_high(PcgState *st, int idx, int hi) {
+  if (st->high_hist && idx >= 0 && idx <= st->maxit) st->high_hist[idx] = (uint8_t)hi;
+}
+
+__device__ __forceinline__ bool temporal_high(const PcgState *st, double relres) {
+  if (st->temporal == BJAC_TEMPORAL_HL) return relres >= st->adp_tol;
+  if (st->temporal == BJAC_TEMPORAL_LH) return !(relres >= st->adp_tol);
+  return false;
+}
+
+// State transition after the r update (rr known): iteration count, relres,
+// convergence, the switch decision for the next application.
+__device__ __forceinline__ void after_update(PcgState *st, double rr) {
+  st->rr = rr;
+  if (st->iter < 0) {
+    st->rnorm0 = sqrt(rr);
+    st->iter = 0;
+    st->relres = INFINITY;
+    if (st->rnorm0 == 0.0) {
+      st->relres = 0.0;
+      st->status = ST_CONVERGED;
+    }
+  } else {
+    st->iter += 1;
+    st->relres = sqrt(rr) / st->rnorm0;
+    if (st->relres_hist) st->relres_hist[st->iter - 1] = st->relres;
+    if (st->relres <= st->tol) st->status = ST_CONVERGED;
+  }
+  st->use_high = temporal_high(st, st->relres) ? 1 : 0;
+}
+
+// State transition after the application (rz known).
+__device__ __forceinline__ void after_apply(PcgState *st, double rz, int used_high) {
+  st->rz = rz;
+  record_high(st, st->iter, used_high);
+  st->n_high += used_high;
+  if (!(rz > 0.0)) {
+    st->status = ST_BREAKDOWN;
+    return;
+  }
+  st->beta = st->iter == 0 ? 0.0 : rz / st->rho;
+  st->rho = rz;
+  if (st->iter >= st->maxit) st->status = ST_MAXIT;
+}
+
+template <int MODE>
+struct ModeTraits {
+  static constexpr bool UPD = MODE == M_FUSED || MODE == M_UPD;
+  static constexpr bool APP = MODE != M_UPD;
+  static constexpr bool PCG = MODE != M_APP;
+};
+
+// Row phase of one lane: x += alpha p and r -= alpha q (update modes) or read r.
+template <int MODE>
+__device__ __forceinline__ double row_update(const ApplyArgs &a, double alpha, bool real, int grow, double &rr) {
+  double rv = 0.0;
+  if (real) {
+    if constexpr (ModeTraits<MODE>::UPD) {
+      const double pv = a.p[grow], qv = a.q[grow], xv = a.x[grow], r0 = a.r[grow];
+      a.x[grow] = fma(alpha, pv, xv);
+      rv = fma(-alpha, qv, r0);
+      a.r[grow] = rv;
+      rr = fma(rv, rv, rr);
+    } else if constexpr (MODE == M_APP) {
+      rv = a.rin[grow];
+    } else {
+      rv = a.r[grow];
+    }
+  }
+  return rv;
+}
+
+// Reductions and the state machine at the end of a PCG launch.
+template <int MODE>
+__device__ __forceinline__ void apply_epilogue(const ApplyArgs &a, double rr, double rz, double *sh, int *flag) {
+  using T = ModeTraits<MODE>;
+  const double brr = T::UPD ? block_sum(rr, sh) : 0.0;
+  const double brz = T::APP ? block_sum(rz, sh) : 0.0;
+  if (threadIdx.x == 0) {
+    if (T::UPD) publish(a.part + 2 * blockIdx.x, brr);
+    if (T::APP) publish(a.part + 2 * blockIdx.x + 1, brz);
+    flag[1] = 1;
+  }
+  uint32_t *ticket = T::UPD ? &a.st->ticket_b : &a.st->ticket_c;
+  if (last_workgroup(ticket, flag)) {
+    const double trr = T::UPD ? sum_partials(a.part, gridDim.x, 2, sh, flag + 1) : 0.0;
+    const double trz = T::APP ? sum_partials(a.part + 1, gridDim.x, 2, sh, flag + 1) : 0.0;
+    if (threadIdx.x == 0) {
+      PcgState *st = a.st;
+      if (!flag[1]) {
+        st->status = ST_SYNC_FAIL;
+      } else {
+        if (T::UPD) after_update(st, trr);
+        if (T::APP && st->status == ST_RUNNING) after_apply(st, trz, MODE == M_APPDEV ? a.want_high : 0);
+      }
+      __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Launches whose map does not match the device-side switch exit at once.
+template <int MODE>
+__device__ __forceinline__ bool apply_skip(const ApplyArgs &a) {
+  if (ModeTraits<MODE>::PCG && a.st->status != ST_RUNNING) return true;
+  if (MODE == M_APPDEV && ((a.st->use_high != 0) != (a.want_high != 0))) return true;
+  return false;
+}
+
+// Fast path: every block but the last has B rows, the map stores every block
+// in P, block k at a fixed stride. Rows, block addresses and the tile shape are
+// arithmetic, so the stored fragments, the per-block scales and the vectors of
+// a tile are all requested before the first wait.
+template <int B, int P, int MODE>
+__global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
+  using T = ModeTraits<MODE>;
+  constexpr int NB = 64 / B;        // blocks per wave tile
+  constexpr int R = NB * B;         // padded rows per wave tile
+  constexpr int MT = R / 16;        // 16-row tiles per wave tile
+  constexpr int MPB = B / 16;       // 16-row tiles per block
+  using F = Frag<B, P>;
+  constexpr int64_t BLK = (int64_t)B * B * prec_bytes(P);
+  constexpr bool PRE = MT * F::G <= 8;
+  __shared__ float r32s[4][64];
+  __shared__ double r64s[4][64];
+  __shared__ double zts[4][64];
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (apply_skip<MODE>(a)) return;
+  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const uint8_t *__restrict__ base = a.map.base + a.off0;
+  const double *__restrict__ scale = a.map.scale;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float *r32 = r32s[wv];
+  double *r64 = r64s[wv];
+  double *zt = zts[wv];
+  const int j = lane / B, li = lane - j * B;
+  double rr = 0.0, rz = 0.0;
+  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+    const int k0 = it.t * NB;
+    const int kb = k0 + j;
+    const int grow = kb * B + li;
+    const bool real = lane < R && kb < a.nb && grow < a.n;
+    F fr[PRE ? MT : 1];
+    double scl = 1.0;
+    if constexpr (T::APP) {
+      if constexpr (P != P64) scl = scale[min(k0 + lane % NB, a.nb - 1)];
+      if constexpr (PRE) {
+#pragma unroll
+        for (int u = 0; u < MT; ++u) fr[u].load(base + (int64_t)min(k0 + u / MPB, a.nb - 1) * BLK, u % MPB, lane);
+      }
+    }
+    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    if constexpr (T::APP) {
+      if (lane < R) {
+        r64[lane] = rv;
+        r32[lane] = __double2float_rn(rv);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < MT; ++u) {
+        const int jb = u / MPB;
+        if (k0 + jb < a.nb) {
+          const int cb = jb * B;
+          double zv;
+          if constexpr (PRE) {
+            zv = fr[u].dot(r32 + cb, r64 + cb, lane);
+          } else {
+            F f;
+            f.load(base + (int64_t)(k0 + jb) * BLK, u % MPB, lane);
+            zv = f.dot(r32 + cb, r64 + cb, lane);
+          }
+          const double sc = (P == P64) ? 1.0 : bcast(scl, jb);
+          if (lane < 16) zt[cb + (u % MPB) * 16 + lane] = zv * sc;
+        }
+      }
+      wave_lds_sync();
+      if (real) {
+        const double zv = zt[lane];
+        a.z[grow] = zv;
+        rz = fma(rv, zv, rz);
+      }
+    }
+  }
+  if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
+}
+
+template <int B>
+__device__ __forceinline__ double mtile_dot(int prec, const uint8_t *blk, int mt, const float *r32, const double *r64,
+                                            int lane) {
+  switch (prec) {
+    case P64: { Frag<B, P64> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
+    case P32: { Frag<B, P32> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
+    case PBF16: { Frag<B, PBF16> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
+    default: { Frag<B, P16> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
+  }
+}
+
+__device__ __forceinline__ int readlane_i(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ int64_t readlane_l(int64_t v, int src) {
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), src);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Generic path: blocks of different sizes and/or precisions. Each wave tile
+// (up to 4 blocks, at most 64 padded rows, from the setup's tile list) reads
+// its blocks' metadata with one lane-parallel load per array and broadcasts it;
+// each 16-row tile dispatches on its block's size and precision.
+template <int MODE>
+__global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
+  using T = ModeTraits<MODE>;
+  __shared__ float r32s[4][64];
+  __shared__ double r64s[4][64];
+  __shared__ double zts[4][64];
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (apply_skip<MODE>(a)) return;
+  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  float *r32 = r32s[wv];
+  double *r64 = r64s[wv];
+  double *zt = zts[wv];
+  double rr = 0.0, rz = 0.0;
+  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+    const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
+    const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
+    const int kl = k0 + min(lane, nk - 1);
+    const int mB = a.bpad[kl], mrow = a.blk_row[kl], mrow1 = a.blk_row[kl + 1];
+    int64_t moff = 0;
+    double msc = 1.0;
+    int mtag = 0;
+    if constexpr (T::APP) {
+      moff = a.map.off[kl];
+      msc = a.map.scale[kl];
+      mtag = a.map.tag[kl];
+    }
+    int cum = 0, row0 = 0, bsz = 0, li = -1;
+    for (int i = 0; i < nk; ++i) {
+      const int Bi = readlane_i(mB, i);
+      if (lane >= cum && lane < cum + Bi) {
+        li = lane - cum;
+        row0 = readlane_i(mrow, i);
+        bsz = readlane_i(mrow1, i) - row0;
+      }
+      cum += Bi;
+    }
+    const bool real = li >= 0 && li < bsz;
+    const int grow = row0 + li;
+    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    if constexpr (T::APP) {
+      if (lane < cum) {
+        r64[lane] = rv;
+        r32[lane] = __double2float_rn(rv);
+      }
+      wave_lds_sync();
+      int cb = 0;
+      for (int i = 0; i < nk; ++i) {
+        const int B = readlane_i(mB, i);
+        const int prec = readlane_i(mtag, i);
+        const uint8_t *blk = a.map.base + readlane_l(moff, i);
+        const double sc = bcast(msc, i);
+        for (int mt = 0; mt < B / 16; ++mt) {
+          double zv;
+          switch (B) {
+            case 16: zv = mtile_dot<16>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            case 32: zv = mtile_dot<32>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            case 48: zv = mtile_dot<48>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            default: zv = mtile_dot<64>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+          }
+          if (lane < 16) zt[cb + mt * 16 + lane] = zv * sc;
+        }
+        cb += B;
+      }
+      wave_lds_sync();
+      if (real) {
+        const double zv = zt[lane];
+        a.z[grow] = zv;
+        rz = fma(rv, zv, rz);
+      }
+    }
+  }
+  if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void state_init_kernel(PcgState *st, double tol, int maxit, double adp_tol, int temporal,
+                                  double *relres_hist, uint8_t *high_hist) {
+  PcgState s{};
+  s.tol = tol;
+  s.maxit = maxit;
+  s.adp_tol = adp_tol;
+  s.temporal = temporal;
+  s.iter = -1;
+  s.status = ST_RUNNING;
+  s.alpha = 0.0;
+  s.relres = INFINITY;
+  s.relres_hist = relres_hist;
+  s.high_hist = high_hist;
+  // the first application sees relres = +inf: hl starts high, lh starts low
+  s.use_high = temporal == BJAC_TEMPORAL_HL ? 1 : 0;
+  *st = s;
+}
+
+__global__ __launch_bounds__(256) void pcg_fill_kernel(int64_t n, double *x, double *r, const double *b, double *p,
+                                                       double *q) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] = 0.0;
+    r[i] = b[i];
+    p[i] = 0.0;
+    q[i] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void round_kernel(const double *in, uint8_t *out, int64_t count, int prec,
+                                                    double inv_scale) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+    const double v = in[i] * inv_scale;
+    if (prec == P32) ((uint32_t *)out)[i] = to_f32_bits(v);
+    else if (prec == PBF16) ((uint16_t *)out)[i] = (uint16_t)to_bf16_bits(v);
+    else ((uint16_t *)out)[i] = (uint16_t)to_f16_bits(v);
+  }
+}
+
+int launch_round(const double *in, void *out, int64_t count, int prec, double scale, hipStream_t s) {
+  if (count <= 0) return BJAC_OK;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(round_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, (uint8_t *)out, count, prec,
+                     1.0 / scale);
+  MPB_HIP(hipGetLastError());
+  return BJAC_OK;
+}
+
+// ---------------------------------------------------------------- launchers
+static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
+                        PcgState *st, double *part, int mode, hipStream_t s) {
+  SpmvArgs a{};
+  a.n = (int32_t)A->n;
+  a.ntiles = (int)((A->n + kSpmvRows - 1) / kSpmvRows);
+  a.rp = A->row_ptr;
+  a.ci = A->col_idx;
+  a.v = A->val;
+  a.z = z;
+  a.pold = pold;
+  a.pnew = pnew;
+  a.q = q;
+  a.st = st;
+  a.part = part;
+  if (mode == SPMV_PCG) {
+    const void *k = (const void *)spmv_kernel<true>;
+    hipLaunchKernelGGL(spmv_kernel<true>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+  } else {
+    const void *k = (const void *)spmv_kernel<false>;
+    hipLaunchKernelGGL(spmv_kernel<false>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+  }
+}
+
+struct MapSel {
+  DevMap map;
+  int prec;      // common precision, -1 if mixed
+  bool fast;
+  int64_t off0;
+};
+
+static MapSel sel_lo(const bjac_handle *h) {
+  return MapSel{DevMap{h->ws, h->off_lo, h->scale_lo, h->tag_lo}, h->uprec_lo, h->fast_lo, h->lo_off0};
+}
+static MapSel sel_hi(const bjac_handle *h) {
+  if (!h->off_hi) return sel_lo(h);
+  return MapSel{DevMap{h->ws, h->off_hi, h->scale_hi, h->tag_hi}, (int)P64, h->fast_hi, h->hi_off0};
+}
+
+template <class K>
+static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a) {
+  hipLaunchKernelGGL(kernel, dim3(grid_for_waves(a.ntiles, (const void *)kernel)), dim3(256), 0, s, a);
+}
+
+template <int B, int MODE>
+static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
+  switch (prec) {
+    case P64: launch_persistent(apply_fast_kernel<B, P64, MODE>, s, a); break;
+    case P32: launch_persistent(apply_fast_kernel<B, P32, MODE>, s, a); break;
+    case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE>, s, a); break;
+    default: launch_persistent(apply_fast_kernel<B, P16, MODE>, s, a); break;
+  }
+}
+
+template <int MODE>
+static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, const ApplyArgs &a) {
+  // the update-only mode reads no map: any fast instance serves
+  const bool fast = MODE == M_UPD ? h->rows_uniform : m.fast;
+  const int prec = MODE == M_UPD ? (int)P16 : m.prec;
+  if (fast && h->uniform_b) {
+    switch (h->uniform_b) {
+      case 16: launch_fast_bm<16, MODE>(prec, s, a); break;
+      case 32: launch_fast_bm<32, MODE>(prec, s, a); break;
+      case 48: launch_fast_bm<48, MODE>(prec, s, a); break;
+      default: launch_fast_bm<64, MODE>(prec, s, a); break;
+    }
+  } else {
+    launch_persistent(apply_generic_kernel<MODE>, s, a);
+  }
+}
+
+// One launch of the application kernel in the given mode and map.
+static void launch_apply(const bjac_handle *h, int mode, int want_high, const MapSel &m, double *x, double *r,
+                         double *z, const double *p, const double *q, const double *rin, PcgState *st, double *part,
+                         hipStream_t s) {
+  ApplyArgs a{};
+  a.ntiles = h->ntiles;
+  a.nb = h->nb;
+  a.n = (int32_t)h->n;
+  a.want_high = want_high;
+  a.tile_blk = h->tile_blk;
+  a.blk_row = h->blk_row;
+  a.bpad = h->bpad;
+  a.map = m.map;
+  a.off0 = m.off0;
+  a.x = x;
+  a.r = r;
+  a.z = z;
+  a.p = p;
+  a.q = q;
+  a.rin = rin;
+  a.st = st;
+  a.part = part;
+  switch (mode) {
+    case M_FUSED: launch_mode<M_FUSED>(h, m, s, a); break;
+    case M_UPD: launch_mode<M_UPD>(h, m, s, a); break;
+    case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a); break;
+    default: launch_mode<M_APP>(h, m, s, a); break;
+  }
+}
+
+struct SolveWs {
+  double *r, *z, *pa, *pb, *q, *part1, *part2;
+  PcgState *st;
+  size_t bytes;
+};
+
+static SolveWs carve_solve(void *ws, int64_t n) {
+  Carver c(ws);
+  SolveWs w{};
+  w.r = c.take<double>(n);
+  w.z = c.take<double>(n);
+  w.pa = c.take<double>(n);
+  w.pb = c.take<double>(n);
+  w.q = c.take<double>(n);
+  w.part1 = c.take<double>(3 * kMaxGrid);  // spmv slots, then update/apply slot pairs
+  w.part2 = w.part1 + kMaxGrid;
+  w.st = c.take<PcgState>(1);
+  w.bytes = c.used;
+  return w;
+}
+
+static hipStream_t capture_stream() {
+  static hipStream_t s = nullptr;
+  if (!s) {
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  }
+  return s;
+}
+
+// The x / r update and the application: fused, or (adaptive switch) an update
+// launch that decides the map and one application launch per map, of which
+// only the chosen one does work. Events bracket the launches when given.
+static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs &w, bool temporal, const double *p,
+                                 hipStream_t s, hipEvent_t *ev) {
+  if (temporal) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    launch_apply(M, M_UPD, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    launch_apply(M, M_APPDEV, 1, sel_hi(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    launch_apply(M, M_APPDEV, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    if (ev) (void)hipEventRecord(ev[2], s);
+  } else {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    launch_apply(M, M_FUSED, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    if (ev) (void)hipEventRecord(ev[1], s);
+  }
+}
+
+// One PCG iteration: q = A p (p updated on the fly), then update + apply.
+static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
+                              const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev) {
+  if (ev) (void)hipEventRecord(ev[0], s);
+  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s);
+  enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr);
+}
+
+// Profile mode: the same kernels launched one by one, bracketed by HIP events
+// on the caller's stream. Only iterations that ran to their end are counted.
+struct Prof {
+  double t[3] = {0.0, 0.0, 0.0};  // spmv, apply (fused or split), update (split)
+  int n[3] = {0, 0, 0};
+};
+
+static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
+                        int chunk, int max_launches, hipStream_t s, PcgState &hs, int &launches, Prof &prof) {
+  constexpr int EV = 4;  // events per iteration: spmv start, update/apply start, split point, end
+  std::vector<hipEvent_t> ev((size_t)EV * chunk);
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return BJAC_EHIP;
+  int rc = BJAC_OK;
+  while (hs.status == ST_RUNNING && launches < max_launches) {
+    const int it0 = hs.iter;
+    for (int i = 0; i < chunk; ++i) {
+      const bool even = (i & 1) == 0;
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, ev.data() + EV * i);
+    }
+    ++launches;
+    if (hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = BJAC_EHIP;
+      break;
+    }
+    const int done = hs.iter - it0;
+    for (int i = 0; i < done && i < chunk; ++i) {
+      hipEvent_t *e = ev.data() + EV * i;
+      float a = 0.f, b = 0.f, c = 0.f;
+      (void)hipEventElapsedTime(&a, e[0], e[1]);
+      (void)hipEventElapsedTime(&b, e[1], e[2]);
+      prof.t[0] += a;
+      prof.n[0] += 1;
+      if (temporal) {
+        (void)hipEventElapsedTime(&c, e[2], e[3]);
+        prof.t[2] += b;
+        prof.n[2] += 1;
+        prof.t[1] += c;
+        prof.n[1] += 1;
+      } else {
+        prof.t[1] += b;
+        prof.n[1] += 1;
+      }
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+}  // namespace mpb
+
+using namespace mpb;
+
+extern "C" int bjac_apply(const bjac_handle *h, int32_t which, const double *r, double *z, void *stream) {
+  if (!h || !r || !z || r == z || (which != 0 && which != 1)) return BJAC_EINVAL;
+  launch_apply(h, M_APP, 0, which == 1 ? sel_hi(h) : sel_lo(h), nullptr, nullptr, z, nullptr, nullptr, r, nullptr,
+               nullptr, (hipStream_t)stream);
+  MPB_HIP(hipGetLastError());
+  return BJAC_OK;
+}
+
+extern "C" int bjac_spmv(const bjac_csr *A, const double *p, double *q, void *stream) {
+  if (!A || !p || !q || p == q || A->n < 1 || A->n >= (int64_t)1 << 31 || !A->row_ptr || !A->col_idx || !A->val)
+    return BJAC_EINVAL;
+  launch_spmv(A, p, nullptr, nullptr, q, nullptr, nullptr, SPMV_PLAIN, (hipStream_t)stream);
+  MPB_HIP(hipGetLastError());
+  return BJAC_OK;
+}
+
+extern "C" int bjac_round(const double *in, void *out, int64_t count, int32_t prec, double scale, void *stream) {
+  if (count < 0 || (count > 0 && (!in || !out)) || prec < BJAC_FP32 || prec > BJAC_FP16) return BJAC_EINVAL;
+  int e;
+  if (!(scale > 0) || std::frexp(scale, &e) != 0.5) return BJAC_EINVAL;
+  return launch_round(in, out, count, prec, scale, (hipStream_t)stream);
+}
+
+extern "C" int pcg_workspace_query(int64_t n, size_t *workspace_bytes) {
+  if (n < 1 || !workspace_bytes) return BJAC_EINVAL;
+  *workspace_bytes = carve_solve(nullptr, n).bytes;
+  return BJAC_OK;
+}
+
+extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double *b, double *x,
+                         const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes, bjac_stats *stats,
+                         void *stream) {
+  if (!A || !Mc || !b || !x || !opts || !workspace || b == x) return BJAC_EINVAL;
+  if (A->n != Mc->n || !A->row_ptr || !A->col_idx || !A->val) return BJAC_EINVAL;
+  if (!(opts->tol >= 0.0) || opts->maxit < 1) return BJAC_EINVAL;
+  bjac_handle *M = const_cast<bjac_handle *>(Mc);
+  const SolveWs w = carve_solve(workspace, A->n);
+  if (w.bytes > workspace_bytes) return BJAC_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
+  int chunk = opts->chunk > 0 ? opts->chunk : 16;
+  chunk += chunk & 1;  // even: the p buffers return to their roles
+
+  hipEvent_t e0, e1;
+  MPB_HIP(hipEventCreate(&e0));
+  MPB_HIP(hipEventCreate(&e1));
+  MPB_HIP(hipEventRecord(e0, s));
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
+                     M->policy.temporal, opts->relres_hist, opts->high_hist);
+  hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q);
+  hipLaunchKernelGGL(fill_empty_kernel, dim3(24), dim3(256), 0, s, w.part1, 3 * kMaxGrid);
+  // first application z_0 = M^-1 r_0 (alpha = 0 leaves x = 0, r = b)
+  enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
+  MPB_HIP(hipGetLastError());
+
+  // captured chunk of iterations, cached in the handle per argument set
+  std::vector<uintptr_t> key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val,
+                                (uintptr_t)A->n, (uintptr_t)x, (uintptr_t)workspace, (uintptr_t)chunk};
+  if (!opts->profile && (!M->gexec || M->gkey != key)) {
+    if (M->gexec) {
+      (void)hipGraphExecDestroy(M->gexec);
+      M->gexec = nullptr;
+    }
+    hipStream_t cs = capture_stream();
+    if (!cs) return BJAC_EHIP;
+    MPB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+    for (int i = 0; i < chunk; ++i) {
+      const bool even = (i & 1) == 0;
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, cs, nullptr);
+    }
+    hipGraph_t g = nullptr;
+    MPB_HIP(hipStreamEndCapture(cs, &g));
+    hipError_t ie = hipGraphInstantiate(&M->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      M->gexec = nullptr;
+      return BJAC_EHIP;
+    }
+    M->gkey = key;
+  }
+
+  PcgState hs{};
+  int launches = 0;
+  const int max_launches = opts->maxit / chunk + 2;
+  MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipStreamSynchronize(s));
+  Prof prof;
+  if (opts->profile) {
+    int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof);
+    if (rc) return rc;
+  } else {
+    while (hs.status == ST_RUNNING && launches < max_launches) {
+      MPB_HIP(hipGraphLaunch(M->gexec, s));
+      ++launches;
+      MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+      MPB_HIP(hipStreamSynchronize(s));
+    }
+  }
+  MPB_HIP(hipEventRecord(e1, s));
+  MPB_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int rc;
+  switch (hs.status) {
+    case ST_CONVERGED: rc = BJAC_OK; break;
+    case ST_BREAKDOWN: rc = BJAC_EBREAKDOWN; break;
+    case ST_SYNC_FAIL: rc = BJAC_EHIP; break;
+    default: rc = BJAC_NOT_CONVERGED; break;
+  }
+  if (stats) {
+    stats->iters = hs.iter < 0 ? 0 : hs.iter;
+    stats->status = rc;
+    stats->relres = hs.iter <= 0 ? (hs.status == ST_CONVERGED ? 0.0 : 1.0) : hs.relres;
+    stats->rnorm0 = hs.rnorm0;
+    stats->high_applications = hs.n_high;
+    stats->graph_launches = launches;
+    stats->solve_ms = ms;
+    stats->spmv_ms = prof.t[0];
+    stats->apply_ms = prof.t[1];
+    stats->update_ms = prof.t[2];
+    stats->n_spmv = prof.n[0];
+    stats->n_apply = prof.n[1];
+    stats->n_update = prof.n[2];
+    stats->reserved = 0;
+  }
+  return rc;
+}

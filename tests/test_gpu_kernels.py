@@ -1,0 +1,252 @@
+"""GPU parity of the hot-path kernels against the CPU oracle: correctly rounded
+storage conversion (bit-exact), CSR SpMV, block extraction + FP64 inversion +
+scaled low-precision packing, block features and the per-block rule, and the
+block-Jacobi application z = M^-1 r. All calls go through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import blocks as OB
+from oracle import precision as OPr
+from paper_2407_15973_amd import binding as mb
+from paper_2407_15973_amd import gen
+
+from gpu_helpers import dev, gamma, oracle_setup, tensor, ulp
+
+pytestmark = pytest.mark.gpu
+
+
+def _edge_values(rng, n=30000):
+    mags = np.ldexp(1.0, rng.integers(-160, 130, size=n)) * rng.uniform(1, 2, size=n)
+    m = rng.integers(1, 2 ** 10, size=3000)
+    ties16 = np.ldexp(2 * m + 1.0, rng.integers(-40, 5, size=3000) - 11)
+    m8 = rng.integers(1, 2 ** 7, size=3000)
+    ties8 = np.ldexp(2 * m8 + 1.0, rng.integers(-140, 100, size=3000) - 8)
+    m32 = rng.integers(1, 2 ** 23, size=3000)
+    ties32 = np.ldexp(2 * m32 + 1.0, rng.integers(-170, 100, size=3000) - 24)
+    special = np.array([0.0, -0.0, 65504.0, 65519.99, 65520.0, 65536.0, 2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26,
+                        2.0 ** -14, 2.0 ** -149, 2.0 ** -150, 3 * 2.0 ** -151, 1e-300, 1e300, np.inf, -np.inf,
+                        float.fromhex("0x1.fep127"), float.fromhex("0x1.ff8p127"), 2.0 ** -133, 2.0 ** -134])
+    v = np.concatenate([mags, ties16, ties8, ties32, special])
+    return np.concatenate([v, -v])
+
+
+def _bits_to_f64(bits, prec):
+    if prec == OPr.FP32:
+        return bits.astype(np.int32).view(np.float32).astype(np.float64)
+    if prec == OPr.FP16:
+        return bits.astype(np.int16).view(np.float16).astype(np.float64)
+    u = (bits.astype(np.int32).astype(np.int64) & 0xFFFF).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", [OPr.FP32, OPr.BF16, OPr.FP16])
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** -20, 2.0 ** 7])
+def test_round_bit_exact(prec, scale):
+    x = _edge_values(np.random.default_rng(prec))
+    with np.errstate(over="ignore"):
+        ref = OPr.round_to_format(x / scale, prec)
+    got = _bits_to_f64(mb.round_bits(tensor(x), prec, scale).cpu().numpy(), prec)
+    np.testing.assert_array_equal(got, ref)
+    assert np.array_equal(np.signbit(got), np.signbit(ref))
+
+
+def test_round_rejects_bad_scale():
+    with pytest.raises(mb.MpbjacError):
+        mb.round_bits(tensor(np.ones(4)), OPr.FP16, 3.0)
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 9), (20, 17, 13)])
+def test_spmv_matches_fp64_product(shape):
+    rng = np.random.default_rng(1)
+    A = gen.diffusion3d(gen.kappa_loguniform(shape, rng))
+    p = rng.uniform(-1, 1, A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    q = mb.spmv(Ad, tensor(p)).cpu().numpy()
+    S = A.to_scipy()
+    ref = S @ p
+    bound = gamma(8, 2.0 ** -53) * (abs(S) @ np.abs(p))
+    assert np.all(np.abs(q - ref) <= bound + 1e-300)
+
+
+def test_spmv_long_rows_unstaged_path():
+    # rows with many entries overflow the LDS staging of a tile
+    rng = np.random.default_rng(2)
+    n = 600
+    D = rng.standard_normal((n, n)) * (rng.uniform(size=(n, n)) < 0.3)
+    r, c = np.nonzero(D)
+    A = gen._csr_from_coo(n, r, c, D[r, c])
+    p = rng.uniform(-1, 1, n)
+    q = mb.spmv(mb.DeviceCSR(A, dev()), tensor(p)).cpu().numpy()
+    np.testing.assert_allclose(q, D @ p, rtol=0, atol=gamma(n, 2 ** -53) * (np.abs(D) @ np.abs(p)).max())
+
+
+def _check_blocks_exact(A, bp, prec):
+    nb = len(bp) - 1
+    M = mb.BlockJacobi(mb.DeviceCSR(A, dev()), bp, mb.Policy(mode=mb.FIXED, low=prec))
+    tags = np.full(nb, prec, np.uint8)
+    H, store = oracle_setup(A, bp, tags)
+    for k in range(nb):
+        got, s = M.block(k)
+        Hh, s_ref, _ = store[k]
+        assert s == s_ref
+        np.testing.assert_array_equal(got, Hh)
+    return M, H, store
+
+
+@pytest.mark.parametrize("prec", [OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16])
+@pytest.mark.parametrize("b", [16, 32, 48, 64])
+def test_exact_inverse_family_packs_bit_exact(prec, b):
+    # blocks L L^T with integer inverses: both eliminations are exact, so the
+    # stored values must equal the oracle's rounding bit for bit
+    A = gen.spd_exact_inverse_blocks(5, b, np.random.default_rng(b))
+    _check_blocks_exact(A, gen.uniform_blocks(A.n, b), prec)
+
+
+def _diffusion_case(seed=3, shape=(12, 10, 9), sizes=None, b=32):
+    rng = np.random.default_rng(seed)
+    A = gen.diffusion3d(gen.kappa_loguniform(shape, rng))
+    bp = gen.random_blocks(A.n, rng, sizes) if sizes else gen.uniform_blocks(A.n, b)
+    return A, bp, rng
+
+
+@pytest.mark.parametrize("b,sizes", [(32, None), (48, None), (64, None), (0, (16, 32, 48, 64)), (0, (5, 13, 40))])
+def test_inverse_and_packing_general(b, sizes):
+    A, bp, _ = _diffusion_case(b=b, sizes=sizes)
+    nb = len(bp) - 1
+    Ad = mb.DeviceCSR(A, dev())
+    H = OB.invert_blocks(A, bp)
+    M64 = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.UNIFORM))
+    for k in range(nb):
+        got, s = M64.block(k)
+        kap = np.linalg.cond(H[k], 1)
+        bk = H[k].shape[0]
+        assert s == 1.0
+        np.testing.assert_allclose(got, H[k], rtol=0, atol=4 * bk * kap * 2.0 ** -53 * np.abs(H[k]).max())
+    for prec in (OPr.FP32, OPr.BF16, OPr.FP16):
+        M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=prec))
+        store = OB.store_blocks(H, np.full(nb, prec, np.uint8))
+        for k in range(nb):
+            got, s = M.block(k)
+            Hh, s_ref, _ = store[k]
+            assert s == s_ref
+            # identical except where the two FP64 inverses straddle a rounding
+            # boundary: then the stored values are adjacent (one ulp apart)
+            d = np.abs(got - Hh)
+            assert np.all(d <= ulp(Hh, prec) * 1.0000001), (prec, k)
+            assert np.count_nonzero(d) <= max(2, d.size // 50)
+
+
+def test_features_and_rule_tags_match_oracle():
+    rng = np.random.default_rng(4)
+    N = 14
+    kap = gen.kappa_subcube_jumps(N, rng, ncubes=4)
+    A = gen.diffusion3d(kap * gen.kappa_loguniform((N, N, N), rng, -1, 1), aniso=(1, 30, 30))
+    bp = gen.random_blocks(A.n, rng)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.RULE, theta=1e-2, d16=1.0))
+    H = OB.invert_blocks(A, bp)
+    F, raw = OB.block_features(A, bp, H)
+    Fg = M.features().astype(np.float64)
+    # features from A alone: rounding only; features from H: the inverses agree to kappa*u
+    fa = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12]
+    np.testing.assert_allclose(Fg[:, fa], F[:, fa].astype(np.float32), rtol=2e-6, atol=1e-6)
+    assert np.all(np.abs(Fg[:, 13] - F[:, 13]) <= 1e-6 + 1e-12 * 10 ** F[:, 13])
+    np.testing.assert_allclose(Fg[:, 14], F[:, 14], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(Fg[:, 15], F[:, 15], rtol=0, atol=2.0 / 64)
+    tags = M.tags()
+    ref = OB.select_rule(raw, theta=1e-2, d16=1.0)
+    # a tag may differ only where kappa_1 * u sits on the threshold within rounding
+    amb = np.zeros(len(ref), bool)
+    for u in (2.0 ** -11, 2.0 ** -24):
+        amb |= np.abs(raw["kappa1"] * u / 1e-2 - 1) < 1e-9
+    assert np.array_equal(tags[~amb], ref[~amb])
+    info = M.info()
+    assert sum(info["blocks_per_prec"]) == len(ref)
+    assert len(set(tags.tolist())) >= 2     # the case mixes precisions
+
+
+def test_not_spd_block_is_reported():
+    A = gen.poisson2d(8, 8)
+    rp, ci = A.row_ptr, A.col_idx
+    i = 19
+    A.val[rp[i]:rp[i + 1]][ci[rp[i]:rp[i + 1]] == i] = -4.0
+    with pytest.raises(mb.MpbjacError) as e:
+        mb.BlockJacobi(mb.DeviceCSR(A, dev()), gen.uniform_blocks(A.n, 16), mb.Policy())
+    assert e.value.code == mb.ENOTSPD
+
+
+def test_bad_partitions_rejected():
+    A = gen.poisson2d(8, 8)
+    Ad = mb.DeviceCSR(A, dev())
+    for bp in ([0, 65, 64], [0, 64, 64], [0, 32, 63], [1, 64]):
+        with pytest.raises(mb.MpbjacError) as e:
+            mb.BlockJacobi(Ad, np.array(bp), mb.Policy())
+        assert e.value.code == mb.EINVAL
+    with pytest.raises(mb.MpbjacError):
+        mb.BlockJacobi(Ad, np.array([0, 64]), mb.Policy(mode=mb.FIXED, low=7))
+
+
+def _apply_bound(store, bp, r, H):
+    # |z_gpu - z_oracle| <= s gamma_b (|Hhat| |r_in|) for the FP32 accumulation,
+    # plus |stored difference| |r_in| where the inverses straddle a rounding
+    z_abs = OB.apply_abs(store, bp, r)
+    bmax = int(np.max(np.diff(bp)))
+    return gamma(bmax, 2.0 ** -24) * z_abs
+
+
+@pytest.mark.parametrize("prec", [OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16])
+def test_apply_exact_family_within_accumulation_bound(prec):
+    rng = np.random.default_rng(7)
+    A = gen.spd_exact_inverse_blocks(40, 48, rng)
+    bp = gen.uniform_blocks(A.n, 48)
+    tags = np.full(len(bp) - 1, prec, np.uint8)
+    H, store = oracle_setup(A, bp, tags)
+    M = mb.BlockJacobi(mb.DeviceCSR(A, dev()), bp, mb.Policy(mode=mb.FIXED, low=prec))
+    for trial in range(3):
+        r = rng.uniform(-1, 1, A.n) * np.exp(rng.uniform(-30, 0, A.n))
+        z = M.apply(tensor(r)).cpu().numpy()
+        ref = OB.apply(store, bp, r)
+        u = 2.0 ** -53 if prec == OPr.FP64 else 2.0 ** -24
+        bound = gamma(48, u) * OB.apply_abs(store, bp, r)
+        assert np.all(np.abs(z - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("sizes", [None, (16, 32, 48, 64), (7, 33, 64)])
+def test_apply_general_mixed_map(sizes):
+    A, bp, rng = _diffusion_case(seed=5, shape=(16, 12, 10), sizes=sizes, b=32)
+    nb = len(bp) - 1
+    tags = rng.choice([OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16], size=nb).astype(np.uint8)
+    M = mb.BlockJacobi(mb.DeviceCSR(A, dev()), bp, mb.Policy(mode=mb.EXPLICIT, explicit_tags=tags))
+    assert np.array_equal(M.tags(), tags)
+    H, store = oracle_setup(A, bp, tags)
+    r = rng.uniform(-1, 1, A.n)
+    z = M.apply(tensor(r)).cpu().numpy()
+    ref = OB.apply(store, bp, r)
+    # stored values may differ by one ulp where the FP64 inverses straddle a
+    # rounding boundary; bound that together with the accumulation error
+    zb = OB.apply_abs(store, bp, r)
+    ulp_rel = np.array([{0: 2.0 ** -52, 1: 2.0 ** -23, 2: 2.0 ** -7, 3: 2.0 ** -10}[t] for t in tags])
+    per_row = np.repeat(ulp_rel, np.diff(bp))
+    bmax = int(np.max(np.diff(bp)))
+    kap = max(np.linalg.cond(h, 1) for h in H)
+    bound = (gamma(bmax, 2.0 ** -24) + per_row + 8 * bmax * kap * 2.0 ** -53) * zb
+    assert np.all(np.abs(z - ref) <= bound + 1e-300)
+
+
+def test_temporal_handle_stores_both_maps():
+    A, bp, rng = _diffusion_case(seed=6, shape=(10, 10, 10), b=48)
+    M = mb.BlockJacobi(mb.DeviceCSR(A, dev()), bp,
+                       mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=mb.TEMPORAL_HL, adp_tol=1e-3))
+    H, store = oracle_setup(A, bp, np.full(len(bp) - 1, OPr.FP16, np.uint8))
+    r = rng.uniform(-1, 1, A.n)
+    z_lo = M.apply(tensor(r), 0).cpu().numpy()
+    z_hi = M.apply(tensor(r), 1).cpu().numpy()
+    store64 = OB.store_blocks(H, np.zeros(len(bp) - 1, np.uint8))
+    ref_hi = OB.apply(store64, bp, r)
+    kap = max(np.linalg.cond(h, 1) for h in H)
+    assert np.all(np.abs(z_hi - ref_hi) <= (gamma(48, 2.0 ** -53) + 8 * 48 * kap * 2.0 ** -53)
+                  * OB.apply_abs(store64, bp, r) + 1e-300)
+    ref_lo = OB.apply(store, bp, r)
+    assert np.all(np.abs(z_lo - ref_lo) <= (gamma(48, 2.0 ** -24) + 2.0 ** -10) * OB.apply_abs(store, bp, r))
+    info = M.info()
+    assert info["high_bytes"] == (len(bp) - 1) * 48 * 48 * 8 and info["low_bytes"] == (len(bp) - 1) * 48 * 48 * 2

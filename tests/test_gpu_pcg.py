@@ -1,0 +1,215 @@
+"""GPU block-Jacobi PCG against the CPU oracle: iteration counts (FP64 within 2
+iterations; reduced maps report their delay), relative-residual histories,
+the adaptive switch, degenerate cases, error paths, determinism, and the
+full-size 128^3 workload on sampled outputs."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import blocks as OB
+from oracle import pcg as OP
+from oracle import precision as OPr
+from paper_2407_15973_amd import binding as mb
+from paper_2407_15973_amd import gen
+
+from gpu_helpers import dev, gamma, tensor
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_solve(A, bp, b, policy, tol, maxit, chunk=16, history=True, raise_on_error=True):
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, policy)
+    S = mb.Solver(A.n, dev())
+    r = S.solve(Ad, M, tensor(b), tol=tol, maxit=maxit, chunk=chunk, history=history,
+                raise_on_error=raise_on_error)
+    return r, M
+
+
+def _tags(prec, nb):
+    return np.full(nb, prec, np.uint8)
+
+
+def test_config1_fp64_matches_oracle():
+    p = gen.config1(0)
+    res, _ = _gpu_solve(p.A, p.block_ptr, p.b, mb.Policy(), p.tol, p.maxit)
+    ref = OP.solve_bjac(p.A, p.block_ptr, p.b, tol=p.tol, maxit=p.maxit)
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= 2
+    m = min(res.iters, ref.iters) - 1
+    np.testing.assert_allclose(res.relres_hist[:m], ref.history[:m], rtol=1e-6)
+    x = res.x.cpu().numpy()
+    assert OP.true_relres(p.A, x, p.b) <= 1.5 * p.tol
+    assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("prec", [OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16])
+def test_config2_small_fixed_precision(prec):
+    p = gen.config2(seed=1, N=24, b=32)
+    nb = len(p.block_ptr) - 1
+    pol = mb.Policy() if prec == OPr.FP64 else mb.Policy(mode=mb.FIXED, low=prec)
+    res, _ = _gpu_solve(p.A, p.block_ptr, p.b, pol, 1e-10, 2000)
+    ref = OP.solve_bjac(p.A, p.block_ptr, p.b, _tags(prec, nb), tol=1e-10, maxit=2000)
+    ref64 = ref if prec == OPr.FP64 else OP.solve_bjac(p.A, p.block_ptr, p.b, tol=1e-10, maxit=2000)
+    assert res.status == mb.OK
+    delay = res.iters - ref64.iters
+    print(f"prec {OPr.NAMES[prec]}: gpu {res.iters} oracle {ref.iters} oracle-fp64 {ref64.iters} delay {delay}")
+    assert abs(res.iters - ref.iters) <= (2 if prec in (OPr.FP64, OPr.FP32) else 4)
+    x = res.x.cpu().numpy()
+    assert OP.true_relres(p.A, x, p.b) <= 2e-10
+
+
+def test_uneven_blocks_mixed_explicit_map():
+    rng = np.random.default_rng(8)
+    A = gen.diffusion3d(gen.kappa_loguniform((20, 18, 16), rng))
+    bp = gen.random_blocks(A.n, rng)
+    nb = len(bp) - 1
+    tags = rng.choice([OPr.FP64, OPr.FP32, OPr.FP16], size=nb).astype(np.uint8)
+    b = rng.uniform(-1, 1, A.n)
+    res, M = _gpu_solve(A, bp, b, mb.Policy(mode=mb.EXPLICIT, explicit_tags=tags), 1e-10, 2000)
+    ref = OP.solve_bjac(A, bp, b, tags, tol=1e-10, maxit=2000)
+    assert abs(res.iters - ref.iters) <= 3
+    assert OP.true_relres(A, res.x.cpu().numpy(), b) <= 2e-10
+
+
+def _amp_case():
+    p = gen.config2(seed=2, N=20, b=32)
+    return p.A, p.block_ptr, p.b
+
+
+@pytest.mark.parametrize("temporal,adp", [(mb.TEMPORAL_HL, 1e-3), (mb.TEMPORAL_HL, 10.0), (mb.TEMPORAL_LH, 1e-4),
+                                          (mb.TEMPORAL_LH, 10.0)])
+def test_adaptive_switch_matches_oracle(temporal, adp):
+    A, bp, b = _amp_case()
+    nb = len(bp) - 1
+    pol = mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=temporal, adp_tol=adp)
+    res, _ = _gpu_solve(A, bp, b, pol, 1e-10, 2000)
+    ref = OP.solve_bjac(A, bp, b, _tags(OPr.FP16, nb), tol=1e-10, maxit=2000, temporal=temporal, adp_tol=adp)
+    assert abs(res.iters - ref.iters) <= 3
+    # the switch sequence agrees wherever relres is not within rounding of adp_tol
+    m = min(res.iters, ref.iters)
+    seen = [math.inf] + ref.history[:m - 1]
+    near = np.array([abs(v / adp - 1) < 1e-6 for v in seen])
+    got = res.high_hist[:m].astype(bool)
+    exp = np.array(ref.used_high[:m])
+    assert np.array_equal(got[~near], exp[~near])
+    assert res.high_applications == int(res.high_hist.sum())
+    assert OP.true_relres(A, res.x.cpu().numpy(), b) <= 2e-10
+
+
+def test_adaptive_degenerations_on_gpu():
+    A, bp, b = _amp_case()
+    uni, _ = _gpu_solve(A, bp, b, mb.Policy(), 1e-10, 2000)
+    fmp, _ = _gpu_solve(A, bp, b, mb.Policy(mode=mb.FIXED, low=mb.FP16), 1e-10, 2000)
+    hl0, _ = _gpu_solve(A, bp, b, mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=mb.TEMPORAL_HL, adp_tol=0.0),
+                        1e-10, 2000)
+    lh0, _ = _gpu_solve(A, bp, b, mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=mb.TEMPORAL_LH, adp_tol=0.0),
+                        1e-10, 2000)
+    assert hl0.iters == uni.iters and np.all(hl0.high_hist == 1)
+    assert lh0.iters == fmp.iters and np.all(lh0.high_hist == 0)
+    np.testing.assert_allclose(hl0.x.cpu().numpy(), uni.x.cpu().numpy(), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(lh0.x.cpu().numpy(), fmp.x.cpu().numpy(), rtol=0, atol=1e-12)
+
+
+def test_rule_policy_matches_oracle_rule():
+    p = gen.config3(seed=1, N=24, b=48)
+    res, M = _gpu_solve(p.A, p.block_ptr, p.b, mb.Policy(mode=mb.RULE), 1e-10, 3000)
+    H = OB.invert_blocks(p.A, p.block_ptr)
+    F, raw = OB.block_features(p.A, p.block_ptr, H)
+    tags = OB.select_rule(raw)
+    ref = OP.solve_bjac(p.A, p.block_ptr, p.b, tags, tol=1e-10, maxit=3000)
+    assert np.array_equal(M.tags(), tags)
+    # a strongly anisotropic case (~1300 iterations, mixed FP16/FP32 storage):
+    # the FP32 accumulation of the stored inverses perturbs the iterates, and
+    # the count follows within a few percent
+    assert abs(res.iters - ref.iters) <= max(3, 0.05 * ref.iters)
+    assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10
+
+
+def test_fp64_long_anisotropic_solve_within_two_iterations():
+    p = gen.config3(seed=1, N=24, b=48)
+    res, _ = _gpu_solve(p.A, p.block_ptr, p.b, mb.Policy(), 1e-10, 3000)
+    ref = OP.solve_bjac(p.A, p.block_ptr, p.b, tol=1e-10, maxit=3000)
+    print(f"fp64 anisotropic: gpu {res.iters} oracle {ref.iters}")
+    assert abs(res.iters - ref.iters) <= 2
+
+
+def test_chunk_size_and_determinism():
+    A, bp, b = _amp_case()
+    pol = mb.Policy(mode=mb.FIXED, low=mb.FP32)
+    r2, _ = _gpu_solve(A, bp, b, pol, 1e-10, 2000, chunk=2)
+    r16, _ = _gpu_solve(A, bp, b, pol, 1e-10, 2000, chunk=16)
+    r16b, _ = _gpu_solve(A, bp, b, pol, 1e-10, 2000, chunk=16)
+    assert r2.iters == r16.iters == r16b.iters
+    assert np.array_equal(r16.x.cpu().numpy(), r16b.x.cpu().numpy())
+    assert np.array_equal(r2.x.cpu().numpy(), r16.x.cpu().numpy())
+
+
+def test_graph_reuse_across_right_hand_sides():
+    A, bp, b = _amp_case()
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    S = mb.Solver(A.n, dev())
+    x = tensor(np.zeros(A.n))
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        bb = rng.uniform(-1, 1, A.n)
+        r = S.solve(Ad, M, tensor(bb), tol=1e-10, maxit=2000, x=x)
+        assert r.status == mb.OK
+        assert OP.true_relres(A, r.x.cpu().numpy(), bb) <= 2e-10
+
+
+def test_error_paths():
+    A, bp, b = _amp_case()
+    r, _ = _gpu_solve(A, bp, b, mb.Policy(), 1e-10, 1)
+    assert r.status == mb.NOT_CONVERGED and r.iters == 1
+    r, _ = _gpu_solve(A, bp, b, mb.Policy(), 1e-20, 30)
+    assert r.status == mb.NOT_CONVERGED and r.iters == 30
+    r, _ = _gpu_solve(A, bp, np.zeros(A.n), mb.Policy(), 1e-10, 30)
+    assert r.status == mb.OK and r.iters == 0 and not np.any(r.x.cpu().numpy())
+    bn = b.copy()
+    bn[5] = np.nan
+    r, _ = _gpu_solve(A, bp, bn, mb.Policy(), 1e-10, 30, raise_on_error=False)
+    assert r.status == mb.EBREAKDOWN
+
+
+def test_indefinite_matrix_breaks_down():
+    # SPD (identity) diagonal blocks, indefinite A: p^T A p < 0 at the first step
+    n, h = 64, 32
+    rows = list(range(n)) + list(range(h)) + list(range(h, n))
+    cols = list(range(n)) + list(range(h, n)) + list(range(h))
+    vals = [1.0] * n + [2.0] * n
+    A = gen._csr_from_coo(n, np.array(rows), np.array(cols), np.array(vals))
+    b = np.concatenate([np.ones(h), -np.ones(h)])
+    r, _ = _gpu_solve(A, gen.uniform_blocks(n, h), b, mb.Policy(), 1e-10, 30, raise_on_error=False)
+    assert r.status == mb.EBREAKDOWN
+
+
+def test_full_size_config2_sampled_parity():
+    # the 128^3 workload the benchmark times, FP16 storage, checked on sampled
+    # blocks and rows against the oracle and by the FP64 true residual
+    p = gen.config2(seed=0)
+    nb = len(p.block_ptr) - 1
+    Ad = mb.DeviceCSR(p.A, dev())
+    M = mb.BlockJacobi(Ad, p.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    rng = np.random.default_rng(10)
+    ks = rng.choice(nb, size=48, replace=False)
+    sub = np.concatenate([[0], np.cumsum(np.diff(p.block_ptr)[ks])]).astype(np.int32)
+    rows = np.concatenate([np.arange(p.block_ptr[k], p.block_ptr[k + 1]) for k in ks])
+    S = p.A.to_scipy()[rows][:, rows]
+    Asub = gen.CSR(len(rows), S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    H = OB.invert_blocks(Asub, sub)
+    store = OB.store_blocks(H, _tags(OPr.FP16, len(ks)))
+    r = rng.uniform(-1, 1, p.A.n)
+    z = M.apply(tensor(r)).cpu().numpy()
+    zref = OB.apply(store, sub, r[rows])
+    bound = (gamma(32, 2.0 ** -24) + 2.0 ** -10) * OB.apply_abs(store, sub, r[rows])
+    assert np.all(np.abs(z[rows] - zref) <= bound)
+    for j, k in enumerate(ks[:8]):
+        got, s = M.block(int(k))
+        Hh, sref, _ = store[j]
+        assert s == sref and np.all(np.abs(got - Hh) <= 2.0 ** -10 * np.abs(Hh) + 2.0 ** -24)
+    res = mb.Solver(p.A.n, dev()).solve(Ad, M, tensor(p.b), tol=1e-10, maxit=5000)
+    assert res.status == mb.OK
+    assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10

@@ -114,7 +114,7 @@ def test_features_hand_values_1d_poisson():
     # A_ii = tridiag(-1,2,-1) of size 4: ||A||_1 = 4, ||A^-1||_1 = max col sum of
     # (1/5)[[4,3,2,1],[3,6,4,2],[2,4,6,3],[1,2,3,4]] = 15/5 = 3
     np.testing.assert_allclose(raw["kappa1"][0], 12.0, rtol=1e-14)
-    np.testing.assert_allclose(F[0, 14], np.log10(6 / 1))
+    np.testing.assert_allclose(F[0, 14], np.log10(6 / 4))       # diag of A_ii^-1: 4,6,6,4 /5
     assert F[0, 15] == 0.0
 
 
