@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -122,6 +124,14 @@ def main():
         solve = [r[2][1].elapsed_time(r[2][2]) for r in runs]
         return (t1 - t0) * 1e3 / k, float(np.median(setup)), float(np.median(solve)), runs[-1]
 
+    if args.calibrate:
+        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB read, 1 GiB written")
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step(pol16)
