@@ -43,8 +43,10 @@ struct WaveIter {
 };
 
 // Workgroups of a persistent grid for T wave tiles: no more than one resident
-// round of the kernel (occupancy x compute units), at most kMaxGrid, a
-// multiple of 8 when possible.
+// round of the kernel (occupancy x compute units), at most kGridPerCu per
+// compute unit, at least two tiles per wave (fewer, longer-lived workgroups
+// cost less ramp-up and a shorter end-of-kernel reduction), a multiple of 8
+// when possible.
 static int grid_for_waves(int T, const void *kernel) {
   static std::unordered_map<const void *, int> cap;
   auto it = cap.find(kernel);
@@ -57,9 +59,9 @@ static int grid_for_waves(int T, const void *kernel) {
       per_cu = 1;
       cus = 256;
     }
-    it = cap.emplace(kernel, per_cu * cus).first;
+    it = cap.emplace(kernel, (per_cu < kGridPerCu ? per_cu : kGridPerCu) * cus).first;
   }
-  int G = (T + 3) / 4;
+  int G = (T + 7) / 8;
   if (G > it->second) G = it->second;
   if (G > kMaxGrid) G = kMaxGrid;
   if (G >= 8) G &= ~7;
