@@ -120,15 +120,18 @@ def test_rule_policy_matches_oracle_rule():
     tags = OB.select_rule(raw)
     ref = OP.solve_bjac(p.A, p.block_ptr, p.b, tags, tol=1e-10, maxit=3000)
     assert np.array_equal(M.tags(), tags)
-    # a strongly anisotropic case (~1300 iterations, mixed FP16/FP32 storage):
-    # the FP32 accumulation of the stored inverses perturbs the iterates, and
-    # the count follows within a few percent
+    # mixed FP64/FP32 storage chosen per block
+    assert len(set(tags.tolist())) >= 2
     assert abs(res.iters - ref.iters) <= max(3, 0.05 * ref.iters)
     assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10
 
 
 def test_fp64_long_anisotropic_solve_within_two_iterations():
-    p = gen.config3(seed=1, N=24, b=48)
+    # the orientation of the paper's Ani(s) (strong y, z couplings across the
+    # row blocks): ~1,100 iterations, where rounding differences accumulate
+    rng = np.random.default_rng(1)
+    A = gen.diffusion3d(gen.kappa_subcube_jumps(24, rng), aniso=(1.0, 1e3, 1e3))
+    p = gen.Problem("ani", A, gen.uniform_blocks(A.n, 48), gen.rhs_uniform(A.n, rng), 1e-10, 3000)
     res, _ = _gpu_solve(p.A, p.block_ptr, p.b, mb.Policy(), 1e-10, 3000)
     ref = OP.solve_bjac(p.A, p.block_ptr, p.b, tol=1e-10, maxit=3000)
     print(f"fp64 anisotropic: gpu {res.iters} oracle {ref.iters}")
