@@ -107,7 +107,7 @@ typedef struct {
   int64_t high_bytes;            /* bytes of the all-FP64 map (temporal only)  */
   int32_t temporal;
   int32_t mode;
-  int32_t ntiles;                /* apply tiles (whole blocks, <= 256 padded rows) */
+  int32_t ntiles;                /* apply wave tiles (whole blocks, <= 64 padded rows) */
   int32_t reserved;
 } bjac_info;
 
@@ -176,6 +176,14 @@ int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block, double *o
  * low map). Reduced blocks use the FP32 copy of r and FP32 accumulation. */
 int bjac_apply(const bjac_handle *h, int32_t which, const double *r, double *z, void *stream);
 
+/* ---- Z = M^-1 R for up to 8 columns (Algorithm 3.1 on a block of columns)
+ * R, Z: device FP64, row-major [n][m] (the m values of one row contiguous),
+ * distinct, 1 <= m <= 8. Applies the low map only. Each block product runs on
+ * the 16x16x4 matrix-core instructions: FP32 for FP32/BF16/FP16 blocks (the
+ * FP32 copy of R, FP32 accumulation, then times the block scale in FP64),
+ * FP64 for FP64 blocks. */
+int bjac_apply_multi(const bjac_handle *h, const double *R, double *Z, int32_t m, void *stream);
+
 /* ---- q = A p, the FP64 CSR product used by PCG ------------------------- */
 int bjac_spmv(const bjac_csr *A, const double *p, double *q, void *stream);
 
@@ -195,6 +203,50 @@ int pcg_workspace_query(int64_t n, size_t *workspace_bytes);
 int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *x,
               const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes,
               bjac_stats *stats, void *stream);
+
+/* ---- batched multi-RHS PCG (Sec. 3.2 per system and column) -------------
+ * nsys independent SPD systems stacked as one block-diagonal CSR A (system s
+ * owns rows sys_row[s] .. sys_row[s+1]-1 and only couples inside them) with
+ * sys_m[s] in 1..8 right-hand sides each. M is a handle set up on the same
+ * stacked A whose block partition has every sys_row[s] as a block boundary;
+ * only its low map is used (no temporal switch). Every (system, column) pair
+ * runs its own CG with x0 = 0 and its own scalars and stops on its own
+ * ||r|| / ||r_0|| <= tol (Sec. 4.2); the z = M^-1 R products of a block with
+ * up to 8 columns run on the 16x16x4 matrix-core instructions (FP32 for
+ * FP32/BF16/FP16 blocks with the FP32 copy of R, FP64 for FP64 blocks).
+ * sys_row[nsys+1], sys_m[nsys]: HOST arrays. b, x: device FP64, system s's
+ * block at offset sum_{t<s} rows_t * m_t, row-major [rows_s][m_s] (the m_s
+ * values of one row are contiguous). col_iters, col_status, col_relres: HOST
+ * arrays of sum_s m_s entries (may be NULL), column order = system order,
+ * then column. opts: tol, maxit, chunk (iterations per captured graph) are
+ * used; relres_hist, high_hist and profile are ignored. */
+typedef struct {
+  int32_t chunk_rows;   /* rows per SpMV chunk and padded rows per apply chunk
+                           (>= 64; 0 = 1024). Chunks never cross systems.     */
+  int32_t wg_per_cu;    /* workgroups of 256 threads per compute unit in the
+                           persistent launches (1..8; 0 = 4)                  */
+} bjac_batch_cfg;
+
+int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t nsys,
+                                const int32_t *sys_row, const int32_t *sys_m,
+                                const bjac_batch_cfg *cfg, size_t *workspace_bytes);
+/* Returns BJAC_OK when every column converged, else BJAC_EBREAKDOWN if any
+ * column broke down, else BJAC_NOT_CONVERGED. stats: iters = the largest
+ * column count, relres = the largest column relres. Synchronises the stream. */
+int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
+                      const int32_t *sys_m, const double *b, double *x, const bjac_solve_opts *opts,
+                      const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes,
+                      int32_t *col_iters, int32_t *col_status, double *col_relres,
+                      bjac_stats *stats, void *stream);
+/* Autotuner: times `iters` PCG iterations of the batch (x is overwritten)
+ * under each of the ncand configurations and returns the fastest in *best;
+ * ms_per_iter (HOST, ncand entries, may be NULL) receives every timing. The
+ * workspace must hold the largest query over the candidates. Synchronises
+ * the stream. */
+int pcg_batched_tune(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
+                     const int32_t *sys_m, const double *b, double *x, const bjac_batch_cfg *cands,
+                     int32_t ncand, int32_t iters, void *workspace, size_t workspace_bytes,
+                     float *ms_per_iter, int32_t *best, void *stream);
 
 /* ---- learned per-block precision selector -------------------------------
  * Network: standardised 16 block features -> 64 ReLU -> 64 ReLU -> 3 logits

@@ -31,6 +31,7 @@ SYMBOLS = (
     "bjac_get_info", "bjac_get_tags", "bjac_get_features", "bjac_get_block", "bjac_apply",
     "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
+    "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
 )
 
 
@@ -62,6 +63,10 @@ class bjac_stats(C.Structure):
                 ("high_applications", C.c_int32), ("graph_launches", C.c_int32), ("solve_ms", C.c_double),
                 ("spmv_ms", C.c_double), ("apply_ms", C.c_double), ("update_ms", C.c_double),
                 ("n_spmv", C.c_int32), ("n_apply", C.c_int32), ("n_update", C.c_int32), ("reserved", C.c_int32)]
+
+
+class bjac_batch_cfg(C.Structure):
+    _fields_ = [("chunk_rows", C.c_int32), ("wg_per_cu", C.c_int32)]
 
 
 _lib = None
@@ -96,6 +101,12 @@ def load(path: str = LIB_PATH):
         "bjac_mlp_workspace_query": (C.c_int, [i32, P(sz)]),
         "bjac_mlp_backward": (C.c_int, [vp, vp, vp, i32, vp, vp, vp, sz, vp]),
         "bjac_mlp_adam": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
+        "bjac_apply_multi": (C.c_int, [vp, vp, vp, i32, vp]),
+        "pcg_batched_workspace_query": (C.c_int, [P(bjac_csr), vp, i32, vp, vp, P(bjac_batch_cfg), P(sz)]),
+        "pcg_solve_batched": (C.c_int, [P(bjac_csr), vp, i32, vp, vp, vp, vp, P(bjac_solve_opts),
+                                        P(bjac_batch_cfg), vp, sz, vp, vp, vp, P(bjac_stats), vp]),
+        "pcg_batched_tune": (C.c_int, [P(bjac_csr), vp, i32, vp, vp, vp, vp, P(bjac_batch_cfg), i32, i32, vp, sz,
+                                       vp, P(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -238,6 +249,13 @@ class BlockJacobi:
         _check(load().bjac_apply(self.h, which, _ptr(r), _ptr(z), _stream()), "bjac_apply")
         return z
 
+    def apply_multi(self, R):
+        """Z = M^-1 R for a contiguous (n, m) FP64 device tensor, m <= 8."""
+        assert R.dim() == 2 and R.is_contiguous()
+        Z = _torch().empty_like(R)
+        _check(load().bjac_apply_multi(self.h, _ptr(R), _ptr(Z), R.shape[1], _stream()), "bjac_apply_multi")
+        return Z
+
 
 @dataclass
 class SolveResult:
@@ -327,3 +345,77 @@ class MlpTrainer:
         self.t += 1
         _check(load().bjac_mlp_adam(_ptr(blob), _ptr(self.grad), _ptr(self.m), _ptr(self.v), self.t, lr, b1, b2,
                                     eps, _stream()), "bjac_mlp_adam")
+
+
+# ------------------------------------------------------------ batched PCG
+@dataclass
+class BatchResult:
+    x: object                 # device [sum rows_s * m_s], system-major, row-major per system
+    col_iters: np.ndarray
+    col_status: np.ndarray
+    col_relres: np.ndarray
+    status: int
+    iters: int
+    graph_launches: int
+    solve_ms: float
+
+
+class BatchSolver:
+    """Batched multi-right-hand-side PCG over a stacked block-diagonal system.
+
+    ``sys_row`` (nsys + 1 row offsets) and ``sys_m`` (columns per system) are
+    host arrays; the workspace is sized for the largest of the configurations
+    this object is asked to run."""
+
+    def __init__(self, A: DeviceCSR, M: BlockJacobi, sys_row, sys_m):
+        self.A, self.M = A, M
+        self.sys_row = np.ascontiguousarray(sys_row, dtype=np.int32)
+        self.sys_m = np.ascontiguousarray(sys_m, dtype=np.int32)
+        self.nsys = len(self.sys_m)
+        self.ncols = int(self.sys_m.sum())
+        self.veclen = int(np.sum(np.diff(self.sys_row).astype(np.int64) * self.sys_m))
+        self.ws = None
+
+    def _query(self, cfg: bjac_batch_cfg) -> int:
+        nbytes = C.c_size_t()
+        _check(load().pcg_batched_workspace_query(C.byref(self.A.c), self.M.h, self.nsys,
+                                                  self.sys_row.ctypes.data, self.sys_m.ctypes.data,
+                                                  C.byref(cfg), C.byref(nbytes)), "pcg_batched_workspace_query")
+        return nbytes.value
+
+    def _ensure(self, nbytes: int):
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = _torch().empty(max(1, nbytes), dtype=_torch().uint8, device=self.A.val.device)
+
+    def solve(self, b, tol=1e-10, maxit=5000, chunk=16, cfg=(0, 0), x=None) -> BatchResult:
+        torch = _torch()
+        c = bjac_batch_cfg(*cfg)
+        self._ensure(self._query(c))
+        x = torch.empty_like(b) if x is None else x
+        its = np.zeros(self.ncols, dtype=np.int32)
+        sts = np.zeros(self.ncols, dtype=np.int32)
+        rel = np.zeros(self.ncols, dtype=np.float64)
+        opts = bjac_solve_opts(tol, maxit, chunk, None, None, 0, 0)
+        st = bjac_stats()
+        rc = load().pcg_solve_batched(C.byref(self.A.c), self.M.h, self.nsys, self.sys_row.ctypes.data,
+                                      self.sys_m.ctypes.data, _ptr(b), _ptr(x), C.byref(opts), C.byref(c),
+                                      _ptr(self.ws), self.ws.numel(), its.ctypes.data, sts.ctypes.data,
+                                      rel.ctypes.data, C.byref(st), _stream())
+        if rc < 0 and rc != EBREAKDOWN:
+            raise MpbjacError(rc, "pcg_solve_batched")
+        return BatchResult(x, its, sts, rel, rc, st.iters, st.graph_launches, st.solve_ms)
+
+    def tune(self, b, cands, iters=8):
+        """Times ``iters`` iterations under each (chunk_rows, wg_per_cu) pair;
+        returns (best index, ms per iteration of every candidate)."""
+        torch = _torch()
+        arr = (bjac_batch_cfg * len(cands))(*[bjac_batch_cfg(*c) for c in cands])
+        self._ensure(max(self._query(c) for c in arr))
+        x = torch.empty_like(b)
+        ms = np.zeros(len(cands), dtype=np.float32)
+        best = C.c_int32(-1)
+        _check(load().pcg_batched_tune(C.byref(self.A.c), self.M.h, self.nsys, self.sys_row.ctypes.data,
+                                       self.sys_m.ctypes.data, _ptr(b), _ptr(x), arr, len(cands), iters,
+                                       _ptr(self.ws), self.ws.numel(), ms.ctypes.data, C.byref(best), _stream()),
+               "pcg_batched_tune")
+        return int(best.value), ms

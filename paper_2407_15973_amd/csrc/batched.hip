@@ -1,0 +1,1012 @@
+// Batched multi-right-hand-side block-Jacobi PCG: many independent SPD systems
+// (stacked into one block-diagonal CSR) with 1..8 right-hand sides each; every
+// (system, column) pair runs its own CG (Sec. 3.2) with its own scalars and
+// stops on its own relative residual (Sec. 4.2). The block products
+// Z_blk = s * Hhat R_blk (Algorithm 3.1 applied to up to 8 columns at once)
+// run on the matrix cores: the stored fragment layout is the A operand of the
+// 16x16x4 FP32 (and FP64) matrix instructions, the FP32 copies of the
+// residual columns form the B operand.
+//
+// Each kernel walks fixed chunks of rows (SpMV) or of whole blocks (apply)
+// that never cross a system; per-chunk, per-column partial dots are reduced
+// per system by a one-workgroup-per-system kernel in chunk order, so results
+// are deterministic and no intra-kernel cross-workgroup synchronisation is
+// needed.
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace mpb {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBCols = 8;          // most right-hand sides per system
+constexpr int kBWaveRows = 64;
+
+enum BStatus { BS_RUNNING = 0, BS_CONVERGED = 1, BS_MAXIT = 2, BS_BREAKDOWN = -3 };
+
+struct BTables {
+  int32_t S, nch, nach;
+  const int32_t *sys_row, *sys_m, *sys_col, *sys_ch, *sys_ach;
+  const int64_t *sys_vec;
+  const int32_t *ch_row0, *ch_sys;    // SpMV chunks: rows [ch_row0[i], ch_row0[i+1])
+  const int32_t *ach_blk, *ach_sys;   // apply chunks: blocks [ach_blk[i], ach_blk[i+1])
+};
+
+struct BState {
+  double *rho, *alpha, *beta, *rnorm0, *relres;
+  int32_t *iter, *status;
+  int32_t *n_active;
+  double tol;
+  int32_t maxit;
+};
+
+__device__ __forceinline__ void bwave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave slot of this wave in a grid whose size is a multiple of 8: workgroup g
+// runs on XCD g mod 8, so slots are numbered XCD by XCD and each XCD's waves
+// own one contiguous run of chunks (and of rows), keeping the SpMV's
+// neighbour rows in that XCD's L2.
+__device__ __forceinline__ int wave_slot(int wv) {
+  const int G = gridDim.x, g = blockIdx.x;
+  return (((g & 7) * (G >> 3)) + (g >> 3)) * 4 + wv;
+}
+
+// ------------------------------------------------------------------ SpMV
+struct BSpmvArgs {
+  BTables t;
+  const int32_t *rp, *ci;
+  const double *v;
+  const double *z, *pold;
+  double *pnew, *q;
+  const double *beta;
+  double *part;          // [nch][8]
+  const int32_t *n_active;
+  const int32_t *sched;   // [waves + 1] first chunk of each wave slot
+};
+
+// One 64-row tile of a system with M columns: q = A p_new, p_new = z + beta p_old
+// formed at every read; returns the per-column (p_new, q) contributions.
+template <int M>
+__device__ __forceinline__ void bspmv_tile(const BSpmvArgs &a, const double (&beta)[kBCols], int rs, int nrows,
+                                           int64_t v0, int r0, int r1, double *sv, int *sc, double (&pq)[kBCols]) {
+  constexpr int CAP = kSpmvNnzCap;
+  constexpr int NL = CAP / 64;
+  const int lane = threadIdx.x & 63;
+  const int row = r0 + lane;
+  const bool has = row < r1;
+  const int rowc = min(row, r1 - 1);
+  const int s = a.rp[rowc], e = a.rp[rowc + 1];
+  const int e0 = __builtin_amdgcn_readfirstlane(a.rp[r0]);
+  const int cnt = __builtin_amdgcn_readfirstlane(a.rp[r1]) - e0;
+  const int len = has ? e - s : 0;
+  const bool staged = cnt > 0 && cnt <= CAP;
+  if (staged) {
+    double vv[NL];
+    int cc[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = min(lane + 64 * k, cnt - 1);
+      vv[k] = a.v[e0 + i];
+      cc[k] = a.ci[e0 + i];
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int i = lane + 64 * k;
+      if (i < cnt) {
+        sv[i] = vv[k];
+        sc[i] = cc[k];
+      }
+    }
+    bwave_lds_sync();
+  }
+  double acc[M], prow[M];
+  bool found = false;
+#pragma unroll
+  for (int c = 0; c < M; ++c) acc[c] = prow[c] = 0.0;
+  constexpr int U = M >= 4 ? 2 : (M == 1 ? 8 : 4);  // entries with loads in flight together
+  const int base = staged ? s - e0 : s;
+  for (int k0 = 0; k0 < len; k0 += U) {
+    int cs[U];
+    double vs[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int idx = base + min(k0 + k, len - 1);
+      cs[k] = staged ? sc[idx] : a.ci[idx];
+      const double vv = staged ? sv[idx] : a.v[idx];
+      vs[k] = (k0 + k < len) ? vv : 0.0;
+    }
+    double g[U][M];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      // a column outside the system (not a block-diagonal stack) is clamped
+      // into it: wrong values for an invalid input, never an access outside x
+      const int jl = min(max(cs[k] - rs, 0), nrows - 1);
+      const int64_t jb = v0 + (int64_t)jl * M;
+#pragma unroll
+      for (int c = 0; c < M; ++c) g[k][c] = fma(beta[c], a.pold[jb + c], a.z[jb + c]);
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const bool me = cs[k] == row && k0 + k < len;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        acc[c] = fma(vs[k], g[k][c], acc[c]);
+        if (me) prow[c] = g[k][c];
+      }
+      found = found || me;
+    }
+  }
+  if (staged) bwave_lds_sync();
+  if (has) {
+    const int64_t rb = v0 + (int64_t)(row - rs) * M;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const double pr = found ? prow[c] : fma(beta[c], a.pold[rb + c], a.z[rb + c]);
+      a.q[rb + c] = acc[c];
+      a.pnew[rb + c] = pr;
+      pq[c] = fma(pr, acc[c], pq[c]);
+    }
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, double *sv, int *sc) {
+  const int lane = threadIdx.x & 63;
+  const int s = __builtin_amdgcn_readfirstlane(a.t.ch_sys[ch]);
+  const int rs = a.t.sys_row[s];
+  const int nrows = a.t.sys_row[s + 1] - rs;
+  const int64_t v0 = a.t.sys_vec[s];
+  const int c0 = a.t.sys_col[s];
+  double beta[kBCols];
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) beta[c] = c < M ? a.beta[c0 + c] : 0.0;
+  double pq[kBCols];
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) pq[c] = 0.0;
+  const int rb = a.t.ch_row0[ch], re = a.t.ch_row0[ch + 1];
+  for (int r0 = rb; r0 < re; r0 += kBWaveRows)
+    bspmv_tile<M>(a, beta, rs, nrows, v0, r0, min(re, r0 + kBWaveRows), sv, sc, pq);
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) {
+    const double t = wave_sum(pq[c]);
+    if (lane == c) a.part[(int64_t)ch * kBCols + c] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
+  __shared__ double svs[4][kSpmvNnzCap];
+  __shared__ int scs[4][kSpmvNnzCap];
+  if (*a.n_active == 0) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wave_slot(wv);
+  const int ce = a.sched[w + 1];
+  for (int ch = a.sched[w]; ch < ce; ++ch) {
+    const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ch_sys[ch]]);
+    switch (m) {
+      case 1: bspmv_chunk<1>(a, ch, svs[wv], scs[wv]); break;
+      case 2: bspmv_chunk<2>(a, ch, svs[wv], scs[wv]); break;
+      case 3: bspmv_chunk<3>(a, ch, svs[wv], scs[wv]); break;
+      case 4: bspmv_chunk<4>(a, ch, svs[wv], scs[wv]); break;
+      case 5: bspmv_chunk<5>(a, ch, svs[wv], scs[wv]); break;
+      case 6: bspmv_chunk<6>(a, ch, svs[wv], scs[wv]); break;
+      case 7: bspmv_chunk<7>(a, ch, svs[wv], scs[wv]); break;
+      default: bspmv_chunk<8>(a, ch, svs[wv], scs[wv]); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------- update + apply
+struct BApplyArgs {
+  BTables t;
+  const int32_t *blk_row;
+  const uint8_t *bpad;
+  DevMap map;
+  double *x, *r, *z;
+  const double *p, *q;
+  const double *alpha;
+  double *part;          // [nach][2][8]: (r, r) then (r, z)
+  const int32_t *n_active;
+  const int32_t *sched;   // [waves + 1] first chunk of each wave slot
+};
+
+// One 16-row tile of a stored block times the FP32 (or FP64) residual columns
+// in the wave's LDS, on the matrix cores; result rows written to zt[row][8].
+template <int B, int P>
+__device__ __forceinline__ void bmtile(const uint8_t *blk, double scale, int mt, const float *r32, const double *r64,
+                                       double *zt, int lane) {
+  constexpr int K = B / 4;
+  constexpr int BY = prec_bytes(P);
+  constexpr int V = 16 / BY;
+  constexpr int G = (K + V - 1) / V;
+  const int kq = lane >> 4, col = lane & 15;
+  uint4 h[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int vg = layout_vg(B, V, g);
+    const uint8_t *src = blk + (layout_group_base(B, V, mt, g) + (int64_t)lane * vg) * BY;
+    if (vg * BY == 16) {
+      h[g] = *(const uint4 *)src;
+    } else {
+      const uint2 t = *(const uint2 *)src;
+      h[g] = make_uint4(t.x, t.y, 0u, 0u);
+    }
+  }
+  if constexpr (P == P64) {
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ks = 2 * g + e;
+        const double av = e ? __hiloint2double((int)h[g].w, (int)h[g].z) : __hiloint2double((int)h[g].y, (int)h[g].x);
+        const double bv = col < kBCols ? r64[(4 * ks + kq) * kBCols + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+    }
+    // FP64 result layout: lane l, register j holds row 4j + l/16, column l%16
+    if (col < kBCols) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) zt[(16 * mt + 4 * j + kq) * kBCols + col] = acc[j];
+    }
+  } else {
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int vg = layout_vg(B, V, g);
+      const uint32_t w[4] = {h[g].x, h[g].y, h[g].z, h[g].w};
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (e < vg) {
+          const int ks = g * V + e;
+          float av;
+          if constexpr (P == P32) av = __uint_as_float(w[e]);
+          else if constexpr (P == PBF16) av = (e & 1) ? bf16_hi(w[e >> 1]) : bf16_lo(w[e >> 1]);
+          else av = (e & 1) ? f16_hi(w[e >> 1]) : f16_lo(w[e >> 1]);
+          const float bv = col < kBCols ? r32[(4 * ks + kq) * kBCols + col] : 0.0f;
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+        }
+      }
+    }
+    // FP32 result layout: lane l, register j holds row 4(l/16) + j, column l%16
+    if (col < kBCols) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) zt[(16 * mt + 4 * kq + j) * kBCols + col] = (double)acc[j] * scale;
+    }
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void bmtile_dispatch(int prec, const uint8_t *blk, double scale, int mt, const float *r32,
+                                                const double *r64, double *zt, int lane) {
+  switch (prec) {
+    case P64: bmtile<B, P64>(blk, scale, mt, r32, r64, zt, lane); break;
+    case P32: bmtile<B, P32>(blk, scale, mt, r32, r64, zt, lane); break;
+    case PBF16: bmtile<B, PBF16>(blk, scale, mt, r32, r64, zt, lane); break;
+    default: bmtile<B, P16>(blk, scale, mt, r32, r64, zt, lane); break;
+  }
+}
+
+__device__ __forceinline__ int rl(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ int64_t rl64(int64_t v, int src) {
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), src);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Blocks [k0, kend) of one system (rows from rs, vectors from v0, M columns):
+// per wave tile of <= 64 padded rows, the row phase (UPD: x += alpha p,
+// r -= alpha q) stages r, in FP64 and as its FP32 copy, in LDS as the B
+// operand; each 16-row tile of each block then takes B/4 matrix-core steps;
+// z goes back to HBM from LDS and (r, r), (r, z) accumulate per column.
+template <bool UPD>
+__device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int kend, int rs, int64_t v0, int M,
+                                              const double (&alpha)[kBCols], float *r32, double *r64, double *zt,
+                                              double (&rr)[kBCols], double (&rz)[kBCols]) {
+  const int lane = threadIdx.x & 63;
+  while (k0 < kend) {
+    // wave tile: consecutive whole blocks with at most 64 padded rows
+    const int kl = min(k0 + min(lane, 3), kend - 1);
+    const int mB = a.bpad[kl], mrow = a.blk_row[kl], mrow1 = a.blk_row[kl + 1];
+    const int64_t moff = a.map.off[kl];
+    const double msc = a.map.scale[kl];
+    const int mtag = a.map.tag[kl];
+    int nk = 0, cum = 0;
+    while (nk < 4 && k0 + nk < kend && cum + rl(mB, nk) <= kBWaveRows) {
+      cum += rl(mB, nk);
+      ++nk;
+    }
+    int row0 = 0, bsz = 0, li = -1, acc = 0;
+    for (int i = 0; i < nk; ++i) {
+      const int Bi = rl(mB, i);
+      if (lane >= acc && lane < acc + Bi) {
+        li = lane - acc;
+        row0 = rl(mrow, i);
+        bsz = rl(mrow1, i) - row0;
+      }
+      acc += Bi;
+    }
+    const bool real = li >= 0 && li < bsz;
+    const int64_t vb = v0 + (int64_t)(row0 + li - rs) * M;
+    double rv[kBCols];
+#pragma unroll
+    for (int c = 0; c < kBCols; ++c) rv[c] = 0.0;
+    if (real && UPD) {
+      double pv[kBCols], qv[kBCols], xv[kBCols];
+#pragma unroll
+      for (int c = 0; c < kBCols; ++c) {
+        if (c < M) {
+          pv[c] = a.p[vb + c];
+          qv[c] = a.q[vb + c];
+          xv[c] = a.x[vb + c];
+          rv[c] = a.r[vb + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kBCols; ++c) {
+        if (c < M) {
+          a.x[vb + c] = fma(alpha[c], pv[c], xv[c]);
+          rv[c] = fma(-alpha[c], qv[c], rv[c]);
+          a.r[vb + c] = rv[c];
+          rr[c] = fma(rv[c], rv[c], rr[c]);
+        }
+      }
+    } else if (real) {
+#pragma unroll
+      for (int c = 0; c < kBCols; ++c)
+        if (c < M) rv[c] = a.r[vb + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kBCols; ++c) {
+      r64[lane * kBCols + c] = rv[c];
+      r32[lane * kBCols + c] = __double2float_rn(rv[c]);
+    }
+    bwave_lds_sync();
+    int cb = 0;
+    for (int i = 0; i < nk; ++i) {
+      const int B = rl(mB, i);
+      const int prec = rl(mtag, i);
+      const uint8_t *blk = a.map.base + rl64(moff, i);
+      const double sc = bcast(msc, i);
+      for (int mt = 0; mt < B / 16; ++mt) {
+        const float *b32 = r32 + cb * kBCols;
+        const double *b64 = r64 + cb * kBCols;
+        double *zb = zt + cb * kBCols;
+        switch (B) {
+          case 16: bmtile_dispatch<16>(prec, blk, sc, mt, b32, b64, zb, lane); break;
+          case 32: bmtile_dispatch<32>(prec, blk, sc, mt, b32, b64, zb, lane); break;
+          case 48: bmtile_dispatch<48>(prec, blk, sc, mt, b32, b64, zb, lane); break;
+          default: bmtile_dispatch<64>(prec, blk, sc, mt, b32, b64, zb, lane); break;
+        }
+      }
+      cb += B;
+    }
+    bwave_lds_sync();
+    if (real) {
+#pragma unroll
+      for (int c = 0; c < kBCols; ++c) {
+        if (c < M) {
+          const double zv = zt[lane * kBCols + c];
+          a.z[vb + c] = zv;
+          rz[c] = fma(rv[c], zv, rz[c]);
+        }
+      }
+    }
+    bwave_lds_sync();
+    k0 += nk;
+  }
+}
+
+__device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M, float *r32, double *r64,
+                                             double *zt) {
+  const int lane = threadIdx.x & 63;
+  const int s = __builtin_amdgcn_readfirstlane(a.t.ach_sys[ch]);
+  const int c0 = a.t.sys_col[s];
+  double alpha[kBCols], rr[kBCols], rz[kBCols];
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) {
+    alpha[c] = c < M ? a.alpha[c0 + c] : 0.0;
+    rr[c] = rz[c] = 0.0;
+  }
+  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], M, alpha, r32, r64,
+                      zt, rr, rz);
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) {
+    const double t1 = wave_sum(rr[c]);
+    const double t2 = wave_sum(rz[c]);
+    if (lane == c) {
+      a.part[(int64_t)ch * 2 * kBCols + c] = t1;
+      a.part[(int64_t)ch * 2 * kBCols + kBCols + c] = t2;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void bapply_kernel(BApplyArgs a) {
+  __shared__ float r32s[4][kBWaveRows * kBCols];
+  __shared__ double r64s[4][kBWaveRows * kBCols];
+  __shared__ double zts[4][kBWaveRows * kBCols];
+  if (*a.n_active == 0) return;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = wave_slot(wv);
+  const int ce = a.sched[w + 1];
+  for (int ch = a.sched[w]; ch < ce; ++ch) {
+    const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ach_sys[ch]]);
+    bapply_chunk(a, ch, m, r32s[wv], r64s[wv], zts[wv]);
+  }
+}
+
+// Z = M^-1 R for one n x m block of columns (no PCG): one wave per wave tile
+// of the handle's partition, grid-stride.
+__global__ __launch_bounds__(256) void bapply_multi_kernel(BApplyArgs a, const int32_t *tile_blk, int ntiles,
+                                                           int m) {
+  __shared__ float r32s[4][kBWaveRows * kBCols];
+  __shared__ double r64s[4][kBWaveRows * kBCols];
+  __shared__ double zts[4][kBWaveRows * kBCols];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double alpha[kBCols], rr[kBCols], rz[kBCols];
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) alpha[c] = rr[c] = rz[c] = 0.0;
+  for (int t = blockIdx.x * 4 + wv; t < ntiles; t += gridDim.x * 4)
+    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, m, alpha, r32s[wv], r64s[wv], zts[wv], rr, rz);
+}
+
+// ------------------------------------------------------- per-system scalars
+__device__ __forceinline__ double wg_sum(double v, double *sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__device__ __forceinline__ void freeze(BState &st, int col, int status) {
+  st.status[col] = status;
+  st.alpha[col] = 0.0;
+  st.beta[col] = 0.0;
+  atomicSub(st.n_active, 1);
+}
+
+// After the SpMV: alpha = rho / (p, A p) for every running column of system s.
+// Other workgroups of the same launch decrement n_active, so the early-exit
+// test reads it once per workgroup and shares the value: every thread of the
+// workgroup then takes the same branch before the barriers of wg_sum.
+__device__ __forceinline__ bool wg_none_active(const int32_t *n_active, int *flag) {
+  if (threadIdx.x == 0) *flag = __hip_atomic_load(n_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  return *flag == 0;
+}
+
+__global__ __launch_bounds__(256) void breduce_pq_kernel(BTables t, BState st, const double *part) {
+  __shared__ double sh[4];
+  __shared__ int act;
+  if (wg_none_active(st.n_active, &act)) return;
+  const int s = blockIdx.x;
+  const int m = t.sys_m[s], c0 = t.sys_col[s];
+  const int cb = t.sys_ch[s], ce = t.sys_ch[s + 1];
+  for (int c = 0; c < m; ++c) {
+    double v = 0.0;
+    for (int ch = cb + (int)threadIdx.x; ch < ce; ch += 256) v += part[(int64_t)ch * kBCols + c];
+    const double pq = wg_sum(v, sh);
+    if (threadIdx.x == 0 && st.status[c0 + c] == BS_RUNNING) {
+      if (!(pq > 0.0)) freeze(st, c0 + c, BS_BREAKDOWN);
+      else st.alpha[c0 + c] = st.rho[c0 + c] / pq;
+    }
+  }
+}
+
+// After the update + apply: relres, convergence, beta, rho; init mode sets
+// ||r_0|| and rho from the first application.
+__global__ __launch_bounds__(256) void breduce_rz_kernel(BTables t, BState st, const double *part, int init) {
+  __shared__ double sh[4];
+  __shared__ int act;
+  if (wg_none_active(st.n_active, &act)) return;
+  const int s = blockIdx.x;
+  const int m = t.sys_m[s], c0 = t.sys_col[s];
+  const int cb = t.sys_ach[s], ce = t.sys_ach[s + 1];
+  for (int c = 0; c < m; ++c) {
+    double v1 = 0.0, v2 = 0.0;
+    for (int ch = cb + (int)threadIdx.x; ch < ce; ch += 256) {
+      v1 += part[(int64_t)ch * 2 * kBCols + c];
+      v2 += part[(int64_t)ch * 2 * kBCols + kBCols + c];
+    }
+    const double rr = wg_sum(v1, sh);
+    const double rz = wg_sum(v2, sh);
+    if (threadIdx.x != 0) continue;
+    const int col = c0 + c;
+    if (st.status[col] != BS_RUNNING) continue;
+    if (init) {
+      st.rnorm0[col] = sqrt(rr);
+      st.iter[col] = 0;
+      if (st.rnorm0[col] == 0.0) {
+        st.relres[col] = 0.0;
+        freeze(st, col, BS_CONVERGED);
+        continue;
+      }
+      if (!(rz > 0.0)) {
+        freeze(st, col, BS_BREAKDOWN);
+        continue;
+      }
+      st.rho[col] = rz;
+      st.beta[col] = 0.0;
+      continue;
+    }
+    st.iter[col] += 1;
+    st.relres[col] = sqrt(rr) / st.rnorm0[col];
+    if (st.relres[col] <= st.tol) {
+      freeze(st, col, BS_CONVERGED);
+    } else if (!(rz > 0.0)) {
+      freeze(st, col, BS_BREAKDOWN);
+    } else {
+      st.beta[col] = rz / st.rho[col];
+      st.rho[col] = rz;
+      if (st.iter[col] >= st.maxit) freeze(st, col, BS_MAXIT);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void binit_kernel(int64_t len, double *x, double *r, const double *b, double *p,
+                                                    double *q, int ncols, BState st) {
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+    x[i] = 0.0;
+    r[i] = b[i];
+    p[i] = 0.0;
+    q[i] = 0.0;
+  }
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < ncols; c += gridDim.x * 256) {
+    st.rho[c] = st.alpha[c] = st.beta[c] = st.rnorm0[c] = 0.0;
+    st.relres[c] = INFINITY;
+    st.iter[c] = 0;
+    st.status[c] = BS_RUNNING;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *st.n_active = ncols;
+}
+
+// ---------------------------------------------------------------- host side
+constexpr int kBMaxGrid = 2048;               // workgroups of a batched launch
+constexpr int kBMaxWaves = kBMaxGrid * 4;
+
+struct BPlan {
+  int32_t S = 0, ncols = 0;
+  int64_t veclen = 0;
+  std::vector<int32_t> sys_row, sys_m, sys_col, sys_ch, sys_ach, ch_row0, ch_sys, ach_blk, ach_sys;
+  std::vector<int64_t> sys_vec;
+  std::vector<double> ch_cost, ach_cost;      // modelled HBM bytes of each chunk
+};
+
+static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const int32_t *sys_row,
+                      const int32_t *sys_m, int chunk_rows, BPlan &pl) {
+  if (!M || S < 1 || !sys_row || !sys_m || sys_row[0] != 0 || sys_row[S] != M->n) return BJAC_EINVAL;
+  if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
+  pl.S = S;
+  pl.sys_row.assign(sys_row, sys_row + S + 1);
+  pl.sys_m.assign(sys_m, sys_m + S);
+  pl.sys_col.resize(S + 1);
+  pl.sys_vec.resize(S + 1);
+  pl.sys_col[0] = 0;
+  pl.sys_vec[0] = 0;
+  for (int s = 0; s < S; ++s) {
+    if (sys_row[s + 1] <= sys_row[s] || sys_m[s] < 1 || sys_m[s] > kBCols) return BJAC_EINVAL;
+    pl.sys_col[s + 1] = pl.sys_col[s] + sys_m[s];
+    pl.sys_vec[s + 1] = pl.sys_vec[s] + (int64_t)(sys_row[s + 1] - sys_row[s]) * sys_m[s];
+  }
+  pl.ncols = pl.sys_col[S];
+  pl.veclen = pl.sys_vec[S];
+  const double nnz_row = A && A->n > 0 ? (double)A->nnz / (double)A->n : 7.0;
+  // SpMV chunks: row ranges of at most chunk_rows inside one system
+  pl.sys_ch.assign(1, 0);
+  for (int s = 0; s < S; ++s) {
+    const int m = sys_m[s];
+    for (int r = sys_row[s]; r < sys_row[s + 1]; r += chunk_rows) {
+      const int rows = std::min(chunk_rows, sys_row[s + 1] - r);
+      pl.ch_row0.push_back(r);
+      pl.ch_sys.push_back(s);
+      pl.ch_cost.push_back(rows * (nnz_row * 12.0 + 32.0 * m) + 256.0);
+    }
+    pl.sys_ch.push_back((int32_t)pl.ch_sys.size());
+  }
+  pl.ch_row0.push_back(sys_row[S]);
+  // apply chunks: whole blocks, at most chunk_rows padded rows, one system
+  // each; every system boundary must be a block boundary
+  const std::vector<int32_t> &br = M->h_blk_row;
+  const std::vector<uint8_t> &tg = M->h_tag_lo;
+  pl.sys_ach.assign(1, 0);
+  int s = 0, rows = 0;
+  bool fresh = true;
+  for (int32_t k = 0; k < M->nb; ++k) {
+    while (br[k] >= sys_row[s + 1]) {
+      ++s;
+      fresh = true;
+      pl.sys_ach.push_back((int32_t)pl.ach_sys.size());
+    }
+    if (br[k + 1] > sys_row[s + 1]) return BJAC_EINVAL;  // block crosses systems
+    const int B = M->h_bpad[k];
+    if (fresh || rows + B > chunk_rows) {
+      pl.ach_blk.push_back(k);
+      pl.ach_sys.push_back(s);
+      pl.ach_cost.push_back(256.0);
+      rows = 0;
+      fresh = false;
+    }
+    rows += B;
+    const int pb = tg.empty() ? 8 : (tg[k] == 0 ? 8 : (tg[k] == 1 ? 4 : 2));
+    pl.ach_cost.back() += (double)B * B * pb + (br[k + 1] - br[k]) * 56.0 * sys_m[s];
+  }
+  while ((int)pl.sys_ach.size() < S + 1) pl.sys_ach.push_back((int32_t)pl.ach_sys.size());
+  pl.ach_blk.push_back(M->nb);
+  return BJAC_OK;
+}
+
+// Contiguous split of the chunks into W runs of about equal modelled cost.
+static void split_cost(const std::vector<double> &cost, int W, std::vector<int32_t> &out) {
+  const int n = (int)cost.size();
+  std::vector<double> pre(n + 1, 0.0);
+  for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + cost[i];
+  out.resize(W + 1);
+  int i = 0;
+  for (int w = 0; w <= W; ++w) {
+    const double goal = pre[n] * w / W;
+    while (i < n && pre[i] + 0.5 * cost[i] < goal) ++i;
+    out[w] = w == W ? n : i;
+  }
+}
+
+static int cu_count() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                               hipSuccess || cus < 1)
+      cus = 256;
+  }
+  return cus;
+}
+
+// workgroups for `units` chunks: a multiple of 8 (XCD-ordered wave slots), at
+// most wg_per_cu per compute unit, no more waves than chunks rounded up
+static int bgrid(int units, int wg_per_cu) {
+  int G = (units + 3) / 4;
+  G = std::min(G, wg_per_cu * cu_count());
+  G = std::min(G, kBMaxGrid);
+  G = (G + 7) & ~7;
+  return std::max(G, 8);
+}
+
+struct BWs {
+  double *r, *z, *pa, *pb, *q, *part1, *part2;
+  double *rho, *alpha, *beta, *rnorm0, *relres;
+  int32_t *iter, *status, *n_active;
+  int32_t *tabs;   // every int32 table, then both wave schedules
+  int64_t *sys_vec;
+  size_t bytes;
+};
+
+static size_t tabs_len(const BPlan &p) {
+  return p.sys_row.size() + p.sys_m.size() + p.sys_col.size() + p.sys_ch.size() + p.sys_ach.size() +
+         p.ch_row0.size() + p.ch_sys.size() + p.ach_blk.size() + p.ach_sys.size() + 2 * (kBMaxWaves + 1);
+}
+
+static BWs carve_b(void *ws, const BPlan &p) {
+  Carver c(ws);
+  BWs w{};
+  w.r = c.take<double>(p.veclen);
+  w.z = c.take<double>(p.veclen);
+  w.pa = c.take<double>(p.veclen);
+  w.pb = c.take<double>(p.veclen);
+  w.q = c.take<double>(p.veclen);
+  w.part1 = c.take<double>((size_t)p.ch_sys.size() * kBCols);
+  w.part2 = c.take<double>((size_t)p.ach_sys.size() * 2 * kBCols);
+  w.rho = c.take<double>(p.ncols);
+  w.alpha = c.take<double>(p.ncols);
+  w.beta = c.take<double>(p.ncols);
+  w.rnorm0 = c.take<double>(p.ncols);
+  w.relres = c.take<double>(p.ncols);
+  w.iter = c.take<int32_t>(p.ncols);
+  w.status = c.take<int32_t>(p.ncols);
+  w.n_active = c.take<int32_t>(1);
+  w.tabs = c.take<int32_t>(tabs_len(p));
+  w.sys_vec = c.take<int64_t>(p.sys_vec.size());
+  w.bytes = c.used;
+  return w;
+}
+
+// Everything one batched solve enqueues, built once per call.
+struct BCtx {
+  BPlan pl;
+  BWs w{};
+  BTables t{};
+  BState st{};
+  DevMap map{};
+  int G1 = 8, G2 = 8;
+  const int32_t *sched1 = nullptr, *sched2 = nullptr;
+  const bjac_csr *A = nullptr;
+  const bjac_handle *M = nullptr;
+  const double *b = nullptr;
+  double *x = nullptr;
+};
+
+static void cfg_defaults(const bjac_batch_cfg *cfg, int &chunk_rows, int &wg_per_cu) {
+  chunk_rows = cfg && cfg->chunk_rows > 0 ? cfg->chunk_rows : 1024;
+  wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 4;
+}
+
+static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
+                     const int32_t *sys_m, const double *b, double *x, double tol, int32_t maxit,
+                     const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes, hipStream_t s, BCtx &c) {
+  if (!A || !M || !b || !x || !workspace || b == x || A->n != M->n) return BJAC_EINVAL;
+  if (!(tol >= 0.0) || maxit < 1) return BJAC_EINVAL;
+  int chunk_rows, wg_per_cu;
+  cfg_defaults(cfg, chunk_rows, wg_per_cu);
+  if (wg_per_cu > 8) return BJAC_EINVAL;
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, c.pl);
+  if (rc) return rc;
+  c.w = carve_b(workspace, c.pl);
+  if (c.w.bytes > workspace_bytes) return BJAC_ENOMEM;
+  const BPlan &pl = c.pl;
+  c.G1 = bgrid((int)pl.ch_sys.size(), wg_per_cu);
+  c.G2 = bgrid((int)pl.ach_sys.size(), wg_per_cu);
+  std::vector<int32_t> sch1, sch2;
+  split_cost(pl.ch_cost, c.G1 * 4, sch1);
+  split_cost(pl.ach_cost, c.G2 * 4, sch2);
+  // tables, uploaded once per call
+  std::vector<int32_t> tabs;
+  tabs.reserve(tabs_len(pl));
+  auto put = [&](const std::vector<int32_t> &v) {
+    const size_t o = tabs.size();
+    tabs.insert(tabs.end(), v.begin(), v.end());
+    return o;
+  };
+  const size_t o_row = put(pl.sys_row), o_m = put(pl.sys_m), o_col = put(pl.sys_col), o_ch = put(pl.sys_ch),
+               o_ach = put(pl.sys_ach), o_chr = put(pl.ch_row0), o_chs = put(pl.ch_sys), o_ab = put(pl.ach_blk),
+               o_as = put(pl.ach_sys), o_s1 = put(sch1), o_s2 = put(sch2);
+  MPB_HIP(hipMemcpyAsync(c.w.tabs, tabs.data(), tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  MPB_HIP(hipMemcpyAsync(c.w.sys_vec, pl.sys_vec.data(), pl.sys_vec.size() * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
+  // the host vectors above go out of scope at return: wait for the copies
+  MPB_HIP(hipStreamSynchronize(s));
+  BTables &t = c.t;
+  t.S = pl.S;
+  t.nch = (int32_t)pl.ch_sys.size();
+  t.nach = (int32_t)pl.ach_sys.size();
+  t.sys_row = c.w.tabs + o_row;
+  t.sys_m = c.w.tabs + o_m;
+  t.sys_col = c.w.tabs + o_col;
+  t.sys_ch = c.w.tabs + o_ch;
+  t.sys_ach = c.w.tabs + o_ach;
+  t.ch_row0 = c.w.tabs + o_chr;
+  t.ch_sys = c.w.tabs + o_chs;
+  t.ach_blk = c.w.tabs + o_ab;
+  t.ach_sys = c.w.tabs + o_as;
+  t.sys_vec = c.w.sys_vec;
+  c.sched1 = c.w.tabs + o_s1;
+  c.sched2 = c.w.tabs + o_s2;
+  c.st = BState{c.w.rho, c.w.alpha, c.w.beta, c.w.rnorm0, c.w.relres, c.w.iter, c.w.status, c.w.n_active, tol, maxit};
+  c.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo};
+  c.A = A;
+  c.M = M;
+  c.b = b;
+  c.x = x;
+  return BJAC_OK;
+}
+
+static void benq_spmv(const BCtx &c, const double *pold, double *pnew, hipStream_t s) {
+  BSpmvArgs a{};
+  a.t = c.t;
+  a.rp = c.A->row_ptr;
+  a.ci = c.A->col_idx;
+  a.v = c.A->val;
+  a.z = c.w.z;
+  a.pold = pold;
+  a.pnew = pnew;
+  a.q = c.w.q;
+  a.beta = c.w.beta;
+  a.part = c.w.part1;
+  a.n_active = c.w.n_active;
+  a.sched = c.sched1;
+  hipLaunchKernelGGL(bspmv_kernel, dim3(c.G1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(breduce_pq_kernel, dim3(c.t.S), dim3(256), 0, s, c.t, c.st, (const double *)c.w.part1);
+}
+
+static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) {
+  BApplyArgs a{};
+  a.t = c.t;
+  a.blk_row = c.M->blk_row;
+  a.bpad = c.M->bpad;
+  a.map = c.map;
+  a.x = c.x;
+  a.r = c.w.r;
+  a.z = c.w.z;
+  a.p = p;
+  a.q = c.w.q;
+  a.alpha = c.w.alpha;
+  a.part = c.w.part2;
+  a.n_active = c.w.n_active;
+  a.sched = c.sched2;
+  hipLaunchKernelGGL(bapply_kernel, dim3(c.G2), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(breduce_rz_kernel, dim3(c.t.S), dim3(256), 0, s, c.t, c.st, (const double *)c.w.part2, init);
+}
+
+// x = 0, r = b, p = q = 0, then z_0 = M^-1 r_0 through the apply kernel with
+// alpha = 0, which also yields ||r_0|| and rho_0
+static void benq_init(const BCtx &c, hipStream_t s) {
+  hipLaunchKernelGGL(binit_kernel, dim3(1024), dim3(256), 0, s, c.pl.veclen, c.x, c.w.r, c.b, c.w.pa, c.w.q,
+                     c.pl.ncols, c.st);
+  benq_apply(c, c.w.pa, 1, s);
+}
+
+// iteration j reads p from one buffer and writes the other
+static void benq_iter(const BCtx &c, int j, hipStream_t s) {
+  const bool even = (j & 1) == 0;
+  benq_spmv(c, even ? c.w.pa : c.w.pb, even ? c.w.pb : c.w.pa, s);
+  benq_apply(c, even ? c.w.pb : c.w.pa, 0, s);
+}
+
+}  // namespace mpb
+
+using namespace mpb;
+
+extern "C" int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t nsys,
+                                           const int32_t *sys_row, const int32_t *sys_m,
+                                           const bjac_batch_cfg *cfg, size_t *workspace_bytes) {
+  if (!workspace_bytes || !A) return BJAC_EINVAL;
+  int chunk_rows, wg_per_cu;
+  cfg_defaults(cfg, chunk_rows, wg_per_cu);
+  BPlan p;
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, p);
+  if (rc) return rc;
+  *workspace_bytes = carve_b(nullptr, p).bytes;
+  return BJAC_OK;
+}
+
+extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
+                                 const int32_t *sys_m, const double *b, double *x, const bjac_solve_opts *opts,
+                                 const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes,
+                                 int32_t *col_iters, int32_t *col_status, double *col_relres, bjac_stats *stats,
+                                 void *stream) {
+  if (!opts) return BJAC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  BCtx c;
+  int rc = bctx_make(A, M, nsys, sys_row, sys_m, b, x, opts->tol, opts->maxit, cfg, workspace, workspace_bytes, s, c);
+  if (rc) return rc;
+  int chunk = opts->chunk > 0 ? opts->chunk : 16;
+  chunk += chunk & 1;  // an even count keeps the p ping-pong in step across launches
+
+  hipEvent_t e0, e1;
+  MPB_HIP(hipEventCreate(&e0));
+  MPB_HIP(hipEventCreate(&e1));
+  MPB_HIP(hipEventRecord(e0, s));
+  benq_init(c, s);
+  MPB_HIP(hipGetLastError());
+
+  // capture `chunk` iterations once; kernels return at once when no column
+  // is running, so replays past convergence cost only their launches
+  hipStream_t cs = nullptr;
+  MPB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    return BJAC_EHIP;
+  }
+  for (int i = 0; i < chunk; ++i) benq_iter(c, i, cs);
+  hipError_t ce = hipStreamEndCapture(cs, &g);
+  if (ce == hipSuccess) ce = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (ce != hipSuccess) return BJAC_EHIP;
+
+  int32_t *active = nullptr;
+  MPB_HIP(hipHostMalloc((void **)&active, sizeof(int32_t), hipHostMallocDefault));
+  int launches = 0;
+  const int max_launches = opts->maxit / chunk + 2;
+  hipError_t le = hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (le == hipSuccess) le = hipStreamSynchronize(s);
+  while (le == hipSuccess && *active > 0 && launches < max_launches) {
+    le = hipGraphLaunch(ge, s);
+    ++launches;
+    if (le == hipSuccess) le = hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (le == hipSuccess) le = hipStreamSynchronize(s);
+  }
+  (void)hipGraphExecDestroy(ge);
+  (void)hipHostFree(active);
+  if (le != hipSuccess) return BJAC_EHIP;
+  MPB_HIP(hipEventRecord(e1, s));
+  MPB_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+
+  const int nc = c.pl.ncols;
+  std::vector<int32_t> its(nc), sts(nc);
+  std::vector<double> rel(nc);
+  MPB_HIP(hipMemcpyAsync(its.data(), c.w.iter, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipMemcpyAsync(sts.data(), c.w.status, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipMemcpyAsync(rel.data(), c.w.relres, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipStreamSynchronize(s));
+  int worst = BJAC_OK, maxits = 0;
+  for (int i = 0; i < nc; ++i) {
+    const int code = sts[i] == BS_CONVERGED ? BJAC_OK
+                     : sts[i] == BS_BREAKDOWN ? BJAC_EBREAKDOWN
+                                              : BJAC_NOT_CONVERGED;
+    if (code == BJAC_EBREAKDOWN || (code == BJAC_NOT_CONVERGED && worst == BJAC_OK)) worst = code;
+    if (col_iters) col_iters[i] = its[i];
+    if (col_status) col_status[i] = code;
+    if (col_relres) col_relres[i] = rel[i];
+    maxits = std::max(maxits, its[i]);
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = maxits;
+    stats->status = worst;
+    stats->graph_launches = launches;
+    stats->solve_ms = ms;
+    stats->relres = 0.0;
+    for (int i = 0; i < nc; ++i) stats->relres = std::max(stats->relres, rel[i]);
+  }
+  return worst;
+}
+
+extern "C" int pcg_batched_tune(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
+                                const int32_t *sys_m, const double *b, double *x, const bjac_batch_cfg *cands,
+                                int32_t ncand, int32_t iters, void *workspace, size_t workspace_bytes,
+                                float *ms_per_iter, int32_t *best, void *stream) {
+  if (!cands || ncand < 1 || iters < 1 || !best) return BJAC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  MPB_HIP(hipEventCreate(&e0));
+  MPB_HIP(hipEventCreate(&e1));
+  int bi = -1;
+  float bms = 0.f;
+  int rc = BJAC_OK;
+  for (int k = 0; k < ncand && rc == BJAC_OK; ++k) {
+    BCtx c;
+    // tol = 0: no column stops during the timed iterations
+    rc = bctx_make(A, M, nsys, sys_row, sys_m, b, x, 0.0, 1 << 30, &cands[k], workspace, workspace_bytes, s, c);
+    if (rc) break;
+    benq_init(c, s);
+    benq_iter(c, 0, s);
+    if (hipEventRecord(e0, s) != hipSuccess) rc = BJAC_EHIP;
+    for (int j = 1; j <= iters && rc == BJAC_OK; ++j) benq_iter(c, j, s);
+    if (rc == BJAC_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                          hipEventSynchronize(e1) != hipSuccess))
+      rc = BJAC_EHIP;
+    float ms = 0.f;
+    if (rc == BJAC_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)iters;
+    if (ms_per_iter) ms_per_iter[k] = ms;
+    if (rc == BJAC_OK && (bi < 0 || ms < bms)) {
+      bi = k;
+      bms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = bi;
+  return BJAC_OK;
+}
+
+extern "C" int bjac_apply_multi(const bjac_handle *M, const double *R, double *Z, int32_t m, void *stream) {
+  if (!M || !R || !Z || R == Z || m < 1 || m > kBCols) return BJAC_EINVAL;
+  BApplyArgs a{};
+  a.blk_row = M->blk_row;
+  a.bpad = M->bpad;
+  a.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo};
+  a.r = const_cast<double *>(R);  // read only in this mode
+  a.z = Z;
+  const int G = std::max(1, std::min((M->ntiles + 3) / 4, 4 * cu_count()));
+  hipLaunchKernelGGL(bapply_multi_kernel, dim3(G), dim3(256), 0, (hipStream_t)stream, a,
+                     (const int32_t *)M->tile_blk, M->ntiles, (int)m);
+  MPB_HIP(hipGetLastError());
+  return BJAC_OK;
+}

@@ -56,32 +56,42 @@ def _csr_from_coo(n, rows, cols, vals) -> CSR:
 
 def diffusion3d(kappa: np.ndarray, aniso=(1.0, 1.0, 1.0)) -> CSR:
     """7-point matrix for -div(K grad u) with point coefficients ``kappa``
-    (shape (nz, ny, nx)) and K = diag(aniso) * kappa."""
+    (shape (nz, ny, nx)) and K = diag(aniso) * kappa. Assembled row by row in
+    column order (-z, -y, -x, centre, +x, +y, +z), so the CSR needs no sort."""
     kappa = np.asarray(kappa, dtype=np.float64)
     nz, ny, nx = kappa.shape
     n = nx * ny * nz
+    if 7 * n >= 2**31:
+        raise ValueError("matrix too large for int32 CSR")
     idx = np.arange(n, dtype=np.int64).reshape(nz, ny, nx)
     diag = np.zeros((nz, ny, nx))
-    rows, cols, vals = [], [], []
-    for axis, a in zip((2, 1, 0), aniso):  # x, y, z
+    cols = np.full((nz, ny, nx, 7), -1, dtype=np.int64)
+    vals = np.zeros((nz, ny, nx, 7))
+    # slot of the lower / upper neighbour along x, y, z in the row order above
+    for axis, a, (slo, shi) in zip((2, 1, 0), aniso, ((2, 4), (1, 5), (0, 6))):
         k0 = np.moveaxis(kappa, axis, 0)
         i0 = np.moveaxis(idx, axis, 0)
         d0 = np.moveaxis(diag, axis, 0)
+        c0 = np.moveaxis(cols, axis, 0)
+        v0 = np.moveaxis(vals, axis, 0)
         lo, hi = k0[:-1], k0[1:]
         face = a * (2.0 * lo * hi / (lo + hi))          # interior faces
         d0[:-1] += face
         d0[1:] += face
         d0[0] += a * k0[0]                               # Dirichlet faces
         d0[-1] += a * k0[-1]
-        il, ih = i0[:-1].ravel(), i0[1:].ravel()
-        f = face.ravel()
-        rows += [il, ih]
-        cols += [ih, il]
-        vals += [-f, -f]
-    rows.append(idx.ravel())
-    cols.append(idx.ravel())
-    vals.append(diag.ravel())
-    A = _csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+        c0[:-1, ..., shi] = i0[1:]                       # row at lower point -> upper neighbour
+        v0[:-1, ..., shi] = -face
+        c0[1:, ..., slo] = i0[:-1]
+        v0[1:, ..., slo] = -face
+    cols[..., 3] = idx
+    vals[..., 3] = diag
+    cols = cols.reshape(n, 7)
+    vals = vals.reshape(n, 7)
+    keep = cols >= 0
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(keep.sum(axis=1), out=row_ptr[1:])
+    A = CSR(n, row_ptr.astype(np.int32), cols[keep].astype(np.int32), vals[keep])
     A.meta.update(shape=(nz, ny, nx), aniso=tuple(float(a) for a in aniso))
     return A
 
@@ -254,3 +264,39 @@ def spd_exact_inverse_blocks(nb: int, b: int, rng) -> CSR:
         vals += [d, off, off]
     A = _csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
     return A
+
+
+@dataclass
+class StackedBatch:
+    """Independent systems stacked into one block-diagonal CSR: system s owns
+    rows sys_row[s] .. sys_row[s+1]-1; its block partition is shifted by
+    sys_row[s]; b is system-major, row-major (rows_s, m_s) per system."""
+    A: CSR
+    block_ptr: np.ndarray
+    sys_row: np.ndarray
+    sys_m: np.ndarray
+    b: np.ndarray
+
+    def system_slice(self, s: int) -> slice:
+        off = int(np.sum(np.diff(self.sys_row[:s + 1]).astype(np.int64) * self.sys_m[:s]))
+        return slice(off, off + int(self.sys_row[s + 1] - self.sys_row[s]) * int(self.sys_m[s]))
+
+
+def stack_batch(systems: list) -> StackedBatch:
+    sizes = np.array([bs.A.n for bs in systems], dtype=np.int64)
+    sys_row = np.zeros(len(systems) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=sys_row[1:])
+    nnz = np.array([bs.A.nnz for bs in systems], dtype=np.int64)
+    if sys_row[-1] >= 2**31 or nnz.sum() >= 2**31:
+        raise ValueError("batch too large for int32 CSR")
+    nnz_off = np.concatenate([[0], np.cumsum(nnz)])
+    row_ptr = np.concatenate([bs.A.row_ptr[:-1].astype(np.int64) + nnz_off[i] for i, bs in enumerate(systems)]
+                             + [[nnz_off[-1]]])
+    col_idx = np.concatenate([bs.A.col_idx.astype(np.int64) + sys_row[i] for i, bs in enumerate(systems)])
+    val = np.concatenate([bs.A.val for bs in systems])
+    bp = np.concatenate([bs.block_ptr[:-1].astype(np.int64) + sys_row[i] for i, bs in enumerate(systems)]
+                        + [[sys_row[-1]]])
+    sys_m = np.array([bs.B.shape[1] for bs in systems], dtype=np.int32)
+    b = np.concatenate([np.ascontiguousarray(bs.B).ravel() for bs in systems])
+    A = CSR(int(sys_row[-1]), row_ptr.astype(np.int32), col_idx.astype(np.int32), val)
+    return StackedBatch(A, bp.astype(np.int32), sys_row.astype(np.int32), sys_m, b)
