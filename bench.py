@@ -13,7 +13,17 @@ pass times each kernel with HIP events on the stream it runs on and reports
 the dominant kernel against the 8 TB/s HBM roofline. The CPU oracle is timed
 on a bounded sample on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Other workloads (each prints its own line of the same form):
+  --workload batched   256 independent 7-point systems, edges U{32..96},
+                       1-8 right-hand sides each, blocks from {16,32,48,64};
+                       FP16 block storage vs FP64, autotuned launch shape
+  --workload aniso     160^3 anisotropic (1e3) diffusion with 1e4 jumps on
+                       16 random subcubes, blocks of 48: per-block rule vs
+                       FP16 and FP64 storage
+  --workload selector  192^3 held-out anisotropic jump problem: learned
+                       selector (trained first, untimed) vs rule vs FP64
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W]
 """
 from __future__ import annotations
 
@@ -73,21 +83,10 @@ def cpu_baseline(p, iters_hint, budget_iters=8):
                       f"scaled to {iters_hint} iterations"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--N", type=int, default=128)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="also run one 1 GiB device-to-device copy (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP64"
 
+
+def bench_diff3d(args):
     import numpy as np
     import torch
 
@@ -176,7 +175,7 @@ def main():
         cpu = cpu_baseline(p, r16.iters)
 
     line = {
-        "metric": "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP64",
+        "metric": METRIC,
         "value": ms16, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms16, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "apply_arith": "fp16-stored block inverses, f32 accumulation", "data": "synthetic",
@@ -191,6 +190,309 @@ def main():
         "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
         "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
     }
+    return line
+
+
+
+# ------------------------------------------------------------- batched solves
+def batched_spmv_bytes(n, nnz, veclen):
+    """One batched SpMV launch: CSR once, and per (row, column) z and p_old
+    read, p_new and q written."""
+    return 12 * nnz + 4 * (n + 1) + 32 * veclen
+
+
+def batched_apply_bytes(nb, stored_bytes, veclen):
+    """One batched update + apply launch: stored inverses and block metadata
+    once, and per (row, column) x, r read and written, p, q read, z written."""
+    return stored_bytes + 21 * nb + 56 * veclen
+
+
+def cpu_baseline_batched(st, col_iters, nsample=2, budget_iters=8):
+    """Oracle on the first ``nsample`` systems: block setup (FP16 storage) and
+    a few PCG iterations of every column; scaled by rows (setup) and by
+    rows x iterations summed over every column of the batch (solve)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pcg as OP
+    from oracle import precision as OPr
+    from paper_2407_15973_amd import gen
+    rows_s = np.diff(st.sys_row).astype(np.int64)
+    t_setup = t_iter = 0.0
+    row_sample = row_iter_sample = 0
+    with threadpool_limits(limits=1):
+        for s in range(nsample):
+            r0, r1 = int(st.sys_row[s]), int(st.sys_row[s + 1])
+            k0, k1 = (int(np.searchsorted(st.block_ptr, v)) for v in (r0, r1))
+            bp = (st.block_ptr[k0:k1 + 1] - r0).astype(np.int32)
+            a, b = int(st.A.row_ptr[r0]), int(st.A.row_ptr[r1])
+            sub = gen.CSR(r1 - r0, (st.A.row_ptr[r0:r1 + 1] - a).astype(np.int32),
+                          (st.A.col_idx[a:b] - r0).astype(np.int32), st.A.val[a:b])
+            t0 = time.perf_counter()
+            M = OP.BJAC(sub, bp, np.full(len(bp) - 1, OPr.FP16, np.uint8))
+            t1 = time.perf_counter()
+            S = sub.to_scipy()
+            m = int(st.sys_m[s])
+            B = st.b[st.system_slice(s)].reshape(r1 - r0, m)
+            its = 0
+            for c in range(m):
+                its += OP.pcg(lambda v: S @ v, B[:, c], M.low, 0.0, budget_iters).iters
+            t2 = time.perf_counter()
+            t_setup += t1 - t0
+            t_iter += t2 - t1
+            row_sample += r1 - r0
+            row_iter_sample += (r1 - r0) * its
+    col_rows = np.repeat(rows_s, st.sys_m)
+    total_row_iters = float(np.sum(col_rows * np.asarray(col_iters, dtype=np.int64)))
+    est = t_setup / row_sample * rows_s.sum() + t_iter / row_iter_sample * total_row_iters
+    return {"value": est * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup + {budget_iters} PCG iterations per column on the first {nsample} systems "
+                      f"({row_sample} rows, {t_setup + t_iter:.1f} s), scaled by rows (setup) and by "
+                      f"rows x iterations of every column (solve)"}
+
+
+def bench_batched(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import autotune
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    log(f"building the batch ({args.nsys} systems)")
+    st = gen.stack_batch(gen.config4(seed=0, nsys=args.nsys))
+    n, nnz, nb = st.A.n, st.A.nnz, len(st.block_ptr) - 1
+    veclen = int(st.b.size)
+    log(f"n = {n}, nnz = {nnz}, blocks = {nb}, columns = {int(st.sys_m.sum())}, vector entries = {veclen}")
+    A = mb.DeviceCSR(st.A, dev)
+    b = torch.as_tensor(st.b, device=dev)
+    tol, maxit = 1e-10, 5000
+    pol16 = mb.Policy(mode=mb.FIXED, low=mb.FP16)
+    pol64 = mb.Policy(mode=mb.UNIFORM)
+    M0 = mb.BlockJacobi(A, st.block_ptr, pol16)
+    bs = mb.BatchSolver(A, M0, st.sys_row, st.sys_m)
+    log("autotuning the launch shape")
+    cfg, entry = autotune.tuned_cfg(bs, b)
+    log(f"tuned (chunk_rows, wg_per_cu, spmv_ilp, apply_rows) = {cfg}: {entry['ms_per_iter']}")
+    del M0
+
+    def step(policy, profile=False):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        M = mb.BlockJacobi(A, st.block_ptr, policy)
+        e1.record()
+        bs.M = M
+        res = bs.solve(b, tol=tol, maxit=maxit, cfg=cfg, profile=profile)
+        e2.record()
+        return M, res, (e0, e1, e2)
+
+    def timed(policy, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [step(policy) for _ in range(k)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        setup = [r[2][0].elapsed_time(r[2][1]) for r in runs]
+        solve = [r[2][1].elapsed_time(r[2][2]) for r in runs]
+        return (t1 - t0) * 1e3 / k, float(np.median(setup)), float(np.median(solve)), runs[-1]
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        step(pol16)
+    log(f"timing {args.steps} steps, FP16 block storage")
+    ms16, setup16, solve16, (M16, r16, _) = timed(pol16, args.steps)
+    log(f"fp16: {ms16:.1f} ms/step (max {r16.iters} iterations)")
+    log(f"timing {args.steps} steps, FP64 block storage")
+    ms64, setup64, solve64, (M64, r64, _) = timed(pol64, args.steps)
+    log(f"fp64: {ms64:.1f} ms/step (max {r64.iters} iterations)")
+
+    # FP64 check of the returned solutions on a sample of systems
+    x16 = r16.x.cpu().numpy()
+    worst = 0.0
+    for s in range(0, len(st.sys_m), max(1, len(st.sys_m) // 16)):
+        r0, r1 = int(st.sys_row[s]), int(st.sys_row[s + 1])
+        a, bb = int(st.A.row_ptr[r0]), int(st.A.row_ptr[r1])
+        sub = gen.CSR(r1 - r0, (st.A.row_ptr[r0:r1 + 1] - a).astype(np.int32),
+                      (st.A.col_idx[a:bb] - r0).astype(np.int32), st.A.val[a:bb]).to_scipy()
+        m = int(st.sys_m[s])
+        X = x16[st.system_slice(s)].reshape(r1 - r0, m)
+        B = st.b[st.system_slice(s)].reshape(r1 - r0, m)
+        worst = max(worst, float(np.max(np.linalg.norm(B - sub @ X, axis=0) / np.linalg.norm(B, axis=0))))
+
+    log("profile pass")
+    _, rp16, _ = step(pol16, profile=True)
+    info16 = M16.info()
+    kb = {"spmv": batched_spmv_bytes(n, nnz, veclen), "apply": batched_apply_bytes(nb, info16["low_bytes"], veclen)}
+    kern = {}
+    for name in ("spmv", "apply"):
+        tot, cnt = rp16.kernel_ms[name]
+        avg_ms = tot / max(1, cnt)
+        kern[name] = {"launches": cnt, "avg_us": avg_ms * 1e3, "bytes": kb[name],
+                      "gbs": kb[name] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
+    tot, cnt = rp16.kernel_ms["reduce"]
+    kern["reduce"] = {"launches": cnt, "avg_us": tot / max(1, cnt) * 1e3}
+    dom = max(("spmv", "apply"), key=lambda k: kern[k]["avg_us"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "bspmv_kernel" if dom == "spmv" else "bapply_kernel",
+                "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
+    iter_bytes = kb["spmv"] + kb["apply"]
+    pair_gbs = iter_bytes / ((kern["spmv"]["avg_us"] + kern["apply"]["avg_us"]) * 1e-6) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline_batched(st, r16.col_iters)
+    return {
+        "metric": METRIC, "value": ms16, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms16, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "apply_arith": "fp16-stored block inverses, f32 matrix-core products", "data": "synthetic",
+        "config": {"workload": f"batched_{len(st.sys_m)}sys_diff3d_edges32-96_rhs1-8", "n": n, "nnz": nnz,
+                   "blocks": nb, "columns": int(st.sys_m.sum()), "vector_entries": veclen,
+                   "block_rows": "U{16,32,48,64}", "precision_map": "fp16 fixed", "tol": tol, "seed": 0,
+                   "tuned": dict(zip(("chunk_rows", "wg_per_cu", "spmv_ilp", "apply_rows"), cfg))},
+        "iters_max": r16.iters, "iters_mean": float(np.mean(r16.col_iters)),
+        "iters_fp64_max": r64.iters, "iters_fp64_mean": float(np.mean(r64.col_iters)),
+        "status": r16.status, "status_fp64": r64.status,
+        "setup_ms": setup16, "solve_ms": solve16, "fp64_ms_per_step": ms64, "fp64_setup_ms": setup64,
+        "fp64_solve_ms": solve64, "speedup_vs_fp64": ms64 / ms16, "true_relres_sampled_max": worst,
+        "bytes_per_iter": iter_bytes, "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
+        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
+        "autotune_ms_per_iter": entry["ms_per_iter"],
+    }
+
+
+# ------------------------------------------- per-block rule / learned selector
+def train_selector(dev):
+    """Selector trained on labels the solver generates on the 2D Poisson and
+    3D log-uniform families (seeds 0-1, 32^3 grids at contrasts 2 and 0)."""
+    import numpy as np
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+    from paper_2407_15973_amd import selector as sel
+    train = [gen.config1(s) for s in range(2)]
+    train += [gen.config2(seed=s, N=32, contrast=c) for c in (2.0, 0.0) for s in range(2)]
+    F, Y = [], []
+    for p in train:
+        ls = sel.make_labels(mb.DeviceCSR(p.A, dev), p.block_ptr, p.b, tol=p.tol, maxit=p.maxit)
+        F.append(ls.features)
+        Y.append(ls.labels)
+    return sel.train(np.concatenate(F), np.concatenate(Y), steps=300, lr=3e-3)
+
+
+def bench_policies(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    selector_mode = args.workload == "selector"
+    log("building the workload")
+    p = gen.config5_eval(seed=100, N=args.N) if selector_mode else gen.config3(seed=0, N=args.N)
+    n, nnz, nb = p.A.n, p.A.nnz, len(p.block_ptr) - 1
+    A = mb.DeviceCSR(p.A, dev)
+    b = torch.as_tensor(p.b, device=dev)
+    solver = mb.Solver(n, dev)
+    pols = {"fp64": mb.Policy(mode=mb.UNIFORM), "fp16": mb.Policy(mode=mb.FIXED, low=mb.FP16),
+            "rule": mb.Policy(mode=mb.RULE)}
+    head = "rule"
+    if selector_mode:
+        log("training the selector (untimed)")
+        s = train_selector(dev)
+        pols = {"fp64": pols["fp64"], "rule": pols["rule"], "learned": mb.Policy(mode=mb.LEARNED, mlp_blob=s.blob)}
+        head = "learned"
+
+    def step(policy, profile=False):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        M = mb.BlockJacobi(A, p.block_ptr, policy)
+        e1.record()
+        res = solver.solve(A, M, b, tol=p.tol, maxit=p.maxit, profile=profile)
+        e2.record()
+        return M, res, (e0, e1, e2)
+
+    rows = {}
+    for name, pol in pols.items():
+        for _ in range(args.warmup):
+            step(pol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [step(pol) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        M, res, ev = runs[-1]
+        info = M.info()
+        rows[name] = {"ms_per_step": ms, "iters": res.iters, "status": res.status,
+                      "setup_ms": float(np.median([r[2][0].elapsed_time(r[2][1]) for r in runs])),
+                      "solve_ms": float(np.median([r[2][1].elapsed_time(r[2][2]) for r in runs])),
+                      "blocks_per_prec": info["blocks_per_prec"], "low_bytes": info["low_bytes"],
+                      "x": res.x}
+        log(f"{name}: {ms:.1f} ms/step, {res.iters} iterations, map {info['blocks_per_prec']}")
+    S = p.A.to_scipy()
+    bn = float(np.linalg.norm(p.b))
+    for r in rows.values():
+        r["true_relres"] = float(np.linalg.norm(p.b - S @ r.pop("x").cpu().numpy()) / bn)
+
+    log("profile pass")
+    M, rp, _ = step(pols[head], profile=True)
+    info = M.info()
+    kb = {"spmv": spmv_bytes(n, nnz), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
+    kern = {}
+    for name in ("spmv", "apply"):
+        tot, cnt = rp.kernel_ms[name]
+        avg_ms = tot / max(1, cnt)
+        kern[name] = {"launches": cnt, "avg_us": avg_ms * 1e3, "bytes": kb[name],
+                      "gbs": kb[name] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": f"{dom}_kernel",
+                "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(p, rows[head]["iters"])
+    hv = rows[head]
+    return {
+        "metric": METRIC, "value": hv["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "apply_arith": "per-block FP64/FP32/FP16 storage, f32 accumulation for reduced blocks",
+        "config": {"workload": f"{p.name}", "n": n, "nnz": nnz, "blocks": nb, "block_rows": 48,
+                   "precision_map": head, "tol": p.tol, "seed": 100 if selector_mode else 0},
+        "policies": rows, "speedup_vs_fp64": rows["fp64"]["ms_per_step"] / hv["ms_per_step"],
+        "delay_iters": hv["iters"] - rows["fp64"]["iters"],
+        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
+    }
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--N", type=int, default=None, help="grid edge (diff3d 128, aniso 160, selector 192)")
+    ap.add_argument("--workload", default="diff3d", choices=("diff3d", "batched", "aniso", "selector"))
+    ap.add_argument("--nsys", type=int, default=256, help="batched: number of systems")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design for sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "diff3d":
+        args.N = args.N or 128
+        line = bench_diff3d(args)
+    elif args.workload == "batched":
+        line = bench_batched(args)
+    else:
+        args.N = args.N or (160 if args.workload == "aniso" else 192)
+        line = bench_policies(args)
     print(json.dumps(line), flush=True)
 
 

@@ -219,12 +219,18 @@ int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *
  * values of one row are contiguous). col_iters, col_status, col_relres: HOST
  * arrays of sum_s m_s entries (may be NULL), column order = system order,
  * then column. opts: tol, maxit, chunk (iterations per captured graph) are
- * used; relres_hist, high_hist and profile are ignored. */
+ * used, and profile (eager launches, kernel times in stats->spmv_ms,
+ * apply_ms and update_ms = the per-system reductions); relres_hist and
+ * high_hist are ignored. */
 typedef struct {
-  int32_t chunk_rows;   /* rows per SpMV chunk and padded rows per apply chunk
-                           (>= 64; 0 = 1024). Chunks never cross systems.     */
+  int32_t chunk_rows;   /* rows per matrix-vector chunk (>= 64; 0 = 128)      */
   int32_t wg_per_cu;    /* workgroups of 256 threads per compute unit in the
-                           persistent launches (1..8; 0 = 4)                  */
+                           persistent launches (1..32; 0 = 8; the matrix-
+                           vector launch is also capped at what is resident) */
+  int32_t spmv_ilp;     /* matrix-vector elements per lane in flight (1 or 2;
+                           0 = 2)                                             */
+  int32_t apply_rows;   /* padded rows per apply chunk (>= 64; 0 = 1024).
+                           Chunks never cross systems.                        */
 } bjac_batch_cfg;
 
 int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t nsys,

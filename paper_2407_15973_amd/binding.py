@@ -66,7 +66,8 @@ class bjac_stats(C.Structure):
 
 
 class bjac_batch_cfg(C.Structure):
-    _fields_ = [("chunk_rows", C.c_int32), ("wg_per_cu", C.c_int32)]
+    _fields_ = [("chunk_rows", C.c_int32), ("wg_per_cu", C.c_int32), ("spmv_ilp", C.c_int32),
+                ("apply_rows", C.c_int32)]
 
 
 _lib = None
@@ -358,6 +359,7 @@ class BatchResult:
     iters: int
     graph_launches: int
     solve_ms: float
+    kernel_ms: dict = None        # profile mode: {"spmv": (total_ms, launches), ...}
 
 
 class BatchSolver:
@@ -387,7 +389,7 @@ class BatchSolver:
         if self.ws is None or self.ws.numel() < nbytes:
             self.ws = _torch().empty(max(1, nbytes), dtype=_torch().uint8, device=self.A.val.device)
 
-    def solve(self, b, tol=1e-10, maxit=5000, chunk=16, cfg=(0, 0), x=None) -> BatchResult:
+    def solve(self, b, tol=1e-10, maxit=5000, chunk=16, cfg=(0, 0, 0, 0), x=None, profile=False) -> BatchResult:
         torch = _torch()
         c = bjac_batch_cfg(*cfg)
         self._ensure(self._query(c))
@@ -395,7 +397,7 @@ class BatchSolver:
         its = np.zeros(self.ncols, dtype=np.int32)
         sts = np.zeros(self.ncols, dtype=np.int32)
         rel = np.zeros(self.ncols, dtype=np.float64)
-        opts = bjac_solve_opts(tol, maxit, chunk, None, None, 0, 0)
+        opts = bjac_solve_opts(tol, maxit, chunk, None, None, 1 if profile else 0, 0)
         st = bjac_stats()
         rc = load().pcg_solve_batched(C.byref(self.A.c), self.M.h, self.nsys, self.sys_row.ctypes.data,
                                       self.sys_m.ctypes.data, _ptr(b), _ptr(x), C.byref(opts), C.byref(c),
@@ -403,10 +405,14 @@ class BatchSolver:
                                       rel.ctypes.data, C.byref(st), _stream())
         if rc < 0 and rc != EBREAKDOWN:
             raise MpbjacError(rc, "pcg_solve_batched")
-        return BatchResult(x, its, sts, rel, rc, st.iters, st.graph_launches, st.solve_ms)
+        res = BatchResult(x, its, sts, rel, rc, st.iters, st.graph_launches, st.solve_ms)
+        if profile:
+            res.kernel_ms = {"spmv": (st.spmv_ms, st.n_spmv), "apply": (st.apply_ms, st.n_apply),
+                             "reduce": (st.update_ms, st.n_update)}
+        return res
 
     def tune(self, b, cands, iters=8):
-        """Times ``iters`` iterations under each (chunk_rows, wg_per_cu) pair;
+        """Times ``iters`` iterations under each (chunk_rows, wg_per_cu[, spmv_ilp[, apply_rows]]);
         returns (best index, ms per iteration of every candidate)."""
         torch = _torch()
         arr = (bjac_batch_cfg * len(cands))(*[bjac_batch_cfg(*c) for c in cands])

@@ -64,6 +64,7 @@ __device__ __forceinline__ int wave_slot(int wv) {
 
 // ------------------------------------------------------------------ SpMV
 struct BSpmvArgs {
+  int ilp;               // elements per lane in flight (1 or 2)
   BTables t;
   const int32_t *rp, *ci;
   const double *v;
@@ -75,134 +76,168 @@ struct BSpmvArgs {
   const int32_t *sched;   // [waves + 1] first chunk of each wave slot
 };
 
-// One 64-row tile of a system with M columns: q = A p_new, p_new = z + beta p_old
-// formed at every read; returns the per-column (p_new, q) contributions.
-template <int M>
-__device__ __forceinline__ void bspmv_tile(const BSpmvArgs &a, const double (&beta)[kBCols], int rs, int nrows,
-                                           int64_t v0, int r0, int r1, double *sv, int *sc, double (&pq)[kBCols]) {
-  constexpr int CAP = kSpmvNnzCap;
-  constexpr int NL = CAP / 64;
-  const int lane = threadIdx.x & 63;
-  const int row = r0 + lane;
-  const bool has = row < r1;
-  const int rowc = min(row, r1 - 1);
-  const int s = a.rp[rowc], e = a.rp[rowc + 1];
-  const int e0 = __builtin_amdgcn_readfirstlane(a.rp[r0]);
-  const int cnt = __builtin_amdgcn_readfirstlane(a.rp[r1]) - e0;
-  const int len = has ? e - s : 0;
-  const bool staged = cnt > 0 && cnt <= CAP;
-  if (staged) {
-    double vv[NL];
-    int cc[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int i = min(lane + 64 * k, cnt - 1);
-      vv[k] = a.v[e0 + i];
-      cc[k] = a.ci[e0 + i];
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-      const int i = lane + 64 * k;
-      if (i < cnt) {
-        sv[i] = vv[k];
-        sc[i] = cc[k];
-      }
-    }
-    bwave_lds_sync();
-  }
-  double acc[M], prow[M];
-  bool found = false;
-#pragma unroll
-  for (int c = 0; c < M; ++c) acc[c] = prow[c] = 0.0;
-  constexpr int U = M >= 4 ? 2 : (M == 1 ? 8 : 4);  // entries with loads in flight together
-  const int base = staged ? s - e0 : s;
-  for (int k0 = 0; k0 < len; k0 += U) {
-    int cs[U];
-    double vs[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const int idx = base + min(k0 + k, len - 1);
-      cs[k] = staged ? sc[idx] : a.ci[idx];
-      const double vv = staged ? sv[idx] : a.v[idx];
-      vs[k] = (k0 + k < len) ? vv : 0.0;
-    }
-    double g[U][M];
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      // a column outside the system (not a block-diagonal stack) is clamped
-      // into it: wrong values for an invalid input, never an access outside x
-      const int jl = min(max(cs[k] - rs, 0), nrows - 1);
-      const int64_t jb = v0 + (int64_t)jl * M;
-#pragma unroll
-      for (int c = 0; c < M; ++c) g[k][c] = fma(beta[c], a.pold[jb + c], a.z[jb + c]);
-    }
-#pragma unroll
-    for (int k = 0; k < U; ++k) {
-      const bool me = cs[k] == row && k0 + k < len;
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        acc[c] = fma(vs[k], g[k][c], acc[c]);
-        if (me) prow[c] = g[k][c];
-      }
-      found = found || me;
-    }
-  }
-  if (staged) bwave_lds_sync();
-  if (has) {
-    const int64_t rb = v0 + (int64_t)(row - rs) * M;
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const double pr = found ? prow[c] : fma(beta[c], a.pold[rb + c], a.z[rb + c]);
-      a.q[rb + c] = acc[c];
-      a.pnew[rb + c] = pr;
-      pq[c] = fma(pr, acc[c], pq[c]);
-    }
-  }
+// floor(e / m) for 0 <= e < 4096 and 1 <= m <= 8 (multiply by ceil(2^16/m);
+// the rounding error e / 2^16 stays below 1/8)
+__device__ __forceinline__ int div_small(int e, int m) {
+  const int inv = (65536 + m - 1) / m;
+  return (e * inv) >> 16;
 }
 
-template <int M>
-__device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, double *sv, int *sc) {
+// One chunk of rows of a system with M columns, in wave tiles of 64 rows.
+// The tile's row pointers and CSR entries are staged in LDS with coalesced
+// loads; then lane l owns elements e = l, l + 64, ... (row e / M, column
+// e mod M) of the tile's rows x M block, so consecutive lanes touch
+// consecutive doubles of the row-major [rows][M] vectors and the lanes of a
+// row read its CSR entries from LDS. q = A p with p = z + beta p_old formed
+// at every read; p_new is the diagonal term's p. H elements per lane are in
+// flight together.
+struct SpmvLds {
+  double v[kSpmvNnzCap];
+  int c[kSpmvNnzCap];
+  int rp[kBWaveRows + 1];
+};
+
+template <int H>
+__device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, SpmvLds &L) {
+  constexpr int CAP = kSpmvNnzCap;
+  constexpr int NL = CAP / 64;
+  constexpr int U = 8;   // CSR entries per row with loads in flight together
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ch_sys[ch]);
   const int rs = a.t.sys_row[s];
   const int nrows = a.t.sys_row[s + 1] - rs;
   const int64_t v0 = a.t.sys_vec[s];
   const int c0 = a.t.sys_col[s];
-  double beta[kBCols];
-#pragma unroll
-  for (int c = 0; c < kBCols; ++c) beta[c] = c < M ? a.beta[c0 + c] : 0.0;
+  double beta_l[H];
   double pq[kBCols];
 #pragma unroll
-  for (int c = 0; c < kBCols; ++c) pq[c] = 0.0;
+  for (int cc = 0; cc < kBCols; ++cc) pq[cc] = 0.0;
   const int rb = a.t.ch_row0[ch], re = a.t.ch_row0[ch + 1];
-  for (int r0 = rb; r0 < re; r0 += kBWaveRows)
-    bspmv_tile<M>(a, beta, rs, nrows, v0, r0, min(re, r0 + kBWaveRows), sv, sc, pq);
+  for (int r0 = rb; r0 < re; r0 += kBWaveRows) {
+    const int r1 = min(re, r0 + kBWaveRows);
+    const int nr = r1 - r0;
+    // stage row pointers (relative) and the CSR entries of the tile
+    const int e0 = __builtin_amdgcn_readfirstlane(a.rp[r0]);
+    const int cnt = __builtin_amdgcn_readfirstlane(a.rp[r1]) - e0;
+    const int rpl = a.rp[r0 + min(lane, nr)] - e0;
+    // cnt = 0 (all rows empty): no entry is read below
+    const bool staged = cnt > 0 && cnt <= CAP;
+    if (staged) {
+      double vv[NL];
+      int cc[NL];
 #pragma unroll
-  for (int c = 0; c < kBCols; ++c) {
-    const double t = wave_sum(pq[c]);
-    if (lane == c) a.part[(int64_t)ch * kBCols + c] = t;
+      for (int k = 0; k < NL; ++k) {
+        const int i = min(lane + 64 * k, max(cnt - 1, 0));
+        vv[k] = a.v[e0 + i];
+        cc[k] = a.ci[e0 + i];
+      }
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const int i = lane + 64 * k;
+        if (i < cnt) {
+          L.v[i] = vv[k];
+          L.c[i] = cc[k];
+        }
+      }
+    }
+    L.rp[lane] = rpl;
+    if (lane == 0) L.rp[64] = cnt;
+    bwave_lds_sync();
+    const int E = nr * M;
+    for (int eb = 0; eb < E; eb += 64 * H) {
+      int row[H], cidx[H], sidx[H], len[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        const int e = min(eb + 64 * h + lane, E - 1);
+        row[h] = div_small(e, M);
+        cidx[h] = e - row[h] * M;
+        sidx[h] = L.rp[row[h]];
+        len[h] = (eb + 64 * h + lane < E) ? L.rp[row[h] + 1] - sidx[h] : 0;
+        beta_l[h] = a.beta[c0 + cidx[h]];
+      }
+      double acc[H], prow[H];
+      bool found[H];
+      int lmax = 0;
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        acc[h] = prow[h] = 0.0;
+        found[h] = false;
+        lmax = max(lmax, len[h]);
+      }
+      for (int k0 = 0; k0 < lmax; k0 += U) {
+        int cs[H][U];
+        double vs[H][U], g[H][U];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            const int idx = min(sidx[h] + min(k0 + k, max(len[h] - 1, 0)), cnt - 1);
+            const bool ok = k0 + k < len[h];
+            cs[h][k] = staged ? L.c[idx] : a.ci[e0 + idx];
+            const double vv = staged ? L.v[idx] : a.v[e0 + idx];
+            vs[h][k] = ok ? vv : 0.0;
+          }
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            // a column outside the system (not a block-diagonal stack) is
+            // clamped into it: wrong values for an invalid input, never an
+            // access outside the vectors
+            const int jl = min(max(cs[h][k] - rs, 0), nrows - 1);
+            const int64_t j = v0 + (int64_t)jl * M + cidx[h];
+            g[h][k] = fma(beta_l[h], a.pold[j], a.z[j]);
+          }
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            const bool ok = k0 + k < len[h];
+            acc[h] = fma(vs[h][k], g[h][k], acc[h]);
+            const bool me = ok && cs[h][k] == r0 + row[h];
+            prow[h] = me ? g[h][k] : prow[h];
+            found[h] = found[h] || me;
+          }
+      }
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if (eb + 64 * h + lane < E) {
+          const int64_t e = v0 + (int64_t)(r0 + row[h] - rs) * M + cidx[h];
+          const double pr = found[h] ? prow[h] : fma(beta_l[h], a.pold[e], a.z[e]);
+          a.q[e] = acc[h];
+          a.pnew[e] = pr;
+          const double t = pr * acc[h];
+#pragma unroll
+          for (int cc = 0; cc < kBCols; ++cc) pq[cc] += cidx[h] == cc ? t : 0.0;
+        }
+      }
+    }
+    bwave_lds_sync();
+  }
+#pragma unroll
+  for (int cc = 0; cc < kBCols; ++cc) {
+    const double t = wave_sum(pq[cc]);
+    if (lane == cc) a.part[(int64_t)ch * kBCols + cc] = t;
   }
 }
 
+// The chunks are split into 8 runs of about equal cost, one per XCD (sched
+// holds the 9 run boundaries). Inside a run the XCD's waves take chunks
+// round-robin, so at any moment its resident waves work on one window of
+// consecutive chunks and the neighbour rows a gather needs (up to a grid
+// plane away) were fetched into that XCD's L2 by another wave of the window.
+template <int H>
 __global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
-  __shared__ double svs[4][kSpmvNnzCap];
-  __shared__ int scs[4][kSpmvNnzCap];
+  __shared__ SpmvLds lds[4];
   if (*a.n_active == 0) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int w = wave_slot(wv);
-  const int ce = a.sched[w + 1];
-  for (int ch = a.sched[w]; ch < ce; ++ch) {
+  const int x = blockIdx.x & 7;
+  const int j = (blockIdx.x >> 3) * 4 + wv;
+  const int Wx = (gridDim.x >> 3) * 4;
+  const int ce = a.sched[x + 1];
+  for (int ch = a.sched[x] + j; ch < ce; ch += Wx) {
     const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ch_sys[ch]]);
-    switch (m) {
-      case 1: bspmv_chunk<1>(a, ch, svs[wv], scs[wv]); break;
-      case 2: bspmv_chunk<2>(a, ch, svs[wv], scs[wv]); break;
-      case 3: bspmv_chunk<3>(a, ch, svs[wv], scs[wv]); break;
-      case 4: bspmv_chunk<4>(a, ch, svs[wv], scs[wv]); break;
-      case 5: bspmv_chunk<5>(a, ch, svs[wv], scs[wv]); break;
-      case 6: bspmv_chunk<6>(a, ch, svs[wv], scs[wv]); break;
-      case 7: bspmv_chunk<7>(a, ch, svs[wv], scs[wv]); break;
-      default: bspmv_chunk<8>(a, ch, svs[wv], scs[wv]); break;
-    }
+    bspmv_chunk<H>(a, ch, m, lds[wv]);
   }
 }
 
@@ -304,80 +339,86 @@ __device__ __forceinline__ int64_t rl64(int64_t v, int src) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-// Blocks [k0, kend) of one system (rows from rs, vectors from v0, M columns):
-// per wave tile of <= 64 padded rows, the row phase (UPD: x += alpha p,
-// r -= alpha q) stages r, in FP64 and as its FP32 copy, in LDS as the B
-// operand; each 16-row tile of each block then takes B/4 matrix-core steps;
-// z goes back to HBM from LDS and (r, r), (r, z) accumulate per column.
+// Blocks [k0, kend) of one system (rows from rs, vectors from v0, M columns).
+// Per wave tile of consecutive whole blocks (<= 64 padded rows):
+//  1. element phase: the tile's real rows are one contiguous run of
+//     rows x M doubles; lane l takes elements l, l + 64, ... (UPD: x += alpha
+//     p, r -= alpha q) and drops r, in FP64 and as its FP32 copy, into LDS
+//     at [padded row][column] (padding rows and columns >= M stay zero);
+//  2. each 16-row tile of each block takes B/4 matrix-core steps with the
+//     LDS columns as the B operand, results to LDS;
+//  3. lane l sums (r, r) and (r, z) of padded row l per column from LDS;
+//  4. element phase: z back to HBM, contiguous.
 template <bool UPD>
 __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int kend, int rs, int64_t v0, int M,
-                                              const double (&alpha)[kBCols], float *r32, double *r64, double *zt,
+                                              const double *alpha_g, float *r32, double *r64, double *zt,
                                               double (&rr)[kBCols], double (&rz)[kBCols]) {
   const int lane = threadIdx.x & 63;
+  // per element-slot column and alpha: element e = pass * 64 + lane has
+  // column (e mod M); 64 mod M shifts it by the same amount every pass
   while (k0 < kend) {
-    // wave tile: consecutive whole blocks with at most 64 padded rows
-    const int kl = min(k0 + min(lane, 3), kend - 1);
-    const int mB = a.bpad[kl], mrow = a.blk_row[kl], mrow1 = a.blk_row[kl + 1];
-    const int64_t moff = a.map.off[kl];
-    const double msc = a.map.scale[kl];
-    const int mtag = a.map.tag[kl];
+    const int kl = min(k0 + min(lane, 4), kend);
+    const int mB = kl < kend ? a.bpad[kl] : 0;
+    const int mrow = a.blk_row[kl];
+    const int kq = min(k0 + min(lane, 3), kend - 1);
+    const int64_t moff = a.map.off[kq];
+    const double msc = a.map.scale[kq];
+    const int mtag = a.map.tag[kq];
     int nk = 0, cum = 0;
     while (nk < 4 && k0 + nk < kend && cum + rl(mB, nk) <= kBWaveRows) {
       cum += rl(mB, nk);
       ++nk;
     }
-    int row0 = 0, bsz = 0, li = -1, acc = 0;
-    for (int i = 0; i < nk; ++i) {
-      const int Bi = rl(mB, i);
-      if (lane >= acc && lane < acc + Bi) {
-        li = lane - acc;
-        row0 = rl(mrow, i);
-        bsz = rl(mrow1, i) - row0;
+    // block starts relative to the tile (rows) and in the padded LDS layout
+    const int R0 = rl(mrow, 0);
+    const int nreal = rl(mrow, nk) - R0;
+    int bst[4], cbo[4];
+    {
+      int cb = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        bst[i] = i < nk ? rl(mrow, i) - R0 : (1 << 30);
+        cbo[i] = cb;
+        cb += i < nk ? rl(mB, i) : 0;
       }
-      acc += Bi;
     }
-    const bool real = li >= 0 && li < bsz;
-    const int64_t vb = v0 + (int64_t)(row0 + li - rs) * M;
-    double rv[kBCols];
-#pragma unroll
-    for (int c = 0; c < kBCols; ++c) rv[c] = 0.0;
-    if (real && UPD) {
-      double pv[kBCols], qv[kBCols], xv[kBCols];
-#pragma unroll
-      for (int c = 0; c < kBCols; ++c) {
-        if (c < M) {
-          pv[c] = a.p[vb + c];
-          qv[c] = a.q[vb + c];
-          xv[c] = a.x[vb + c];
-          rv[c] = a.r[vb + c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < kBCols; ++c) {
-        if (c < M) {
-          a.x[vb + c] = fma(alpha[c], pv[c], xv[c]);
-          rv[c] = fma(-alpha[c], qv[c], rv[c]);
-          a.r[vb + c] = rv[c];
-          rr[c] = fma(rv[c], rv[c], rr[c]);
-        }
-      }
-    } else if (real) {
-#pragma unroll
-      for (int c = 0; c < kBCols; ++c)
-        if (c < M) rv[c] = a.r[vb + c];
-    }
+    // 1. zero this lane's LDS row, then the element phase
 #pragma unroll
     for (int c = 0; c < kBCols; ++c) {
-      r64[lane * kBCols + c] = rv[c];
-      r32[lane * kBCols + c] = __double2float_rn(rv[c]);
+      r64[lane * kBCols + c] = 0.0;
+      r32[lane * kBCols + c] = 0.0f;
     }
     bwave_lds_sync();
-    int cb = 0;
+    const int E = nreal * M;
+    const int64_t base = v0 + (int64_t)(R0 - rs) * M;
+    for (int e = lane; e < E; e += 64) {
+      const int row = div_small(e, M);
+      const int c = e - row * M;
+      double rv;
+      if (UPD) {
+        const double pv = a.p[base + e], qv = a.q[base + e], xv = a.x[base + e], r0v = a.r[base + e];
+        const double al = alpha_g[c];
+        a.x[base + e] = fma(al, pv, xv);
+        rv = fma(-al, qv, r0v);
+        a.r[base + e] = rv;
+      } else {
+        rv = a.r[base + e];
+      }
+      const int i = (row >= bst[1]) + (row >= bst[2]) + (row >= bst[3]);
+      const int bs_i = i == 0 ? bst[0] : i == 1 ? bst[1] : i == 2 ? bst[2] : bst[3];
+      const int cb_i = i == 0 ? cbo[0] : i == 1 ? cbo[1] : i == 2 ? cbo[2] : cbo[3];
+      const int lr = row - bs_i + cb_i;
+      r64[lr * kBCols + c] = rv;
+      r32[lr * kBCols + c] = __double2float_rn(rv);
+    }
+    bwave_lds_sync();
+    // 2. block products
     for (int i = 0; i < nk; ++i) {
       const int B = rl(mB, i);
       const int prec = rl(mtag, i);
       const uint8_t *blk = a.map.base + rl64(moff, i);
       const double sc = bcast(msc, i);
+      const int cb = cbo[i];
       for (int mt = 0; mt < B / 16; ++mt) {
         const float *b32 = r32 + cb * kBCols;
         const double *b64 = r64 + cb * kBCols;
@@ -389,18 +430,30 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
           default: bmtile_dispatch<64>(prec, blk, sc, mt, b32, b64, zb, lane); break;
         }
       }
-      cb += B;
     }
     bwave_lds_sync();
-    if (real) {
+    // 3. per-column dots over the real rows of the tile (lane = LDS row)
+    const int li = (lane >= cbo[1] && nk > 1) + (lane >= cbo[2] && nk > 2) + (lane >= cbo[3] && nk > 3);
+    const int lb_start = li == 0 ? cbo[0] : li == 1 ? cbo[1] : li == 2 ? cbo[2] : cbo[3];
+    const int lb_rows = (li + 1 < nk ? (li == 0 ? bst[1] : li == 1 ? bst[2] : bst[3]) : nreal) -
+                        (li == 0 ? bst[0] : li == 1 ? bst[1] : li == 2 ? bst[2] : bst[3]);
+    if (lane < cum && lane - lb_start < lb_rows) {
 #pragma unroll
       for (int c = 0; c < kBCols; ++c) {
-        if (c < M) {
-          const double zv = zt[lane * kBCols + c];
-          a.z[vb + c] = zv;
-          rz[c] = fma(rv[c], zv, rz[c]);
-        }
+        const double rv = r64[lane * kBCols + c];
+        const double zv = zt[lane * kBCols + c];
+        rr[c] = fma(rv, rv, rr[c]);
+        rz[c] = fma(rv, zv, rz[c]);
       }
+    }
+    // 4. z to HBM
+    for (int e = lane; e < E; e += 64) {
+      const int row = div_small(e, M);
+      const int c = e - row * M;
+      const int i = (row >= bst[1]) + (row >= bst[2]) + (row >= bst[3]);
+      const int bs_i = i == 0 ? bst[0] : i == 1 ? bst[1] : i == 2 ? bst[2] : bst[3];
+      const int cb_i = i == 0 ? cbo[0] : i == 1 ? cbo[1] : i == 2 ? cbo[2] : cbo[3];
+      a.z[base + e] = zt[(row - bs_i + cb_i) * kBCols + c];
     }
     bwave_lds_sync();
     k0 += nk;
@@ -412,14 +465,11 @@ __device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M,
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ach_sys[ch]);
   const int c0 = a.t.sys_col[s];
-  double alpha[kBCols], rr[kBCols], rz[kBCols];
+  double rr[kBCols], rz[kBCols];
 #pragma unroll
-  for (int c = 0; c < kBCols; ++c) {
-    alpha[c] = c < M ? a.alpha[c0 + c] : 0.0;
-    rr[c] = rz[c] = 0.0;
-  }
-  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], M, alpha, r32, r64,
-                      zt, rr, rz);
+  for (int c = 0; c < kBCols; ++c) rr[c] = rz[c] = 0.0;
+  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], M, a.alpha + c0,
+                      r32, r64, zt, rr, rz);
 #pragma unroll
   for (int c = 0; c < kBCols; ++c) {
     const double t1 = wave_sum(rr[c]);
@@ -453,11 +503,11 @@ __global__ __launch_bounds__(256) void bapply_multi_kernel(BApplyArgs a, const i
   __shared__ double r64s[4][kBWaveRows * kBCols];
   __shared__ double zts[4][kBWaveRows * kBCols];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double alpha[kBCols], rr[kBCols], rz[kBCols];
+  double rr[kBCols], rz[kBCols];
 #pragma unroll
-  for (int c = 0; c < kBCols; ++c) alpha[c] = rr[c] = rz[c] = 0.0;
+  for (int c = 0; c < kBCols; ++c) rr[c] = rz[c] = 0.0;
   for (int t = blockIdx.x * 4 + wv; t < ntiles; t += gridDim.x * 4)
-    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, m, alpha, r32s[wv], r64s[wv], zts[wv], rr, rz);
+    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, m, nullptr, r32s[wv], r64s[wv], zts[wv], rr, rz);
 }
 
 // ------------------------------------------------------- per-system scalars
@@ -572,7 +622,7 @@ __global__ __launch_bounds__(256) void binit_kernel(int64_t len, double *x, doub
 }
 
 // ---------------------------------------------------------------- host side
-constexpr int kBMaxGrid = 2048;               // workgroups of a batched launch
+constexpr int kBMaxGrid = 8192;               // workgroups of a batched launch
 constexpr int kBMaxWaves = kBMaxGrid * 4;
 
 struct BPlan {
@@ -584,9 +634,10 @@ struct BPlan {
 };
 
 static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const int32_t *sys_row,
-                      const int32_t *sys_m, int chunk_rows, BPlan &pl) {
+                      const int32_t *sys_m, int chunk_rows, int apply_rows, BPlan &pl) {
   if (!M || S < 1 || !sys_row || !sys_m || sys_row[0] != 0 || sys_row[S] != M->n) return BJAC_EINVAL;
   if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
+  if (apply_rows < kBWaveRows || apply_rows > (1 << 20)) return BJAC_EINVAL;
   pl.S = S;
   pl.sys_row.assign(sys_row, sys_row + S + 1);
   pl.sys_m.assign(sys_m, sys_m + S);
@@ -615,7 +666,7 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
     pl.sys_ch.push_back((int32_t)pl.ch_sys.size());
   }
   pl.ch_row0.push_back(sys_row[S]);
-  // apply chunks: whole blocks, at most chunk_rows padded rows, one system
+  // apply chunks: whole blocks, at most apply_rows padded rows, one system
   // each; every system boundary must be a block boundary
   const std::vector<int32_t> &br = M->h_blk_row;
   const std::vector<uint8_t> &tg = M->h_tag_lo;
@@ -630,7 +681,7 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
     }
     if (br[k + 1] > sys_row[s + 1]) return BJAC_EINVAL;  // block crosses systems
     const int B = M->h_bpad[k];
-    if (fresh || rows + B > chunk_rows) {
+    if (fresh || rows + B > apply_rows) {
       pl.ach_blk.push_back(k);
       pl.ach_sys.push_back(s);
       pl.ach_cost.push_back(256.0);
@@ -681,6 +732,18 @@ static int bgrid(int units, int wg_per_cu) {
   return std::max(G, 8);
 }
 
+// workgroups of the SpMV that fit on one compute unit at once: its grid is
+// one resident round, so every wave of an XCD sweeps the same window
+static int spmv_resident(int ilp) {
+  static int occ[3] = {0, 0, 0};
+  int &o = occ[ilp == 1 ? 1 : 2];
+  if (!o) {
+    const void *k = ilp == 1 ? (const void *)bspmv_kernel<1> : (const void *)bspmv_kernel<2>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, 256, 0) != hipSuccess || o < 1) o = 2;
+  }
+  return o;
+}
+
 struct BWs {
   double *r, *z, *pa, *pb, *q, *part1, *part2;
   double *rho, *alpha, *beta, *rnorm0, *relres;
@@ -727,6 +790,7 @@ struct BCtx {
   BState st{};
   DevMap map{};
   int G1 = 8, G2 = 8;
+  int ilp = 2;
   const int32_t *sched1 = nullptr, *sched2 = nullptr;
   const bjac_csr *A = nullptr;
   const bjac_handle *M = nullptr;
@@ -734,9 +798,11 @@ struct BCtx {
   double *x = nullptr;
 };
 
-static void cfg_defaults(const bjac_batch_cfg *cfg, int &chunk_rows, int &wg_per_cu) {
-  chunk_rows = cfg && cfg->chunk_rows > 0 ? cfg->chunk_rows : 1024;
-  wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 4;
+static void cfg_defaults(const bjac_batch_cfg *cfg, int &chunk_rows, int &wg_per_cu, int &ilp, int &apply_rows) {
+  chunk_rows = cfg && cfg->chunk_rows > 0 ? cfg->chunk_rows : 128;
+  apply_rows = cfg && cfg->apply_rows > 0 ? cfg->apply_rows : 1024;
+  wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 8;
+  ilp = cfg && cfg->spmv_ilp > 0 ? cfg->spmv_ilp : 2;
 }
 
 static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
@@ -744,18 +810,19 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
                      const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes, hipStream_t s, BCtx &c) {
   if (!A || !M || !b || !x || !workspace || b == x || A->n != M->n) return BJAC_EINVAL;
   if (!(tol >= 0.0) || maxit < 1) return BJAC_EINVAL;
-  int chunk_rows, wg_per_cu;
-  cfg_defaults(cfg, chunk_rows, wg_per_cu);
-  if (wg_per_cu > 8) return BJAC_EINVAL;
-  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, c.pl);
+  int chunk_rows, wg_per_cu, ilp, apply_rows;
+  cfg_defaults(cfg, chunk_rows, wg_per_cu, ilp, apply_rows);
+  if (wg_per_cu > 32 || ilp > 2) return BJAC_EINVAL;
+  c.ilp = ilp;
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, apply_rows, c.pl);
   if (rc) return rc;
   c.w = carve_b(workspace, c.pl);
   if (c.w.bytes > workspace_bytes) return BJAC_ENOMEM;
   const BPlan &pl = c.pl;
-  c.G1 = bgrid((int)pl.ch_sys.size(), wg_per_cu);
+  c.G1 = bgrid((int)pl.ch_sys.size(), std::min(wg_per_cu, spmv_resident(ilp)));
   c.G2 = bgrid((int)pl.ach_sys.size(), wg_per_cu);
   std::vector<int32_t> sch1, sch2;
-  split_cost(pl.ch_cost, c.G1 * 4, sch1);
+  split_cost(pl.ch_cost, 8, sch1);
   split_cost(pl.ach_cost, c.G2 * 4, sch2);
   // tables, uploaded once per call
   std::vector<int32_t> tabs;
@@ -798,7 +865,7 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
   return BJAC_OK;
 }
 
-static void benq_spmv(const BCtx &c, const double *pold, double *pnew, hipStream_t s) {
+static void benq_spmv_k(const BCtx &c, const double *pold, double *pnew, hipStream_t s) {
   BSpmvArgs a{};
   a.t = c.t;
   a.rp = c.A->row_ptr;
@@ -812,11 +879,23 @@ static void benq_spmv(const BCtx &c, const double *pold, double *pnew, hipStream
   a.part = c.w.part1;
   a.n_active = c.w.n_active;
   a.sched = c.sched1;
-  hipLaunchKernelGGL(bspmv_kernel, dim3(c.G1), dim3(256), 0, s, a);
+  a.ilp = c.ilp;
+  if (c.ilp == 1)
+    hipLaunchKernelGGL(bspmv_kernel<1>, dim3(c.G1), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(bspmv_kernel<2>, dim3(c.G1), dim3(256), 0, s, a);
+}
+
+static void benq_spmv_r(const BCtx &c, hipStream_t s) {
   hipLaunchKernelGGL(breduce_pq_kernel, dim3(c.t.S), dim3(256), 0, s, c.t, c.st, (const double *)c.w.part1);
 }
 
-static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) {
+static void benq_spmv(const BCtx &c, const double *pold, double *pnew, hipStream_t s) {
+  benq_spmv_k(c, pold, pnew, s);
+  benq_spmv_r(c, s);
+}
+
+static void benq_apply_k(const BCtx &c, const double *p, hipStream_t s) {
   BApplyArgs a{};
   a.t = c.t;
   a.blk_row = c.M->blk_row;
@@ -832,7 +911,15 @@ static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) 
   a.n_active = c.w.n_active;
   a.sched = c.sched2;
   hipLaunchKernelGGL(bapply_kernel, dim3(c.G2), dim3(256), 0, s, a);
+}
+
+static void benq_apply_r(const BCtx &c, int init, hipStream_t s) {
   hipLaunchKernelGGL(breduce_rz_kernel, dim3(c.t.S), dim3(256), 0, s, c.t, c.st, (const double *)c.w.part2, init);
+}
+
+static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) {
+  benq_apply_k(c, p, s);
+  benq_apply_r(c, init, s);
 }
 
 // x = 0, r = b, p = q = 0, then z_0 = M^-1 r_0 through the apply kernel with
@@ -850,6 +937,110 @@ static void benq_iter(const BCtx &c, int j, hipStream_t s) {
   benq_apply(c, even ? c.w.pb : c.w.pa, 0, s);
 }
 
+static int bcollect(const BCtx &c, hipStream_t s, int32_t *col_iters, int32_t *col_status, double *col_relres,
+                    bjac_stats *stats, int launches, float ms) {
+  const int nc = c.pl.ncols;
+  std::vector<int32_t> its(nc), sts(nc);
+  std::vector<double> rel(nc);
+  MPB_HIP(hipMemcpyAsync(its.data(), c.w.iter, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipMemcpyAsync(sts.data(), c.w.status, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipMemcpyAsync(rel.data(), c.w.relres, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  MPB_HIP(hipStreamSynchronize(s));
+  int worst = BJAC_OK, maxits = 0;
+  double maxrel = 0.0;
+  for (int i = 0; i < nc; ++i) {
+    const int code = sts[i] == BS_CONVERGED ? BJAC_OK
+                     : sts[i] == BS_BREAKDOWN ? BJAC_EBREAKDOWN
+                                              : BJAC_NOT_CONVERGED;
+    if (code == BJAC_EBREAKDOWN || (code == BJAC_NOT_CONVERGED && worst == BJAC_OK)) worst = code;
+    if (col_iters) col_iters[i] = its[i];
+    if (col_status) col_status[i] = code;
+    if (col_relres) col_relres[i] = rel[i];
+    maxits = std::max(maxits, its[i]);
+    maxrel = std::max(maxrel, rel[i]);
+  }
+  if (stats) {
+    const double sp = stats->spmv_ms, ap = stats->apply_ms, up = stats->update_ms;
+    const int nsp = stats->n_spmv, nap = stats->n_apply, nup = stats->n_update;
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = maxits;
+    stats->status = worst;
+    stats->graph_launches = launches;
+    stats->solve_ms = ms;
+    stats->relres = maxrel;
+    stats->spmv_ms = sp;
+    stats->apply_ms = ap;
+    stats->update_ms = up;
+    stats->n_spmv = nsp;
+    stats->n_apply = nap;
+    stats->n_update = nup;
+  }
+  return worst;
+}
+
+// Profile mode: eager launches, one host check of n_active per iteration,
+// HIP events around every kernel on the caller's stream.
+static int bcollect(const BCtx &c, hipStream_t s, int32_t *col_iters, int32_t *col_status, double *col_relres,
+                    bjac_stats *stats, int launches, float ms);
+
+static int bprofile_run(const BCtx &c, int maxit, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int32_t *col_iters,
+                        int32_t *col_status, double *col_relres, bjac_stats *stats) {
+  hipEvent_t ev[5];
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) return BJAC_EHIP;
+  int32_t *active = nullptr;
+  if (hipHostMalloc((void **)&active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return BJAC_EHIP;
+  double t_spmv = 0.0, t_apply = 0.0, t_red = 0.0;
+  int n_it = 0, rc = BJAC_OK;
+  *active = 1;
+  if (hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    rc = BJAC_EHIP;
+  for (int j = 0; rc == BJAC_OK && *active > 0 && j < maxit; ++j) {
+    const bool even = (j & 1) == 0;
+    (void)hipEventRecord(ev[0], s);
+    benq_spmv_k(c, even ? c.w.pa : c.w.pb, even ? c.w.pb : c.w.pa, s);
+    (void)hipEventRecord(ev[1], s);
+    benq_spmv_r(c, s);
+    (void)hipEventRecord(ev[2], s);
+    benq_apply_k(c, even ? c.w.pb : c.w.pa, s);
+    (void)hipEventRecord(ev[3], s);
+    benq_apply_r(c, 0, s);
+    (void)hipEventRecord(ev[4], s);
+    if (hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = BJAC_EHIP;
+      break;
+    }
+    float a = 0.f, b = 0.f, d = 0.f, f = 0.f;
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    (void)hipEventElapsedTime(&d, ev[2], ev[3]);
+    (void)hipEventElapsedTime(&f, ev[3], ev[4]);
+    t_spmv += a;
+    t_apply += d;
+    t_red += b + f;
+    ++n_it;
+  }
+  (void)hipHostFree(active);
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  MPB_HIP(hipEventRecord(e1, s));
+  MPB_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (stats) {
+    stats->spmv_ms = t_spmv;
+    stats->apply_ms = t_apply;
+    stats->update_ms = t_red;
+    stats->n_spmv = stats->n_apply = n_it;
+    stats->n_update = 2 * n_it;
+  }
+  return bcollect(c, s, col_iters, col_status, col_relres, stats, 0, ms);
+}
+
 }  // namespace mpb
 
 using namespace mpb;
@@ -858,10 +1049,10 @@ extern "C" int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle 
                                            const int32_t *sys_row, const int32_t *sys_m,
                                            const bjac_batch_cfg *cfg, size_t *workspace_bytes) {
   if (!workspace_bytes || !A) return BJAC_EINVAL;
-  int chunk_rows, wg_per_cu;
-  cfg_defaults(cfg, chunk_rows, wg_per_cu);
+  int chunk_rows, wg_per_cu, ilp, apply_rows;
+  cfg_defaults(cfg, chunk_rows, wg_per_cu, ilp, apply_rows);
   BPlan p;
-  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, p);
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, apply_rows, p);
   if (rc) return rc;
   *workspace_bytes = carve_b(nullptr, p).bytes;
   return BJAC_OK;
@@ -886,6 +1077,8 @@ extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_
   MPB_HIP(hipEventRecord(e0, s));
   benq_init(c, s);
   MPB_HIP(hipGetLastError());
+
+  if (opts->profile) return bprofile_run(c, opts->maxit, s, e0, e1, col_iters, col_status, col_relres, stats);
 
   // capture `chunk` iterations once; kernels return at once when no column
   // is running, so replays past convergence cost only their launches
@@ -926,34 +1119,11 @@ extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 
-  const int nc = c.pl.ncols;
-  std::vector<int32_t> its(nc), sts(nc);
-  std::vector<double> rel(nc);
-  MPB_HIP(hipMemcpyAsync(its.data(), c.w.iter, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-  MPB_HIP(hipMemcpyAsync(sts.data(), c.w.status, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-  MPB_HIP(hipMemcpyAsync(rel.data(), c.w.relres, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
-  MPB_HIP(hipStreamSynchronize(s));
-  int worst = BJAC_OK, maxits = 0;
-  for (int i = 0; i < nc; ++i) {
-    const int code = sts[i] == BS_CONVERGED ? BJAC_OK
-                     : sts[i] == BS_BREAKDOWN ? BJAC_EBREAKDOWN
-                                              : BJAC_NOT_CONVERGED;
-    if (code == BJAC_EBREAKDOWN || (code == BJAC_NOT_CONVERGED && worst == BJAC_OK)) worst = code;
-    if (col_iters) col_iters[i] = its[i];
-    if (col_status) col_status[i] = code;
-    if (col_relres) col_relres[i] = rel[i];
-    maxits = std::max(maxits, its[i]);
-  }
   if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->iters = maxits;
-    stats->status = worst;
-    stats->graph_launches = launches;
-    stats->solve_ms = ms;
-    stats->relres = 0.0;
-    for (int i = 0; i < nc; ++i) stats->relres = std::max(stats->relres, rel[i]);
+    stats->spmv_ms = stats->apply_ms = stats->update_ms = 0.0;
+    stats->n_spmv = stats->n_apply = stats->n_update = 0;
   }
-  return worst;
+  return bcollect(c, s, col_iters, col_status, col_relres, stats, launches, ms);
 }
 
 extern "C" int pcg_batched_tune(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,

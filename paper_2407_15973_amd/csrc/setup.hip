@@ -259,7 +259,13 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   }
   if (a.tag_out && lane == 0) a.tag_out[k] = (uint8_t)tag;
 
-  // --- scale, round, pack
+  // --- scale, round, pack. The padding rows of diag(A_ii, I) are stored as
+  // zeros: their outputs are never used, and 1/s of a scaled 16-bit block can
+  // exceed the format (an infinity times a zero residual would be NaN)
+  if (!real) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) row[j] = 0.0;
+  }
   if (a.off_hi) {
     store_block<B>(a.base + a.off_hi[k], P64, row, lane, 1.0);
     if (lane == 0) a.scale_hi[k] = 1.0;

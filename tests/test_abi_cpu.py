@@ -40,4 +40,4 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(binding.bjac_solve_opts) == 40
     assert C.sizeof(binding.bjac_stats) == 80
     assert C.sizeof(binding.bjac_info) == 64
-    assert C.sizeof(binding.bjac_batch_cfg) == 8
+    assert C.sizeof(binding.bjac_batch_cfg) == 16

@@ -151,13 +151,13 @@ def test_batched_pcg_matches_oracle(prec, slack):
 
 def test_batched_rule_map_and_uneven_chunks():
     st = _batch(5, nsys=5, edge=(6, 12), nrhs=(2, 6))
-    M, bs, res = _run(st, mb.Policy(mode=mb.RULE), cfg=(64, 2))
+    M, bs, res = _run(st, mb.Policy(mode=mb.RULE), cfg=(64, 2, 1, 64))
     assert res.status == mb.OK
     ref = _oracle_cols(st, M.tags(), 1e-10, 3000)
     for col, (it, status, xo, sub, bcol) in enumerate(ref):
         assert abs(int(res.col_iters[col]) - it) <= max(3, int(0.05 * it))
     # a different chunking reorders only the per-column dot reductions
-    res2 = bs.solve(tensor(st.b), tol=1e-10, maxit=3000, cfg=(4096, 8))
+    res2 = bs.solve(tensor(st.b), tol=1e-10, maxit=3000, cfg=(4096, 32, 2))
     assert res2.status == mb.OK
     assert np.all(np.abs(res2.col_iters - res.col_iters) <= 1)
 
@@ -210,7 +210,7 @@ def test_autotuner_picks_a_candidate_and_it_solves():
     Ad = mb.DeviceCSR(st.A, dev())
     M = mb.BlockJacobi(Ad, st.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16))
     bs = mb.BatchSolver(Ad, M, st.sys_row, st.sys_m)
-    cands = [(256, 2), (1024, 4), (4096, 8)]
+    cands = [(256, 2, 1), (1024, 4, 2), (4096, 16, 1)]
     best, ms = bs.tune(tensor(st.b), cands, iters=4)
     assert 0 <= best < len(cands)
     assert np.all(ms > 0) and ms[best] == ms.min()
@@ -219,3 +219,29 @@ def test_autotuner_picks_a_candidate_and_it_solves():
     ref = _oracle_cols(st, M.tags(), 1e-10, 3000)
     for col, (it, *_r) in enumerate(ref):
         assert abs(int(res.col_iters[col]) - it) <= max(3, int(0.05 * it))
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    from paper_2407_15973_amd import autotune
+    st = _batch(10, nsys=4, edge=(8, 12), nrhs=(1, 4))
+    Ad = mb.DeviceCSR(st.A, dev())
+    M = mb.BlockJacobi(Ad, st.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    bs = mb.BatchSolver(Ad, M, st.sys_row, st.sys_m)
+    path = str(tmp_path / "tune.json")
+    cands = [(64, 2, 1, 256), (2048, 4, 2, 4096)]
+    cfg1, e1 = autotune.tuned_cfg(bs, tensor(st.b), candidates=cands, iters=3, cache_path=path)
+    cfg2, e2 = autotune.tuned_cfg(bs, tensor(st.b), candidates=cands, iters=3, cache_path=path)
+    assert cfg1 == cfg2 and cfg1 in cands and e1 == e2
+    assert bs.solve(tensor(st.b), cfg=cfg1).status == mb.OK
+
+
+def test_profile_mode_runs_the_same_iterations():
+    st = _batch(11, nsys=4, edge=(8, 14), nrhs=(1, 8))
+    M, bs, res = _run(st, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    rp = bs.solve(tensor(st.b), tol=1e-10, maxit=3000, profile=True)
+    # same kernels in the same order: bit-identical iterates
+    assert np.array_equal(rp.col_iters, res.col_iters)
+    assert np.array_equal(rp.x.cpu().numpy(), res.x.cpu().numpy())
+    n_it = rp.kernel_ms["spmv"][1]
+    assert n_it == res.iters and rp.kernel_ms["apply"][1] == n_it
+    assert rp.kernel_ms["spmv"][0] > 0 and rp.kernel_ms["apply"][0] > 0
