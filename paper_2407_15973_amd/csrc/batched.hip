@@ -34,7 +34,8 @@ enum BStatus { BS_RUNNING = 0, BS_CONVERGED = 1, BS_MAXIT = 2, BS_BREAKDOWN = -3
 struct BTables {
   int32_t S, nch, nach;
   const int32_t *sys_row, *sys_m, *sys_col, *sys_ch, *sys_ach;
-  const int64_t *sys_vec;
+  const int64_t *sys_vec;    // system start in the solver's vectors (64-byte aligned)
+  const int64_t *sys_xvec;   // system start in the caller's b and x (contiguous)
   const int32_t *ch_row0, *ch_sys;    // SpMV chunks: rows [ch_row0[i], ch_row0[i+1])
   const int32_t *ach_blk, *ach_sys;   // apply chunks: blocks [ach_blk[i], ach_blk[i+1])
 };
@@ -97,18 +98,40 @@ struct SpmvLds {
   int rp[kBWaveRows + 1];
 };
 
-template <int H>
+template <int VW>
+struct VecT;
+template <>
+struct VecT<1> {
+  static __device__ __forceinline__ void load(const double *p, double (&v)[1]) { v[0] = *p; }
+  static __device__ __forceinline__ void store(double *p, const double (&v)[1]) { *p = v[0]; }
+};
+template <>
+struct VecT<2> {
+  // 16-byte aligned: solver vectors start on 64 bytes, M and the column are even
+  static __device__ __forceinline__ void load(const double *p, double (&v)[2]) {
+    const double2 t = *(const double2 *)p;
+    v[0] = t.x;
+    v[1] = t.y;
+  }
+  static __device__ __forceinline__ void store(double *p, const double (&v)[2]) {
+    *(double2 *)p = make_double2(v[0], v[1]);
+  }
+};
+
+// H: elements per lane in flight; VW: consecutive columns per element (2
+// needs an even M: one 16-byte access per vector and neighbour).
+template <int H, int VW>
 __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, SpmvLds &L) {
   constexpr int CAP = kSpmvNnzCap;
   constexpr int NL = CAP / 64;
-  constexpr int U = 8;   // CSR entries per row with loads in flight together
+  constexpr int U = 8 / VW;   // CSR entries per row with loads in flight together
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ch_sys[ch]);
   const int rs = a.t.sys_row[s];
   const int nrows = a.t.sys_row[s + 1] - rs;
   const int64_t v0 = a.t.sys_vec[s];
   const int c0 = a.t.sys_col[s];
-  double beta_l[H];
+  const int LPR = M / VW;   // lanes per row
   double pq[kBCols];
 #pragma unroll
   for (int cc = 0; cc < kBCols; ++cc) pq[cc] = 0.0;
@@ -127,7 +150,7 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
       int cc[NL];
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
-        const int i = min(lane + 64 * k, max(cnt - 1, 0));
+        const int i = min(lane + 64 * k, cnt - 1);
         vv[k] = a.v[e0 + i];
         cc[k] = a.ci[e0 + i];
       }
@@ -143,30 +166,33 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
     L.rp[lane] = rpl;
     if (lane == 0) L.rp[64] = cnt;
     bwave_lds_sync();
-    const int E = nr * M;
+    const int E = nr * LPR;
     for (int eb = 0; eb < E; eb += 64 * H) {
-      int row[H], cidx[H], sidx[H], len[H];
+      int row[H], col[H], sidx[H], len[H];
+      double beta[H][VW];
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         const int e = min(eb + 64 * h + lane, E - 1);
-        row[h] = div_small(e, M);
-        cidx[h] = e - row[h] * M;
+        row[h] = div_small(e, LPR);
+        col[h] = (e - row[h] * LPR) * VW;
         sidx[h] = L.rp[row[h]];
         len[h] = (eb + 64 * h + lane < E) ? L.rp[row[h] + 1] - sidx[h] : 0;
-        beta_l[h] = a.beta[c0 + cidx[h]];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) beta[h][v] = a.beta[c0 + col[h] + v];
       }
-      double acc[H], prow[H];
+      double acc[H][VW], prow[H][VW];
       bool found[H];
       int lmax = 0;
 #pragma unroll
       for (int h = 0; h < H; ++h) {
-        acc[h] = prow[h] = 0.0;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[h][v] = prow[h][v] = 0.0;
         found[h] = false;
         lmax = max(lmax, len[h]);
       }
       for (int k0 = 0; k0 < lmax; k0 += U) {
         int cs[H][U];
-        double vs[H][U], g[H][U];
+        double vs[H][U], gz[H][U][VW], gp[H][U][VW];
 #pragma unroll
         for (int h = 0; h < H; ++h)
 #pragma unroll
@@ -185,30 +211,48 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
             // clamped into it: wrong values for an invalid input, never an
             // access outside the vectors
             const int jl = min(max(cs[h][k] - rs, 0), nrows - 1);
-            const int64_t j = v0 + (int64_t)jl * M + cidx[h];
-            g[h][k] = fma(beta_l[h], a.pold[j], a.z[j]);
+            const int64_t j = v0 + (int64_t)jl * M + col[h];
+            VecT<VW>::load(a.pold + j, gp[h][k]);
+            VecT<VW>::load(a.z + j, gz[h][k]);
           }
 #pragma unroll
         for (int h = 0; h < H; ++h)
 #pragma unroll
           for (int k = 0; k < U; ++k) {
             const bool ok = k0 + k < len[h];
-            acc[h] = fma(vs[h][k], g[h][k], acc[h]);
             const bool me = ok && cs[h][k] == r0 + row[h];
-            prow[h] = me ? g[h][k] : prow[h];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) {
+              const double g = fma(beta[h][v], gp[h][k][v], gz[h][k][v]);
+              acc[h][v] = fma(vs[h][k], g, acc[h][v]);
+              prow[h][v] = me ? g : prow[h][v];
+            }
             found[h] = found[h] || me;
           }
       }
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         if (eb + 64 * h + lane < E) {
-          const int64_t e = v0 + (int64_t)(r0 + row[h] - rs) * M + cidx[h];
-          const double pr = found[h] ? prow[h] : fma(beta_l[h], a.pold[e], a.z[e]);
-          a.q[e] = acc[h];
-          a.pnew[e] = pr;
-          const double t = pr * acc[h];
+          const int64_t e = v0 + (int64_t)(r0 + row[h] - rs) * M + col[h];
+          double pr[VW];
+          if (!found[h]) {
+            double zz[VW], pp[VW];
+            VecT<VW>::load(a.z + e, zz);
+            VecT<VW>::load(a.pold + e, pp);
 #pragma unroll
-          for (int cc = 0; cc < kBCols; ++cc) pq[cc] += cidx[h] == cc ? t : 0.0;
+            for (int v = 0; v < VW; ++v) pr[v] = fma(beta[h][v], pp[v], zz[v]);
+          } else {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) pr[v] = prow[h][v];
+          }
+          VecT<VW>::store(a.q + e, acc[h]);
+          VecT<VW>::store(a.pnew + e, pr);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) {
+            const double t = pr[v] * acc[h][v];
+#pragma unroll
+            for (int cc = 0; cc < kBCols; ++cc) pq[cc] += col[h] + v == cc ? t : 0.0;
+          }
         }
       }
     }
@@ -237,7 +281,10 @@ __global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
   const int ce = a.sched[x + 1];
   for (int ch = a.sched[x] + j; ch < ce; ch += Wx) {
     const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ch_sys[ch]]);
-    bspmv_chunk<H>(a, ch, m, lds[wv]);
+    if (m & 1)
+      bspmv_chunk<H, 1>(a, ch, m, lds[wv]);
+    else
+      bspmv_chunk<H, 2>(a, ch, m, lds[wv]);
   }
 }
 
@@ -258,7 +305,7 @@ struct BApplyArgs {
 // One 16-row tile of a stored block times the FP32 (or FP64) residual columns
 // in the wave's LDS, on the matrix cores; result rows written to zt[row][8].
 template <int B, int P>
-__device__ __forceinline__ void bmtile(const uint8_t *blk, double scale, int mt, const float *r32, const double *r64,
+__device__ __forceinline__ void bmtile(const uint8_t *blk, double scale, int mt, const double *r64,
                                        double *zt, int lane) {
   constexpr int K = B / 4;
   constexpr int BY = prec_bytes(P);
@@ -308,7 +355,8 @@ __device__ __forceinline__ void bmtile(const uint8_t *blk, double scale, int mt,
           if constexpr (P == P32) av = __uint_as_float(w[e]);
           else if constexpr (P == PBF16) av = (e & 1) ? bf16_hi(w[e >> 1]) : bf16_lo(w[e >> 1]);
           else av = (e & 1) ? f16_hi(w[e >> 1]) : f16_lo(w[e >> 1]);
-          const float bv = col < kBCols ? r32[(4 * ks + kq) * kBCols + col] : 0.0f;
+          // the FP32 copy of r (Algorithm 3.1), rounded to nearest even
+          const float bv = col < kBCols ? __double2float_rn(r64[(4 * ks + kq) * kBCols + col]) : 0.0f;
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
         }
       }
@@ -322,13 +370,26 @@ __device__ __forceinline__ void bmtile(const uint8_t *blk, double scale, int mt,
 }
 
 template <int B>
-__device__ __forceinline__ void bmtile_dispatch(int prec, const uint8_t *blk, double scale, int mt, const float *r32,
+__device__ __forceinline__ void bmtile_dispatch(int prec, const uint8_t *blk, double scale, int mt,
                                                 const double *r64, double *zt, int lane) {
   switch (prec) {
-    case P64: bmtile<B, P64>(blk, scale, mt, r32, r64, zt, lane); break;
-    case P32: bmtile<B, P32>(blk, scale, mt, r32, r64, zt, lane); break;
-    case PBF16: bmtile<B, PBF16>(blk, scale, mt, r32, r64, zt, lane); break;
-    default: bmtile<B, P16>(blk, scale, mt, r32, r64, zt, lane); break;
+    case P64: bmtile<B, P64>(blk, scale, mt, r64, zt, lane); break;
+    case P32: bmtile<B, P32>(blk, scale, mt, r64, zt, lane); break;
+    case PBF16: bmtile<B, PBF16>(blk, scale, mt, r64, zt, lane); break;
+    default: bmtile<B, P16>(blk, scale, mt, r64, zt, lane); break;
+  }
+}
+
+// Z = s * Hhat R for one stored block of padded size B, tile by tile.
+__device__ __forceinline__ void bblock(int B, int prec, const uint8_t *blk, double scale, const double *r64,
+                                       double *zt, int lane) {
+  for (int mt = 0; mt < B / 16; ++mt) {
+    switch (B) {
+      case 16: bmtile_dispatch<16>(prec, blk, scale, mt, r64, zt, lane); break;
+      case 32: bmtile_dispatch<32>(prec, blk, scale, mt, r64, zt, lane); break;
+      case 48: bmtile_dispatch<48>(prec, blk, scale, mt, r64, zt, lane); break;
+      default: bmtile_dispatch<64>(prec, blk, scale, mt, r64, zt, lane); break;
+    }
   }
 }
 
@@ -343,16 +404,16 @@ __device__ __forceinline__ int64_t rl64(int64_t v, int src) {
 // Per wave tile of consecutive whole blocks (<= 64 padded rows):
 //  1. element phase: the tile's real rows are one contiguous run of
 //     rows x M doubles; lane l takes elements l, l + 64, ... (UPD: x += alpha
-//     p, r -= alpha q) and drops r, in FP64 and as its FP32 copy, into LDS
+//     p, r -= alpha q) and drops r (FP64) into LDS
 //     at [padded row][column] (padding rows and columns >= M stay zero);
 //  2. each 16-row tile of each block takes B/4 matrix-core steps with the
 //     LDS columns as the B operand, results to LDS;
-//  3. lane l sums (r, r) and (r, z) of padded row l per column from LDS;
+//  3. (r, r) and (r, z) per column from LDS: lane l takes column l mod 8;
 //  4. element phase: z back to HBM, contiguous.
 template <bool UPD>
-__device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int kend, int rs, int64_t v0, int M,
-                                              const double *alpha_g, float *r32, double *r64, double *zt,
-                                              double (&rr)[kBCols], double (&rz)[kBCols]) {
+__device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int kend, int rs, int64_t v0, int64_t xv0,
+                                              int M, const double *alpha_g, double *r64, double *zt,
+                                              double &rr, double &rz) {
   const int lane = threadIdx.x & 63;
   // per element-slot column and alpha: element e = pass * 64 + lane has
   // column (e mod M); 64 mod M shifts it by the same amount every pass
@@ -386,19 +447,19 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
 #pragma unroll
     for (int c = 0; c < kBCols; ++c) {
       r64[lane * kBCols + c] = 0.0;
-      r32[lane * kBCols + c] = 0.0f;
     }
     bwave_lds_sync();
     const int E = nreal * M;
     const int64_t base = v0 + (int64_t)(R0 - rs) * M;
+    const int64_t xbase = xv0 + (int64_t)(R0 - rs) * M;
     for (int e = lane; e < E; e += 64) {
       const int row = div_small(e, M);
       const int c = e - row * M;
       double rv;
       if (UPD) {
-        const double pv = a.p[base + e], qv = a.q[base + e], xv = a.x[base + e], r0v = a.r[base + e];
+        const double pv = a.p[base + e], qv = a.q[base + e], xv = a.x[xbase + e], r0v = a.r[base + e];
         const double al = alpha_g[c];
-        a.x[base + e] = fma(al, pv, xv);
+        a.x[xbase + e] = fma(al, pv, xv);
         rv = fma(-al, qv, r0v);
         a.r[base + e] = rv;
       } else {
@@ -409,7 +470,6 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
       const int cb_i = i == 0 ? cbo[0] : i == 1 ? cbo[1] : i == 2 ? cbo[2] : cbo[3];
       const int lr = row - bs_i + cb_i;
       r64[lr * kBCols + c] = rv;
-      r32[lr * kBCols + c] = __double2float_rn(rv);
     }
     bwave_lds_sync();
     // 2. block products
@@ -419,31 +479,24 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
       const uint8_t *blk = a.map.base + rl64(moff, i);
       const double sc = bcast(msc, i);
       const int cb = cbo[i];
-      for (int mt = 0; mt < B / 16; ++mt) {
-        const float *b32 = r32 + cb * kBCols;
-        const double *b64 = r64 + cb * kBCols;
-        double *zb = zt + cb * kBCols;
-        switch (B) {
-          case 16: bmtile_dispatch<16>(prec, blk, sc, mt, b32, b64, zb, lane); break;
-          case 32: bmtile_dispatch<32>(prec, blk, sc, mt, b32, b64, zb, lane); break;
-          case 48: bmtile_dispatch<48>(prec, blk, sc, mt, b32, b64, zb, lane); break;
-          default: bmtile_dispatch<64>(prec, blk, sc, mt, b32, b64, zb, lane); break;
-        }
-      }
+      bblock(B, prec, blk, sc, r64 + cb * kBCols, zt + cb * kBCols, lane);
     }
     bwave_lds_sync();
-    // 3. per-column dots over the real rows of the tile (lane = LDS row)
-    const int li = (lane >= cbo[1] && nk > 1) + (lane >= cbo[2] && nk > 2) + (lane >= cbo[3] && nk > 3);
-    const int lb_start = li == 0 ? cbo[0] : li == 1 ? cbo[1] : li == 2 ? cbo[2] : cbo[3];
-    const int lb_rows = (li + 1 < nk ? (li == 0 ? bst[1] : li == 1 ? bst[2] : bst[3]) : nreal) -
-                        (li == 0 ? bst[0] : li == 1 ? bst[1] : li == 2 ? bst[2] : bst[3]);
-    if (lane < cum && lane - lb_start < lb_rows) {
-#pragma unroll
-      for (int c = 0; c < kBCols; ++c) {
-        const double rv = r64[lane * kBCols + c];
-        const double zv = zt[lane * kBCols + c];
-        rr[c] = fma(rv, rv, rr[c]);
-        rz[c] = fma(rv, zv, rz[c]);
+    // 3. per-column dots over the real rows of the tile: lane l sums column
+    //    l mod 8 over LDS rows l / 8, l / 8 + 8, ...
+    {
+      const int c = lane & 7;
+      for (int lr = lane >> 3; lr < cum; lr += 8) {
+        const int li = (lr >= cbo[1] && nk > 1) + (lr >= cbo[2] && nk > 2) + (lr >= cbo[3] && nk > 3);
+        const int lb_start = li == 0 ? cbo[0] : li == 1 ? cbo[1] : li == 2 ? cbo[2] : cbo[3];
+        const int lb_rows = (li + 1 < nk ? (li == 0 ? bst[1] : li == 1 ? bst[2] : bst[3]) : nreal) -
+                            (li == 0 ? bst[0] : li == 1 ? bst[1] : li == 2 ? bst[2] : bst[3]);
+        if (c < M && lr - lb_start < lb_rows) {
+          const double rv = r64[lr * kBCols + c];
+          const double zv = zt[lr * kBCols + c];
+          rr = fma(rv, rv, rr);
+          rz = fma(rv, zv, rz);
+        }
       }
     }
     // 4. z to HBM
@@ -460,29 +513,27 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
   }
 }
 
-__device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M, float *r32, double *r64,
+__device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M, double *r64,
                                              double *zt) {
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ach_sys[ch]);
   const int c0 = a.t.sys_col[s];
-  double rr[kBCols], rz[kBCols];
+  double rr = 0.0, rz = 0.0;
+  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], a.t.sys_xvec[s], M,
+                      a.alpha + c0, r64, zt, rr, rz);
+  // column l mod 8 lives in lanes l, l + 8, ..., l + 56
 #pragma unroll
-  for (int c = 0; c < kBCols; ++c) rr[c] = rz[c] = 0.0;
-  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], M, a.alpha + c0,
-                      r32, r64, zt, rr, rz);
-#pragma unroll
-  for (int c = 0; c < kBCols; ++c) {
-    const double t1 = wave_sum(rr[c]);
-    const double t2 = wave_sum(rz[c]);
-    if (lane == c) {
-      a.part[(int64_t)ch * 2 * kBCols + c] = t1;
-      a.part[(int64_t)ch * 2 * kBCols + kBCols + c] = t2;
-    }
+  for (int o = 8; o < 64; o <<= 1) {
+    rr += __shfl_xor(rr, o, 64);
+    rz += __shfl_xor(rz, o, 64);
+  }
+  if (lane < kBCols) {
+    a.part[(int64_t)ch * 2 * kBCols + lane] = rr;
+    a.part[(int64_t)ch * 2 * kBCols + kBCols + lane] = rz;
   }
 }
 
 __global__ __launch_bounds__(256) void bapply_kernel(BApplyArgs a) {
-  __shared__ float r32s[4][kBWaveRows * kBCols];
   __shared__ double r64s[4][kBWaveRows * kBCols];
   __shared__ double zts[4][kBWaveRows * kBCols];
   if (*a.n_active == 0) return;
@@ -491,7 +542,7 @@ __global__ __launch_bounds__(256) void bapply_kernel(BApplyArgs a) {
   const int ce = a.sched[w + 1];
   for (int ch = a.sched[w]; ch < ce; ++ch) {
     const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ach_sys[ch]]);
-    bapply_chunk(a, ch, m, r32s[wv], r64s[wv], zts[wv]);
+    bapply_chunk(a, ch, m, r64s[wv], zts[wv]);
   }
 }
 
@@ -499,15 +550,12 @@ __global__ __launch_bounds__(256) void bapply_kernel(BApplyArgs a) {
 // of the handle's partition, grid-stride.
 __global__ __launch_bounds__(256) void bapply_multi_kernel(BApplyArgs a, const int32_t *tile_blk, int ntiles,
                                                            int m) {
-  __shared__ float r32s[4][kBWaveRows * kBCols];
   __shared__ double r64s[4][kBWaveRows * kBCols];
   __shared__ double zts[4][kBWaveRows * kBCols];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double rr[kBCols], rz[kBCols];
-#pragma unroll
-  for (int c = 0; c < kBCols; ++c) rr[c] = rz[c] = 0.0;
+  double rr = 0.0, rz = 0.0;
   for (int t = blockIdx.x * 4 + wv; t < ntiles; t += gridDim.x * 4)
-    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, m, nullptr, r32s[wv], r64s[wv], zts[wv], rr, rz);
+    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, 0, m, nullptr, r64s[wv], zts[wv], rr, rz);
 }
 
 // ------------------------------------------------------- per-system scalars
@@ -604,21 +652,32 @@ __global__ __launch_bounds__(256) void breduce_rz_kernel(BTables t, BState st, c
   }
 }
 
-__global__ __launch_bounds__(256) void binit_kernel(int64_t len, double *x, double *r, const double *b, double *p,
+// x = 0 and r = b per system (caller layout -> solver layout), p = q = 0,
+// column state reset. blockIdx.y is the system.
+__global__ __launch_bounds__(256) void binit_kernel(BTables t, double *x, double *r, const double *b, double *p,
                                                     double *q, int ncols, BState st) {
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
-    x[i] = 0.0;
-    r[i] = b[i];
-    p[i] = 0.0;
-    q[i] = 0.0;
+  const int s = blockIdx.y;
+  const int64_t xo = t.sys_xvec[s], vo = t.sys_vec[s];
+  const int64_t len = t.sys_xvec[s + 1] - xo, plen = t.sys_vec[s + 1] - vo;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < plen; i += (int64_t)gridDim.x * 256) {
+    if (i < len) {
+      x[xo + i] = 0.0;
+      r[vo + i] = b[xo + i];
+    } else {
+      r[vo + i] = 0.0;
+    }
+    p[vo + i] = 0.0;
+    q[vo + i] = 0.0;
   }
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < ncols; c += gridDim.x * 256) {
-    st.rho[c] = st.alpha[c] = st.beta[c] = st.rnorm0[c] = 0.0;
-    st.relres[c] = INFINITY;
-    st.iter[c] = 0;
-    st.status[c] = BS_RUNNING;
+  if (s == 0) {
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < ncols; c += gridDim.x * 256) {
+      st.rho[c] = st.alpha[c] = st.beta[c] = st.rnorm0[c] = 0.0;
+      st.relres[c] = INFINITY;
+      st.iter[c] = 0;
+      st.status[c] = BS_RUNNING;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st.n_active = ncols;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *st.n_active = ncols;
 }
 
 // ---------------------------------------------------------------- host side
@@ -629,7 +688,8 @@ struct BPlan {
   int32_t S = 0, ncols = 0;
   int64_t veclen = 0;
   std::vector<int32_t> sys_row, sys_m, sys_col, sys_ch, sys_ach, ch_row0, ch_sys, ach_blk, ach_sys;
-  std::vector<int64_t> sys_vec;
+  std::vector<int64_t> sys_vec, sys_xvec;
+  int64_t xlen = 0;
   std::vector<double> ch_cost, ach_cost;      // modelled HBM bytes of each chunk
 };
 
@@ -643,15 +703,20 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
   pl.sys_m.assign(sys_m, sys_m + S);
   pl.sys_col.resize(S + 1);
   pl.sys_vec.resize(S + 1);
+  pl.sys_xvec.resize(S + 1);
   pl.sys_col[0] = 0;
   pl.sys_vec[0] = 0;
+  pl.sys_xvec[0] = 0;
   for (int s = 0; s < S; ++s) {
     if (sys_row[s + 1] <= sys_row[s] || sys_m[s] < 1 || sys_m[s] > kBCols) return BJAC_EINVAL;
     pl.sys_col[s + 1] = pl.sys_col[s] + sys_m[s];
-    pl.sys_vec[s + 1] = pl.sys_vec[s] + (int64_t)(sys_row[s + 1] - sys_row[s]) * sys_m[s];
+    const int64_t len = (int64_t)(sys_row[s + 1] - sys_row[s]) * sys_m[s];
+    pl.sys_xvec[s + 1] = pl.sys_xvec[s] + len;
+    pl.sys_vec[s + 1] = pl.sys_vec[s] + ((len + 7) & ~int64_t(7));
   }
   pl.ncols = pl.sys_col[S];
   pl.veclen = pl.sys_vec[S];
+  pl.xlen = pl.sys_xvec[S];
   const double nnz_row = A && A->n > 0 ? (double)A->nnz / (double)A->n : 7.0;
   // SpMV chunks: row ranges of at most chunk_rows inside one system
   pl.sys_ch.assign(1, 0);
@@ -749,7 +814,7 @@ struct BWs {
   double *rho, *alpha, *beta, *rnorm0, *relres;
   int32_t *iter, *status, *n_active;
   int32_t *tabs;   // every int32 table, then both wave schedules
-  int64_t *sys_vec;
+  int64_t *sys_vec, *sys_xvec;
   size_t bytes;
 };
 
@@ -778,6 +843,7 @@ static BWs carve_b(void *ws, const BPlan &p) {
   w.n_active = c.take<int32_t>(1);
   w.tabs = c.take<int32_t>(tabs_len(p));
   w.sys_vec = c.take<int64_t>(p.sys_vec.size());
+  w.sys_xvec = c.take<int64_t>(p.sys_xvec.size());
   w.bytes = c.used;
   return w;
 }
@@ -838,6 +904,8 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
   MPB_HIP(hipMemcpyAsync(c.w.tabs, tabs.data(), tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MPB_HIP(hipMemcpyAsync(c.w.sys_vec, pl.sys_vec.data(), pl.sys_vec.size() * sizeof(int64_t),
                          hipMemcpyHostToDevice, s));
+  MPB_HIP(hipMemcpyAsync(c.w.sys_xvec, pl.sys_xvec.data(), pl.sys_xvec.size() * sizeof(int64_t),
+                         hipMemcpyHostToDevice, s));
   // the host vectors above go out of scope at return: wait for the copies
   MPB_HIP(hipStreamSynchronize(s));
   BTables &t = c.t;
@@ -854,6 +922,7 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
   t.ach_blk = c.w.tabs + o_ab;
   t.ach_sys = c.w.tabs + o_as;
   t.sys_vec = c.w.sys_vec;
+  t.sys_xvec = c.w.sys_xvec;
   c.sched1 = c.w.tabs + o_s1;
   c.sched2 = c.w.tabs + o_s2;
   c.st = BState{c.w.rho, c.w.alpha, c.w.beta, c.w.rnorm0, c.w.relres, c.w.iter, c.w.status, c.w.n_active, tol, maxit};
@@ -925,7 +994,7 @@ static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) 
 // x = 0, r = b, p = q = 0, then z_0 = M^-1 r_0 through the apply kernel with
 // alpha = 0, which also yields ||r_0|| and rho_0
 static void benq_init(const BCtx &c, hipStream_t s) {
-  hipLaunchKernelGGL(binit_kernel, dim3(1024), dim3(256), 0, s, c.pl.veclen, c.x, c.w.r, c.b, c.w.pa, c.w.q,
+  hipLaunchKernelGGL(binit_kernel, dim3(64, c.t.S), dim3(256), 0, s, c.t, c.x, c.w.r, c.b, c.w.pa, c.w.q,
                      c.pl.ncols, c.st);
   benq_apply(c, c.w.pa, 1, s);
 }
