@@ -86,6 +86,31 @@ def cpu_baseline(p, iters_hint, budget_iters=8):
 METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP64"
 
 
+def stream_ceilings(dev, gib=1):
+    """Achievable streaming rates of this GPU, measured with PyTorch's own
+    kernels on gib-GiB FP64 tensors: a reduction (read only), a fill (write
+    only) and a copy (read + write). Context for the roofline fraction: the
+    hot kernels mix reads and writes like the copy."""
+    import torch
+    n = gib * (2 ** 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("read", lambda: a.sum(), n * 8), ("write", lambda: b.fill_(2.0), n * 8),
+                             ("copy", lambda: b.copy_(a), 2 * n * 8)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name] = nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_diff3d(args):
     import numpy as np
     import torch
@@ -173,6 +198,9 @@ def bench_diff3d(args):
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
         cpu = cpu_baseline(p, r16.iters)
+    ceil = stream_ceilings(dev)
+    roofline["copy_ceiling_gbs"] = ceil["copy"]
+    roofline["frac_of_copy_ceiling"] = dk["gbs"] / ceil["copy"]
 
     line = {
         "metric": METRIC,
@@ -188,7 +216,7 @@ def bench_diff3d(args):
         "us_per_iter": iter_us16, "bytes_per_iter": iter_bytes,
         "iter_gbs": iter_bytes / (iter_us16 * 1e-6) / 1e9,
         "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
-        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
+        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu, "stream_ceilings_gbs": ceil,
     }
     return line
 
