@@ -84,6 +84,9 @@ def cpu_baseline(p, iters_hint, budget_iters=8):
 
 
 METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP64"
+# every timed solve checks ||b - A x|| / ||b|| <= tol in FP64 on the device and
+# restarts from the true residual (at most this many times) when it is above
+VERIFY = 3
 
 
 def stream_ceilings(dev, gib=1):
@@ -134,7 +137,7 @@ def bench_diff3d(args):
         e0.record()
         M = mb.BlockJacobi(A, p.block_ptr, policy)
         e1.record()
-        res = solver.solve(A, M, b, tol=tol, maxit=maxit, profile=profile)
+        res = solver.solve(A, M, b, tol=tol, maxit=maxit, profile=profile, verify=0 if profile else VERIFY)
         e2.record()
         return M, res, (e0, e1, e2)
 
@@ -210,6 +213,7 @@ def bench_diff3d(args):
         "config": {"workload": f"diff3d_loguniform_{args.N}^3_b32", "n": n, "nnz": nnz, "blocks": nb,
                    "block_rows": 32, "precision_map": "fp16 fixed (fMP)", "tol": tol, "seed": 0},
         "iters": r16.iters, "iters_fp64": r64.iters, "delay_iters": r16.iters - r64.iters,
+        "restarts": r16.restarts, "restarts_fp64": r64.restarts, "true_relres_device": r16.true_relres,
         "setup_ms": setup16, "solve_ms": solve16, "fp64_ms_per_step": ms64, "fp64_setup_ms": setup64,
         "fp64_solve_ms": solve64, "speedup_vs_fp64": ms64 / ms16,
         "true_relres": true16, "true_relres_fp64": true64,
@@ -439,7 +443,7 @@ def bench_policies(args):
         e0.record()
         M = mb.BlockJacobi(A, p.block_ptr, policy)
         e1.record()
-        res = solver.solve(A, M, b, tol=p.tol, maxit=p.maxit, profile=profile)
+        res = solver.solve(A, M, b, tol=p.tol, maxit=p.maxit, profile=profile, verify=0 if profile else VERIFY)
         e2.record()
         return M, res, (e0, e1, e2)
 
@@ -454,7 +458,8 @@ def bench_policies(args):
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
         M, res, ev = runs[-1]
         info = M.info()
-        rows[name] = {"ms_per_step": ms, "iters": res.iters, "status": res.status,
+        rows[name] = {"ms_per_step": ms, "iters": res.iters, "status": res.status, "restarts": res.restarts,
+                      "true_relres_device": res.true_relres,
                       "setup_ms": float(np.median([r[2][0].elapsed_time(r[2][1]) for r in runs])),
                       "solve_ms": float(np.median([r[2][1].elapsed_time(r[2][2]) for r in runs])),
                       "blocks_per_prec": info["blocks_per_prec"], "low_bytes": info["low_bytes"],

@@ -121,7 +121,11 @@ typedef struct {
                                     the application used the FP64 map          */
   int32_t profile;               /* 1: launch without graphs, time every kernel
                                     with HIP events on the stream (stats.*_ms) */
-  int32_t reserved;
+  int32_t verify;                /* > 0: when the recursive relres reaches tol,
+                                    recompute ||b - A x|| / ||b|| in FP64; if it
+                                    exceeds tol, replace r by b - A x and
+                                    restart CG (p = z), at most `verify` times
+                                    (then BJAC_NOT_CONVERGED). Graph mode only. */
 } bjac_solve_opts;
 
 typedef struct {
@@ -135,7 +139,8 @@ typedef struct {
   /* profile mode only: summed kernel durations over the iterations that ran */
   double spmv_ms, apply_ms, update_ms;
   int32_t n_spmv, n_apply, n_update;
-  int32_t reserved;
+  int32_t restarts;              /* verify: residual replacements performed    */
+  double true_relres;            /* verify: last FP64 ||b - A x|| / ||b||, else -1 */
 } bjac_stats;
 
 /* ---- library ------------------------------------------------------------ */

@@ -55,14 +55,15 @@ class bjac_info(C.Structure):
 class bjac_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("relres_hist", C.c_void_p), ("high_hist", C.c_void_p), ("profile", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("verify", C.c_int32)]
 
 
 class bjac_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double), ("rnorm0", C.c_double),
                 ("high_applications", C.c_int32), ("graph_launches", C.c_int32), ("solve_ms", C.c_double),
                 ("spmv_ms", C.c_double), ("apply_ms", C.c_double), ("update_ms", C.c_double),
-                ("n_spmv", C.c_int32), ("n_apply", C.c_int32), ("n_update", C.c_int32), ("reserved", C.c_int32)]
+                ("n_spmv", C.c_int32), ("n_apply", C.c_int32), ("n_update", C.c_int32), ("restarts", C.c_int32),
+                ("true_relres", C.c_double)]
 
 
 class bjac_batch_cfg(C.Structure):
@@ -271,6 +272,8 @@ class SolveResult:
     relres_hist: object = None
     high_hist: object = None
     kernel_ms: dict = None        # profile mode: {"spmv": (total_ms, launches), ...}
+    restarts: int = 0             # verify: residual replacements
+    true_relres: float = -1.0     # verify: FP64 ||b - A x|| / ||b|| computed on the device
 
 
 class Solver:
@@ -284,20 +287,20 @@ class Solver:
         self.n = n
 
     def solve(self, A: DeviceCSR, M: BlockJacobi, b, tol=1e-10, maxit=5000, chunk=16, history=False, x=None,
-              raise_on_error=True, profile=False) -> SolveResult:
+              raise_on_error=True, profile=False, verify=0) -> SolveResult:
         torch = _torch()
         x = torch.empty_like(b) if x is None else x
         rh = torch.empty(maxit, dtype=torch.float64, device=b.device) if history else None
         hh = torch.zeros(maxit + 1, dtype=torch.uint8, device=b.device) if history else None
         opts = bjac_solve_opts(tol, maxit, chunk, rh.data_ptr() if rh is not None else None,
-                               hh.data_ptr() if hh is not None else None, 1 if profile else 0, 0)
+                               hh.data_ptr() if hh is not None else None, 1 if profile else 0, int(verify))
         st = bjac_stats()
         rc = load().pcg_solve(C.byref(A.c), M.h, _ptr(b), _ptr(x), C.byref(opts), _ptr(self.ws),
                               self.ws.numel(), C.byref(st), _stream())
         if rc < 0 and (raise_on_error or rc != EBREAKDOWN):
             raise MpbjacError(rc, "pcg_solve")
         res = SolveResult(x, st.iters, rc, st.relres, st.rnorm0, st.high_applications, st.graph_launches,
-                          st.solve_ms)
+                          st.solve_ms, restarts=st.restarts, true_relres=st.true_relres)
         if profile:
             res.kernel_ms = {"spmv": (st.spmv_ms, st.n_spmv), "apply": (st.apply_ms, st.n_apply),
                              "update": (st.update_ms, st.n_update)}

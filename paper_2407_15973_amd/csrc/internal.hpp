@@ -28,6 +28,7 @@ struct alignas(64) PcgState {
   double rnorm0;     // ||r_0|| = ||b||
   double relres;     // ||r|| / ||r_0|| seen by the next preconditioner application
   double tol, adp_tol;
+  double rr_true;    // ||b - A x||^2 of the last verification
   int32_t iter;      // x updates done; -1 before the first application
   int32_t maxit;
   int32_t status;    // 0 running, 1 converged, 2 maxit, -3 breakdown
@@ -35,7 +36,7 @@ struct alignas(64) PcgState {
   int32_t temporal;
   int32_t n_high;    // applications that used the FP64 map
   uint32_t ticket_a, ticket_b, ticket_c;
-  int32_t pad_;
+  int32_t restart;   // 1: the next application restarts CG from a replaced residual
   double *relres_hist;
   uint8_t *high_hist;
 };

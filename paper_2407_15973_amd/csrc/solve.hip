@@ -375,7 +375,10 @@ __device__ __forceinline__ bool temporal_high(const PcgState *st, double relres)
 // convergence, the switch decision for the next application.
 __device__ __forceinline__ void after_update(PcgState *st, double rr) {
   st->rr = rr;
-  if (st->iter < 0) {
+  if (st->restart) {
+    // r was replaced by b - A x (alpha = 0, no x update): new relres only
+    st->relres = sqrt(rr) / st->rnorm0;
+  } else if (st->iter < 0) {
     st->rnorm0 = sqrt(rr);
     st->iter = 0;
     st->relres = INFINITY;
@@ -401,8 +404,10 @@ __device__ __forceinline__ void after_apply(PcgState *st, double rz, int used_hi
     st->status = ST_BREAKDOWN;
     return;
   }
-  st->beta = st->iter == 0 ? 0.0 : rz / st->rho;
+  // a restart begins a new direction sequence: p = z
+  st->beta = (st->iter == 0 || st->restart) ? 0.0 : rz / st->rho;
   st->rho = rz;
+  st->restart = 0;
   if (st->iter >= st->maxit) st->status = ST_MAXIT;
 }
 
@@ -676,6 +681,41 @@ __global__ __launch_bounds__(256) void pcg_fill_kernel(int64_t n, double *x, dou
   }
 }
 
+// r = b - A x in FP64 with per-workgroup partial sums of r^2 (true-residual
+// verification; one thread per row, grid-stride).
+__global__ __launch_bounds__(256) void resid_kernel(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                                                    const double *x, const double *b, double *r, double *part) {
+  __shared__ double sh[4];
+  double acc2 = 0.0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    double ax = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) ax = fma(v[k], x[ci[k]], ax);
+    const double ri = b[i] - ax;
+    r[i] = ri;
+    acc2 = fma(ri, ri, acc2);
+  }
+  const double t = block_sum(acc2, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Sums the partials in order; if ||b - A x|| / ||b|| > tol, CG continues from
+// the replaced residual: the next application runs with alpha = 0 and starts
+// a new direction sequence.
+__global__ __launch_bounds__(256) void restart_kernel(PcgState *st, const double *part, int G) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < G; i += 256) v += part[i];
+  const double rr = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    st->rr_true = rr;
+    if (st->status == ST_CONVERGED && sqrt(rr) > st->tol * st->rnorm0 && st->iter < st->maxit) {
+      st->status = ST_RUNNING;
+      st->alpha = 0.0;
+      st->restart = 1;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void round_kernel(const double *in, uint8_t *out, int64_t count, int prec,
                                                     double inv_scale) {
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
@@ -798,7 +838,7 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
 }
 
 struct SolveWs {
-  double *r, *z, *pa, *pb, *q, *part1, *part2;
+  double *r, *z, *pa, *pb, *q, *part1, *part2, *part3;
   PcgState *st;
   size_t bytes;
 };
@@ -813,6 +853,7 @@ static SolveWs carve_solve(void *ws, int64_t n) {
   w.q = c.take<double>(n);
   w.part1 = c.take<double>(3 * kMaxGrid);  // spmv slots, then update/apply slot pairs
   w.part2 = w.part1 + kMaxGrid;
+  w.part3 = c.take<double>(kMaxGrid);      // true-residual partials
   w.st = c.take<PcgState>(1);
   w.bytes = c.used;
   return w;
@@ -989,7 +1030,8 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   }
 
   PcgState hs{};
-  int launches = 0;
+  int launches = 0, restarts = 0;
+  bool verified = false;
   const int max_launches = opts->maxit / chunk + 2;
   MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   MPB_HIP(hipStreamSynchronize(s));
@@ -998,9 +1040,29 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
     int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof);
     if (rc) return rc;
   } else {
-    while (hs.status == ST_RUNNING && launches < max_launches) {
-      MPB_HIP(hipGraphLaunch(M->gexec, s));
-      ++launches;
+    for (;;) {
+      while (hs.status == ST_RUNNING && launches < max_launches + restarts) {
+        MPB_HIP(hipGraphLaunch(M->gexec, s));
+        ++launches;
+        MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        MPB_HIP(hipStreamSynchronize(s));
+      }
+      if (hs.status != ST_CONVERGED || !opts->verify) break;
+      // FP64 check of the recursive residual: r = b - A x; restart if needed
+      const int G = (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (A->n + 255) / 256));
+      hipLaunchKernelGGL(resid_kernel, dim3(G), dim3(256), 0, s, A->n, A->row_ptr, A->col_idx, A->val, x, b, w.r,
+                         w.part3);
+      hipLaunchKernelGGL(restart_kernel, dim3(1), dim3(256), 0, s, w.st, (const double *)w.part3, G);
+      MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+      MPB_HIP(hipStreamSynchronize(s));
+      verified = true;
+      if (hs.status != ST_RUNNING || restarts >= opts->verify) {
+        if (hs.status == ST_RUNNING) hs.status = ST_MAXIT;  // restarts exhausted: report not converged
+        break;
+      }
+      ++restarts;
+      enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
+      MPB_HIP(hipGetLastError());
       MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
       MPB_HIP(hipStreamSynchronize(s));
     }
@@ -1032,7 +1094,8 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
     stats->n_spmv = prof.n[0];
     stats->n_apply = prof.n[1];
     stats->n_update = prof.n[2];
-    stats->reserved = 0;
+    stats->restarts = restarts;
+    stats->true_relres = verified && hs.rnorm0 > 0.0 ? sqrt(hs.rr_true) / hs.rnorm0 : -1.0;
   }
   return rc;
 }

@@ -38,6 +38,6 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(binding.bjac_csr) == 40
     assert C.sizeof(binding.bjac_policy) == 56
     assert C.sizeof(binding.bjac_solve_opts) == 40
-    assert C.sizeof(binding.bjac_stats) == 80
+    assert C.sizeof(binding.bjac_stats) == 88
     assert C.sizeof(binding.bjac_info) == 64
     assert C.sizeof(binding.bjac_batch_cfg) == 16

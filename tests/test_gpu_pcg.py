@@ -163,6 +163,39 @@ def test_graph_reuse_across_right_hand_sides():
         assert OP.true_relres(A, r.x.cpu().numpy(), bb) <= 2e-10
 
 
+@pytest.mark.parametrize("tol", [1e-10, 1e-12, 1e-15])
+def test_verify_true_residual_and_restart(tol):
+    # verify: when the recursive relres reaches tol, ||b - A x|| / ||b|| is
+    # recomputed in FP64; above tol, r is replaced and CG restarts. Either the
+    # FP64 true residual meets tol or every allowed restart was spent.
+    rng = np.random.default_rng(3)
+    A = gen.diffusion3d(gen.kappa_subcube_jumps(20, rng), aniso=(1e3, 1.0, 1.0))
+    bp = gen.uniform_blocks(A.n, 48)
+    b = gen.rhs_uniform(A.n, rng)
+    Ad = mb.DeviceCSR(A, dev())
+    # (an FP16 map of this small jump problem loses definiteness: breakdown)
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP32))
+    S = mb.Solver(A.n, dev())
+    r = S.solve(Ad, M, tensor(b), tol=tol, maxit=4000, verify=2, raise_on_error=False)
+    x = r.x.cpu().numpy()
+    host = OP.true_relres(A, x, b)
+    assert r.true_relres > 0
+    # both sides round A x in their own order: |delta ||b - A x||| <= 2 gamma_7 || |A| |x| ||
+    S_abs = abs(A.to_scipy())
+    bound = 2 * gamma(7, 2.0 ** -53) * np.linalg.norm(S_abs @ np.abs(x)) / np.linalg.norm(b)
+    assert abs(r.true_relres - host) <= bound + 1e-6 * host
+    if r.status == mb.OK:
+        assert r.true_relres <= tol and host <= tol + bound
+    else:
+        assert r.status == mb.NOT_CONVERGED and r.restarts == 2
+        assert host <= 1e-9
+    print(f"tol {tol:g}: status {r.status}, iterations {r.iters}, restarts {r.restarts}, true relres {host:.3e}")
+    # without verification the solve stops on the recursive residual alone
+    r0 = S.solve(Ad, M, tensor(b), tol=tol, maxit=4000, raise_on_error=False)
+    assert r0.restarts == 0 and r0.true_relres == -1.0
+    assert r0.iters <= r.iters
+
+
 def test_error_paths():
     A, bp, b = _amp_case()
     r, _ = _gpu_solve(A, bp, b, mb.Policy(), 1e-10, 1)
