@@ -175,6 +175,36 @@ int bjac_get_features(const bjac_handle *h, float *features);
  * which = 0: low map, 1: all-FP64 map (temporal handles only). */
 int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block, double *out, double *scale);
 
+/* ---- paper-mode BJAC(k, t) (Sec. 3.1 eq. 3-1 to 3-3; Sec. 3.2) ----------
+ * The preconditioner as the paper defines it for large blocks (one per
+ * process there): k outer steps z_1 = Dhat^-1 r, z_{j+1} = z_j + Dhat^-1
+ * (r - A z_j), where Dhat^-1 applies t point-Jacobi sweeps y <- y + D^-1 (v -
+ * D_b y) from y = 0 inside every diagonal block (D_b: the entries of A whose
+ * row and column lie in the same block; D: its diagonal). Nothing is
+ * inverted; blocks are contiguous row ranges of any size (block_ptr as for
+ * bjac_setup, no size limit). low != 0: every operation of the application
+ * in FP32 (FP32 copy of A's values and of 1/a_ii, r rounded to FP32 on entry,
+ * z widened on exit; Algorithm 3.1's fMP); low = 0: FP64. temporal/adp_tol:
+ * Algorithms 3.2 / 3.3 between the FP64 and FP32 applications.
+ * The handle keeps A's device pointers: A must stay alive and unchanged while
+ * the handle is used (bjac_apply, pcg_solve with the same A). bjac_apply's
+ * `which` selects the low (0) or FP64 (1) application. bjac_get_features and
+ * bjac_get_block return BJAC_EINVAL for these handles. A non-positive
+ * diagonal entry gives BJAC_ENOTSPD. */
+typedef struct {
+  int32_t k;             /* outer steps (1..64)                            */
+  int32_t t;             /* Jacobi sweeps per block solve (1..64)          */
+  int32_t low;           /* 1: FP32 application, 0: FP64                   */
+  int32_t temporal;      /* bjac_temporal                                  */
+  double adp_tol;        /* threshold of the temporal switch               */
+} bjac_poly_params;
+
+int bjac_poly_setup_query(const bjac_csr *A, const int32_t *block_ptr, int32_t nb,
+                          const bjac_poly_params *params, size_t *workspace_bytes);
+int bjac_poly_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t nb,
+                    const bjac_poly_params *params, void *workspace, size_t workspace_bytes,
+                    void *stream, bjac_handle **out);
+
 /* ---- z = M^-1 r (eq. 3-1, k = 1; Algorithm 3.1) --------------------------
  * r, z: device FP64 vectors of length n (distinct). which = 0 applies the
  * low map, 1 the all-FP64 map (temporal handles; for others both are the

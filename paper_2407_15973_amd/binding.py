@@ -32,6 +32,7 @@ SYMBOLS = (
     "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
     "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
+    "bjac_poly_setup_query", "bjac_poly_setup",
 )
 
 
@@ -64,6 +65,11 @@ class bjac_stats(C.Structure):
                 ("spmv_ms", C.c_double), ("apply_ms", C.c_double), ("update_ms", C.c_double),
                 ("n_spmv", C.c_int32), ("n_apply", C.c_int32), ("n_update", C.c_int32), ("restarts", C.c_int32),
                 ("true_relres", C.c_double)]
+
+
+class bjac_poly_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("t", C.c_int32), ("low", C.c_int32), ("temporal", C.c_int32),
+                ("adp_tol", C.c_double)]
 
 
 class bjac_batch_cfg(C.Structure):
@@ -104,6 +110,8 @@ def load(path: str = LIB_PATH):
         "bjac_mlp_backward": (C.c_int, [vp, vp, vp, i32, vp, vp, vp, sz, vp]),
         "bjac_mlp_adam": (C.c_int, [vp, vp, vp, vp, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
         "bjac_apply_multi": (C.c_int, [vp, vp, vp, i32, vp]),
+        "bjac_poly_setup_query": (C.c_int, [P(bjac_csr), vp, i32, P(bjac_poly_params), P(sz)]),
+        "bjac_poly_setup": (C.c_int, [P(bjac_csr), vp, i32, P(bjac_poly_params), vp, sz, vp, P(vp)]),
         "pcg_batched_workspace_query": (C.c_int, [P(bjac_csr), vp, i32, vp, vp, P(bjac_batch_cfg), P(sz)]),
         "pcg_solve_batched": (C.c_int, [P(bjac_csr), vp, i32, vp, vp, vp, vp, P(bjac_solve_opts),
                                         P(bjac_batch_cfg), vp, sz, vp, vp, vp, P(bjac_stats), vp]),
@@ -257,6 +265,28 @@ class BlockJacobi:
         Z = _torch().empty_like(R)
         _check(load().bjac_apply_multi(self.h, _ptr(R), _ptr(Z), R.shape[1], _stream()), "bjac_apply_multi")
         return Z
+
+
+class PaperBJAC(BlockJacobi):
+    """Handle of the paper-mode BJAC(k, t): k outer steps, t Jacobi sweeps per
+    block solve, FP32 (low) or FP64 application; any block sizes. The device
+    CSR must outlive the handle."""
+
+    def __init__(self, A: DeviceCSR, block_ptr, k=2, t=2, low=True, temporal=TEMPORAL_NONE, adp_tol=math.inf):
+        torch = _torch()
+        L = load()
+        self.A = A
+        self.block_ptr = np.ascontiguousarray(block_ptr, dtype=np.int32)
+        self.nb = len(self.block_ptr) - 1
+        self.params = bjac_poly_params(int(k), int(t), 1 if low else 0, int(temporal), float(adp_tol))
+        nbytes = C.c_size_t()
+        _check(L.bjac_poly_setup_query(C.byref(A.c), self.block_ptr.ctypes.data, self.nb, C.byref(self.params),
+                                       C.byref(nbytes)), "bjac_poly_setup_query")
+        self.ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=A.val.device)
+        h = C.c_void_p()
+        _check(L.bjac_poly_setup(C.byref(A.c), self.block_ptr.ctypes.data, self.nb, C.byref(self.params),
+                                 _ptr(self.ws), nbytes.value, _stream(), C.byref(h)), "bjac_poly_setup")
+        self.h = h
 
 
 @dataclass

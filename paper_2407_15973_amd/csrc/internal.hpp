@@ -90,6 +90,18 @@ struct bjac_handle {
   // cached PCG graph
   hipGraphExec_t gexec = nullptr;
   std::vector<uintptr_t> gkey;
+  // paper-mode BJAC(k, t) (kind 1): no stored inverses; k outer steps with t
+  // point-Jacobi sweeps inside each block, in FP32 (low) or FP64
+  int32_t kind = 0;
+  int32_t pk = 1, pt = 1, plow = 0;
+  const int32_t *prp = nullptr, *pci = nullptr;   // A as given at setup (kept alive by the caller)
+  const double *pval = nullptr;
+  int64_t pnnz = 0;
+  float *val32 = nullptr;        // [nnz] FP32 copy of A's values
+  double *dinv64 = nullptr;      // [n] 1 / a_ii
+  float *dinv32 = nullptr;       // [n]
+  int32_t *rlo = nullptr, *rhi = nullptr;  // [n] column range of the row's block
+  double *pbuf = nullptr;        // [6 n] work vectors of one application
 };
 
 namespace mpb {

@@ -618,7 +618,7 @@ extern "C" int bjac_get_tags(const bjac_handle *h, uint8_t *tags) {
 }
 
 extern "C" int bjac_get_features(const bjac_handle *h, float *features) {
-  if (!h || !features) return BJAC_EINVAL;
+  if (!h || !features || h->kind != 0) return BJAC_EINVAL;
   MPB_HIP(hipMemcpyAsync(features, h->feat, sizeof(float) * 16 * (size_t)h->nb, hipMemcpyDeviceToHost, h->stream));
   MPB_HIP(hipStreamSynchronize(h->stream));
   return BJAC_OK;
@@ -643,7 +643,7 @@ static double decode(const uint8_t *p, int prec) {
 }
 
 extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block, double *out, double *scale) {
-  if (!h || !out || block < 0 || block >= h->nb) return BJAC_EINVAL;
+  if (!h || !out || block < 0 || block >= h->nb || h->kind != 0) return BJAC_EINVAL;
   if (which == 1 && !h->off_hi) return BJAC_EINVAL;
   const int b = h->h_blk_row[block + 1] - h->h_blk_row[block];
   const int B = h->h_bpad[block];

@@ -14,6 +14,7 @@
 // that XCD's L2.
 #include <math.h>
 
+#include <algorithm>
 #include <cstring>
 #include <unordered_map>
 #include <vector>
@@ -736,6 +737,204 @@ int launch_round(const double *in, void *out, int64_t count, int prec, double sc
   return BJAC_OK;
 }
 
+// ------------------------------------------------ paper-mode BJAC(k, t)
+// Eq. 3-1 with k outer steps z_{j+1} = z_j + Dhat^-1 (r - A z_j), z_1 =
+// Dhat^-1 r, where Dhat^-1 is eq. 3-3: t point-Jacobi sweeps y <- y + D^-1 (v -
+// D_b y) from y = 0 inside every diagonal block. Every operation runs in T:
+// FP32 for the low map (Sec. 3.2: all floating-point work of M^-1(p_l) in p_l,
+// r converted on entry, z widened on exit, Algorithm 3.1), FP64 for the high
+// map. One thread per row, grid-stride.
+struct PolyArgs {
+  int64_t n;
+  const int32_t *rp, *ci;
+  const void *val;           // T values of A
+  const void *dinv;          // T reciprocals of the diagonal
+  const int32_t *rlo, *rhi;  // column range of each row's block
+  PcgState *st;              // null outside PCG
+  int want_high;             // temporal handles: launch serves the FP64 (1) or low (0) map
+  int temporal;
+};
+
+__device__ __forceinline__ bool poly_skip(const PolyArgs &a) {
+  if (!a.st) return false;
+  if (a.st->status != ST_RUNNING) return true;
+  return a.temporal && ((a.st->use_high != 0) != (a.want_high != 0));
+}
+
+// v = T(r); y = D^-1 v (the first sweep from y = 0)
+template <class T>
+__global__ __launch_bounds__(256) void poly_first_kernel(PolyArgs a, const double *r, T *v, T *y) {
+  if (poly_skip(a)) return;
+  const T *dinv = (const T *)a.dinv;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    const T vi = (T)r[i];
+    v[i] = vi;
+    y[i] = dinv[i] * vi;
+  }
+}
+
+// yout = yin + D^-1 (v - D_b yin) [+ add]: D_b keeps the entries whose column
+// lies in the row's block
+template <class T>
+__global__ __launch_bounds__(256) void poly_sweep_kernel(PolyArgs a, const T *v, const T *yin, T *yout,
+                                                         const T *add) {
+  if (poly_skip(a)) return;
+  const T *val = (const T *)a.val, *dinv = (const T *)a.dinv;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    const int lo = a.rlo[i], hi = a.rhi[i];
+    T acc = 0;
+    for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+      const int j = a.ci[k];
+      if (j >= lo && j < hi) acc += val[k] * yin[j];
+    }
+    T yi = yin[i] + dinv[i] * (v[i] - acc);
+    if (add) yi = add[i] + yi;
+    yout[i] = yi;
+  }
+}
+
+// w = v - A z; y = D^-1 w; with zout (t = 1): zout = z + y
+template <class T>
+__global__ __launch_bounds__(256) void poly_resid_kernel(PolyArgs a, const T *v, const T *z, T *w, T *y, T *zout) {
+  if (poly_skip(a)) return;
+  const T *val = (const T *)a.val, *dinv = (const T *)a.dinv;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    T acc = 0;
+    for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) acc += val[k] * z[a.ci[k]];
+    const T wi = v[i] - acc;
+    w[i] = wi;
+    const T yi = dinv[i] * wi;
+    y[i] = yi;
+    if (zout) zout[i] = z[i] + yi;
+  }
+}
+
+// z = FP64(zt); in PCG also (r, z) and the state transition after it
+template <class T>
+__global__ __launch_bounds__(256) void poly_finish_kernel(PolyArgs a, const T *zt, double *z, const double *r,
+                                                          double *part) {
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (poly_skip(a)) return;
+  double rz = 0.0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    const double zi = (double)zt[i];
+    z[i] = zi;
+    if (a.st) rz = fma(r[i], zi, rz);
+  }
+  if (!a.st) return;
+  const double brz = block_sum(rz, sh);
+  if (threadIdx.x == 0) {
+    publish(part + 2 * blockIdx.x + 1, brz);
+    flag[1] = 1;
+  }
+  if (last_workgroup(&a.st->ticket_c, flag)) {
+    const double trz = sum_partials(part + 1, gridDim.x, 2, sh, flag + 1);
+    if (threadIdx.x == 0) {
+      PcgState *st = a.st;
+      if (!flag[1]) st->status = ST_SYNC_FAIL;
+      else if (st->status == ST_RUNNING) after_apply(st, trz, a.temporal ? a.want_high : 0);
+      __hip_atomic_store(&st->ticket_c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q, (r, r) and the state transition after it
+__global__ __launch_bounds__(256) void poly_update_kernel(int64_t n, PcgState *st, double *x, double *r,
+                                                          const double *p, const double *q, double *part) {
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (st->status != ST_RUNNING) return;
+  const double alpha = st->alpha;
+  double rr = 0.0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double pv = p[i], qv = q[i], xv = x[i], r0 = r[i];
+    x[i] = fma(alpha, pv, xv);
+    const double rv = fma(-alpha, qv, r0);
+    r[i] = rv;
+    rr = fma(rv, rv, rr);
+  }
+  const double brr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    publish(part + 2 * blockIdx.x, brr);
+    flag[1] = 1;
+  }
+  if (last_workgroup(&st->ticket_b, flag)) {
+    const double trr = sum_partials(part, gridDim.x, 2, sh, flag + 1);
+    if (threadIdx.x == 0) {
+      if (!flag[1]) st->status = ST_SYNC_FAIL;
+      else after_update(st, trr);
+      __hip_atomic_store(&st->ticket_b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+static int poly_grid(int64_t n) { return (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (n + 255) / 256)); }
+
+// One application z = M^-1 r of a paper-mode handle in precision T.
+template <class T>
+static void enqueue_poly_app(const bjac_handle *M, PolyArgs a, const double *r, double *z, double *part,
+                             hipStream_t s) {
+  const int64_t n = M->n;
+  const int G = poly_grid(n);
+  a.val = sizeof(T) == 4 ? (const void *)M->val32 : (const void *)M->pval;
+  a.dinv = sizeof(T) == 4 ? (const void *)M->dinv32 : (const void *)M->dinv64;
+  T *v = (T *)M->pbuf, *w = (T *)(M->pbuf + n), *ya = (T *)(M->pbuf + 2 * n), *yb = (T *)(M->pbuf + 3 * n);
+  T *za = (T *)(M->pbuf + 4 * n), *zb = (T *)(M->pbuf + 5 * n);
+  const int t = M->pt, k = M->pk;
+  // block solve of the first outer step, ending in za
+  hipLaunchKernelGGL(poly_first_kernel<T>, dim3(G), dim3(256), 0, s, a, r, v, t == 1 ? za : ya);
+  {
+    T *in = ya, *spare = yb;
+    for (int sw = 2; sw <= t; ++sw) {
+      T *out = sw == t ? za : spare;
+      hipLaunchKernelGGL(poly_sweep_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)v, (const T *)in, out,
+                         (const T *)nullptr);
+      spare = in;
+      in = out;
+    }
+  }
+  T *zc = za;
+  for (int j = 2; j <= k; ++j) {
+    T *zn = zc == za ? zb : za;
+    hipLaunchKernelGGL(poly_resid_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)v, (const T *)zc, w, ya,
+                       t == 1 ? zn : (T *)nullptr);
+    T *in = ya, *spare = yb;
+    for (int sw = 2; sw <= t; ++sw) {
+      T *out = sw == t ? zn : spare;
+      hipLaunchKernelGGL(poly_sweep_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)w, (const T *)in, out,
+                         sw == t ? (const T *)zc : (const T *)nullptr);
+      spare = in;
+      in = out;
+    }
+    zc = zn;
+  }
+  hipLaunchKernelGGL(poly_finish_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)zc, z, r, part);
+}
+
+static PolyArgs poly_args(const bjac_handle *M, PcgState *st, int want_high) {
+  PolyArgs a{};
+  a.n = M->n;
+  a.rp = M->prp;
+  a.ci = M->pci;
+  a.rlo = M->rlo;
+  a.rhi = M->rhi;
+  a.st = st;
+  a.want_high = want_high;
+  a.temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
+  return a;
+}
+
+// the map of a paper-mode handle: low = FP32 arithmetic, high = FP64
+static void enqueue_poly_map(const bjac_handle *M, int high, PcgState *st, const double *r, double *z, double *part,
+                             hipStream_t s) {
+  const PolyArgs a = poly_args(M, st, high);
+  if (high || !M->plow)
+    enqueue_poly_app<double>(M, a, r, z, part, s);
+  else
+    enqueue_poly_app<float>(M, a, r, z, part, s);
+}
+
 // ---------------------------------------------------------------- launchers
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
                         PcgState *st, double *part, int mode, hipStream_t s) {
@@ -872,6 +1071,20 @@ static hipStream_t capture_stream() {
 // only the chosen one does work. Events bracket the launches when given.
 static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs &w, bool temporal, const double *p,
                                  hipStream_t s, hipEvent_t *ev) {
+  if (M->kind == 1) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(poly_update_kernel, dim3(poly_grid(M->n)), dim3(256), 0, s, (int64_t)M->n, w.st, x, w.r, p,
+                       (const double *)w.q, w.part2);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    if (temporal) {
+      enqueue_poly_map(M, 1, w.st, w.r, w.z, w.part2, s);
+      enqueue_poly_map(M, 0, w.st, w.r, w.z, w.part2, s);
+    } else {
+      enqueue_poly_map(M, 0, w.st, w.r, w.z, w.part2, s);
+    }
+    if (ev) (void)hipEventRecord(ev[2], s);
+    return;
+  }
   if (temporal) {
     if (ev) (void)hipEventRecord(ev[0], s);
     launch_apply(M, M_UPD, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
@@ -950,6 +1163,11 @@ using namespace mpb;
 
 extern "C" int bjac_apply(const bjac_handle *h, int32_t which, const double *r, double *z, void *stream) {
   if (!h || !r || !z || r == z || (which != 0 && which != 1)) return BJAC_EINVAL;
+  if (h->kind == 1) {
+    enqueue_poly_map(h, which, nullptr, r, z, nullptr, (hipStream_t)stream);
+    MPB_HIP(hipGetLastError());
+    return BJAC_OK;
+  }
   launch_apply(h, M_APP, 0, which == 1 ? sel_hi(h) : sel_lo(h), nullptr, nullptr, z, nullptr, nullptr, r, nullptr,
                nullptr, (hipStream_t)stream);
   MPB_HIP(hipGetLastError());

@@ -1,0 +1,125 @@
+"""Paper-mode BJAC(k, t) on the GPU against the oracle's PolyBJAC (eq. 3-1
+with k outer steps, eq. 3-3's t point-Jacobi sweeps per block solve; FP32
+application for the low map, Sec. 3.2 / Algorithm 3.1).
+
+Application: FP64 mode within a few ulps of the oracle (only the summation
+order differs); FP32 mode within the FP32 rounding of the k * t sweep chain.
+PCG: iteration counts against the oracle's PCG with the same preconditioner.
+"""
+import numpy as np
+import pytest
+
+from oracle import pcg as OP
+from paper_2407_15973_amd import binding as mb
+from paper_2407_15973_amd import gen
+
+from gpu_helpers import dev, tensor
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed=0, shape=(12, 10, 14), nb=4):
+    rng = np.random.default_rng(seed)
+    A = gen.diffusion3d(gen.kappa_loguniform(shape, rng, -1.0, 1.0))
+    # equal contiguous slabs (the paper's one block per process), remainder last
+    bp = np.linspace(0, A.n, nb + 1).round().astype(np.int32)
+    return A, bp, rng
+
+
+@pytest.mark.parametrize("k,t", [(1, 1), (1, 2), (2, 2), (3, 3), (2, 1)])
+def test_apply_fp64_matches_oracle(k, t):
+    A, bp, rng = _case()
+    M = mb.PaperBJAC(mb.DeviceCSR(A, dev()), bp, k=k, t=t, low=False)
+    ref_op = OP.PolyBJAC(A, bp, k=k, t=t, low=False)
+    for _ in range(2):
+        r = rng.uniform(-1, 1, A.n)
+        z = M.apply(tensor(r)).cpu().numpy()
+        ref = ref_op(r)
+        assert np.max(np.abs(z - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k,t", [(1, 2), (2, 2), (3, 2)])
+def test_apply_fp32_matches_oracle_low_mode(k, t):
+    A, bp, rng = _case(seed=1)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.PaperBJAC(Ad, bp, k=k, t=t, low=True)
+    ref_op = OP.PolyBJAC(A, bp, k=k, t=t, low=True)
+    r = rng.uniform(-1, 1, A.n)
+    z = M.apply(tensor(r), 0).cpu().numpy()
+    ref = ref_op(r)
+    # FP32 rounding of every step of the chain, relative to the result's scale
+    assert np.max(np.abs(z - ref)) <= 2e-6 * k * t * np.max(np.abs(ref))
+    # which = 1 is the FP64 application
+    z64 = M.apply(tensor(r), 1).cpu().numpy()
+    ref64 = OP.PolyBJAC(A, bp, k=k, t=t, low=False)(r)
+    assert np.max(np.abs(z64 - ref64)) <= 1e-12 * np.max(np.abs(ref64))
+
+
+def test_k_t_one_is_point_jacobi():
+    # k = t = 1: z = D^-1 r exactly (one rounding of 1/a_ii times r in FP64)
+    A, bp, rng = _case(seed=2)
+    M = mb.PaperBJAC(mb.DeviceCSR(A, dev()), bp, k=1, t=1, low=False)
+    r = rng.uniform(-1, 1, A.n)
+    z = M.apply(tensor(r)).cpu().numpy()
+    d = A.to_scipy().diagonal()
+    assert np.array_equal(z, (1.0 / d) * r)
+
+
+@pytest.mark.parametrize("low,slack", [(False, 2), (True, 3)])
+def test_pcg_paper_mode_matches_oracle(low, slack):
+    rng = np.random.default_rng(3)
+    A = gen.diffusion3d(gen.kappa_const(16))
+    bp = np.linspace(0, A.n, 33).round().astype(np.int32)     # 32 slabs, as with 32 processes
+    b = gen.rhs_uniform(A.n, rng)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low)
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(b), tol=1e-10, maxit=2000)
+    ref = OP.solve_poly(A, bp, b, k=2, t=2, low=low, tol=1e-10, maxit=2000)
+    print(f"paper mode low={low}: gpu {res.iters} oracle {ref.iters}")
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= max(slack, int(0.05 * ref.iters))
+    assert OP.true_relres(A, res.x.cpu().numpy(), b) <= 2e-10
+
+
+def test_pcg_paper_mode_adaptive_hl():
+    rng = np.random.default_rng(4)
+    A = gen.diffusion3d(gen.kappa_dis(14, 100.0))
+    bp = np.linspace(0, A.n, 9).round().astype(np.int32)
+    b = gen.rhs_uniform(A.n, rng)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=True, temporal=mb.TEMPORAL_HL, adp_tol=1e-4)
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(b), tol=1e-10, maxit=2000, history=True)
+    ref = OP.solve_poly(A, bp, b, k=2, t=2, low=True, tol=1e-10, maxit=2000, temporal=OP.TEMPORAL_HL,
+                        adp_tol=1e-4)
+    assert res.status == mb.OK
+    assert abs(res.iters - ref.iters) <= 3
+    # FP64 applications while relres >= 1e-4, then FP32 (where relres is not
+    # within rounding of the threshold the two switch histories agree)
+    hist = res.relres_hist
+    hh = res.high_hist.astype(bool)
+    assert hh[0]
+    seen = np.concatenate([[np.inf], hist])[:len(hh)]
+    clear = np.abs(np.log10(seen / 1e-4)) > 1e-6
+    assert np.array_equal(hh[clear], (seen >= 1e-4)[clear])
+
+
+def test_paper_mode_errors():
+    A, bp, rng = _case(seed=5)
+    Ad = mb.DeviceCSR(A, dev())
+    with pytest.raises(mb.MpbjacError):
+        mb.PaperBJAC(Ad, bp, k=0, t=2)
+    with pytest.raises(mb.MpbjacError):
+        mb.PaperBJAC(Ad, np.array([0, 5, 5, A.n], np.int32), k=1, t=1)
+    # a non-positive diagonal entry
+    B = gen.CSR(A.n, A.row_ptr.copy(), A.col_idx.copy(), A.val.copy())
+    i = 7
+    for kk in range(B.row_ptr[i], B.row_ptr[i + 1]):
+        if B.col_idx[kk] == i:
+            B.val[kk] = -1.0
+    with pytest.raises(mb.MpbjacError) as e:
+        mb.PaperBJAC(mb.DeviceCSR(B, dev()), bp, k=1, t=1)
+    assert e.value.code == mb.ENOTSPD
+    M = mb.PaperBJAC(Ad, bp, k=2, t=2)
+    info = M.info()
+    assert info["nb"] == len(bp) - 1 and info["max_block"] == int(np.max(np.diff(bp)))
+    assert np.all(M.tags() == mb.FP32)
