@@ -22,6 +22,9 @@ Other workloads (each prints its own line of the same form):
                        FP16 and FP64 storage
   --workload selector  192^3 held-out anisotropic jump problem: learned
                        selector (trained first, untimed) vs rule vs FP64
+  --workload paper     the paper's own setting (Sec. 4.2, Table 4.2): 128^3
+                       Diff3D-Const / Dis(1000) / Ani(s), f = 1, 32 slabs,
+                       BJAC(k=2, t=2) uniform FP64 vs fMP FP32 vs aMP(hl/lh)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload W]
 """
@@ -502,13 +505,87 @@ def bench_policies(args):
         "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
     }
 
+
+# ------------------------------------------------- the paper's own setting
+# Iteration counts printed by the paper (Table 4.2; Sec. 4.5.1 for Ani(s)),
+# BJAC k = t = 2 on 32 blocks, tol 1e-10, fp32 low precision, Diff3D 128^3.
+PAPER_TABLE_4_2 = {
+    "Const": {"uniform": 148, "fMP": 165, "hl@10": 165, "hl@5": 148, "hl@1": 148, "hl@0.1": 148,
+              "lh@1e-05": 165, "lh@10": 165},
+    "Dis(1000)": {"uniform": 185, "fMP": 211, "hl@10": 205, "hl@5": 201, "hl@1": 185, "hl@0.1": 185,
+                  "lh@1e-05": 211, "lh@10": 201},
+}
+PAPER_ANI = {1000: (327, 327), 100: (321, 321), 10: (205, 205), 4: (179, 179), 2: (159, 177), 1: (148, 165)}
+
+
+def bench_paper(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    N = args.N or 128
+    runs = {}
+
+    def solve(A, Ad, bp, b, S, low, temporal=mb.TEMPORAL_NONE, adp=math.inf):
+        M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low, temporal=temporal, adp_tol=adp)
+        for _ in range(args.warmup):
+            S.solve(Ad, M, b, tol=1e-10, maxit=2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = S.solve(Ad, M, b, tol=1e-10, maxit=2000)
+        torch.cuda.synchronize()
+        return res, (time.perf_counter() - t0) * 1e3 / args.steps
+
+    problems = [("Const", gen.kappa_const(N), (1.0, 1.0, 1.0)), ("Dis(1000)", gen.kappa_dis(N, 1000.0), (1.0, 1.0, 1.0))]
+    for s_ in PAPER_ANI:
+        problems.append((f"Ani({s_})", gen.kappa_const(N), (1.0, float(s_), float(s_))))
+    head_ms = None
+    for name, kap, an in problems:
+        log(f"paper mode {name}")
+        A = gen.diffusion3d(kap, aniso=an)
+        Ad = mb.DeviceCSR(A, dev)
+        bp = gen.uniform_blocks(A.n, A.n // 32)
+        b = torch.ones(A.n, dtype=torch.float64, device=dev)
+        S = mb.Solver(A.n, dev)
+        pols = [("uniform", False, mb.TEMPORAL_NONE, math.inf), ("fMP", True, mb.TEMPORAL_NONE, math.inf)]
+        if not name.startswith("Ani"):
+            pols += [(f"hl@{a:g}", True, mb.TEMPORAL_HL, a) for a in (10.0, 5.0, 1.0, 0.1)]
+            pols += [(f"lh@{a:g}", True, mb.TEMPORAL_LH, a) for a in (1e-5, 10.0)]
+        row = {}
+        for pname, low, temporal, adp in pols:
+            res, ms = solve(A, Ad, bp, b, S, low, temporal, adp)
+            if name.startswith("Ani"):
+                paper = PAPER_ANI[int(name[4:-1])][0 if pname == "uniform" else 1]
+            else:
+                paper = PAPER_TABLE_4_2[name][pname]
+            row[pname] = {"iters": res.iters, "paper_iters": paper, "ms": ms, "status": res.status,
+                          "high_applications": res.high_applications}
+            log(f"  {pname}: {res.iters} iterations (paper {paper}), {ms:.1f} ms")
+        runs[name] = row
+        if name == "Const":
+            head_ms = row["fMP"]["ms"]
+            speed = row["uniform"]["ms"] / row["fMP"]["ms"]
+        del Ad, S
+        torch.cuda.empty_cache()
+    return {
+        "metric": METRIC, "value": head_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "apply_arith": "paper-mode BJAC(2, 2): FP32 (fMP) or FP64 application", "data": "synthetic",
+        "config": {"workload": f"paper_mode_diff3d_{N}^3_32slabs_k2t2_f1", "tol": 1e-10},
+        "speedup_vs_fp64": speed, "runs": runs,
+    }
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=None, help="grid edge (diff3d 128, aniso 160, selector 192)")
-    ap.add_argument("--workload", default="diff3d", choices=("diff3d", "batched", "aniso", "selector"))
+    ap.add_argument("--workload", default="diff3d", choices=("diff3d", "batched", "aniso", "selector", "paper"))
     ap.add_argument("--nsys", type=int, default=256, help="batched: number of systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
@@ -523,6 +600,8 @@ def main():
         line = bench_diff3d(args)
     elif args.workload == "batched":
         line = bench_batched(args)
+    elif args.workload == "paper":
+        line = bench_paper(args)
     else:
         args.N = args.N or (160 if args.workload == "aniso" else 192)
         line = bench_policies(args)

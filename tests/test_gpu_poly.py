@@ -123,3 +123,27 @@ def test_paper_mode_errors():
     info = M.info()
     assert info["nb"] == len(bp) - 1 and info["max_block"] == int(np.max(np.diff(bp)))
     assert np.all(M.tags() == mb.FP32)
+
+
+def test_paper_table_4_2_const_at_full_size():
+    # Table 4.2 / Sec. 4.4.1 (Diff3D-Const 128^3, 32 blocks, k = t = 2,
+    # tol 1e-10, f = 1): uniform 148, fMP 165, hl@0.1 148. The paper leaves
+    # the partition and ordering unstated: a soft check (5 %) of the printed
+    # counts and of the delay's direction.
+    A = gen.diffusion3d(gen.kappa_const(128))
+    Ad = mb.DeviceCSR(A, dev())
+    bp = gen.uniform_blocks(A.n, A.n // 32)
+    b = tensor(np.ones(A.n))
+    S = mb.Solver(A.n, dev())
+    it = {}
+    for name, low, temporal, adp in (("uniform", False, mb.TEMPORAL_NONE, np.inf), ("fMP", True, mb.TEMPORAL_NONE, np.inf),
+                                     ("hl@0.1", True, mb.TEMPORAL_HL, 0.1)):
+        M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low, temporal=temporal, adp_tol=adp)
+        res = S.solve(Ad, M, b, tol=1e-10, maxit=1000)
+        assert res.status == mb.OK
+        it[name] = res.iters
+    print("paper mode 128^3 Const:", it)
+    assert abs(it["uniform"] - 148) <= 0.05 * 148
+    assert abs(it["fMP"] - 165) <= 0.05 * 165
+    assert abs(it["hl@0.1"] - 148) <= 0.05 * 148
+    assert it["fMP"] > it["uniform"]
