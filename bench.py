@@ -22,6 +22,9 @@ Other workloads (each prints its own line of the same form):
                        FP16 and FP64 storage
   --workload selector  192^3 held-out anisotropic jump problem: learned
                        selector (trained first, untimed) vs rule vs FP64
+  --workload rhd       synthetic radiation-diffusion-like systems at 128^3:
+                       coupled 3T (eq. 4-3, 6.3M rows) and 1T, stored
+                       inverses and paper mode, and a P_diag sweep (Sec. 4.5.2)
   --workload paper     the paper's own setting (Sec. 4.2, Table 4.2): 128^3
                        Diff3D-Const / Dis(1000) / Ani(s), f = 1, 32 slabs,
                        BJAC(k=2, t=2) uniform FP64 vs fMP FP32 vs aMP(hl/lh)
@@ -579,13 +582,92 @@ def bench_paper(args):
         "speedup_vs_fp64": speed, "runs": runs,
     }
 
+
+# ----------------------------------------- radiation-diffusion-like systems
+# Sec. 4.5.2 (RHD3D-1T): ratio of fp32-fMP to uniform iterations at P_diag
+# 1, 2, 8 as the paper states them.
+PAPER_PDIAG_ITER_O = {1.0: 1.36, 2.0: 1.24, 8.0: 1.20}
+
+
+def bench_rhd(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    N = args.N or 128
+    out = {}
+
+    def timed(Ad, M, b, S, tol):
+        for _ in range(args.warmup):
+            S.solve(Ad, M, b, tol=tol, maxit=5000, raise_on_error=False, verify=VERIFY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = S.solve(Ad, M, b, tol=tol, maxit=5000, raise_on_error=False, verify=VERIFY)
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3 / args.steps
+
+    for kind, tol in (("3T", 1e-10), ("1T", 1e-12)):
+        log(f"rhd {kind} {N}^3")
+        A = gen.rhd3t_like(N) if kind == "3T" else gen.rhd1t_like(N)
+        Ad = mb.DeviceCSR(A, dev)
+        b = torch.ones(A.n, dtype=torch.float64, device=dev)
+        S = mb.Solver(A.n, dev)
+        bp48 = gen.uniform_blocks(A.n, 48)
+        slabs = gen.uniform_blocks(A.n, A.n // 32)
+        row = {}
+        for name, mk in (("fp64", lambda: mb.BlockJacobi(Ad, bp48, mb.Policy())),
+                         ("fp32", lambda: mb.BlockJacobi(Ad, bp48, mb.Policy(mode=mb.FIXED, low=mb.FP32))),
+                         ("fp16", lambda: mb.BlockJacobi(Ad, bp48, mb.Policy(mode=mb.FIXED, low=mb.FP16))),
+                         ("rule", lambda: mb.BlockJacobi(Ad, bp48, mb.Policy(mode=mb.RULE))),
+                         ("paper_fp64", lambda: mb.PaperBJAC(Ad, slabs, 2, 2, low=False)),
+                         ("paper_fp32", lambda: mb.PaperBJAC(Ad, slabs, 2, 2, low=True))):
+            M = mk()
+            r, ms = timed(Ad, M, b, S, tol)
+            row[name] = {"iters": r.iters, "status": r.status, "true_relres_device": r.true_relres,
+                         "restarts": r.restarts, "ms": ms, "blocks_per_prec": M.info()["blocks_per_prec"]}
+            log(f"  {name}: {r.iters} iterations, status {r.status}, true relres {r.true_relres:.2e}, {ms:.1f} ms")
+            del M
+        out[kind] = {"n": A.n, "nnz": A.nnz, "tol": tol, "runs": row}
+        del Ad, S
+        torch.cuda.empty_cache()
+    log("P_diag sweep (1T, paper mode)")
+    sweep = {}
+    A0 = gen.rhd1t_like(N)
+    for p in (0.0, 1.0, 2.0, 4.0, 8.0):
+        A = gen.with_pdiag(A0, p)
+        Ad = mb.DeviceCSR(A, dev)
+        b = torch.ones(A.n, dtype=torch.float64, device=dev)
+        S = mb.Solver(A.n, dev)
+        slabs = gen.uniform_blocks(A.n, A.n // 32)
+        it = {}
+        for low in (False, True):
+            r = S.solve(Ad, mb.PaperBJAC(Ad, slabs, 2, 2, low=low), b, tol=1e-12, maxit=5000, raise_on_error=False)
+            it[low] = r.iters
+        sweep[p] = {"uniform": it[False], "fMP": it[True], "iter_o": it[True] / max(1, it[False]),
+                    "paper_iter_o": PAPER_PDIAG_ITER_O.get(p)}
+        log(f"  P_diag {p:g}: uniform {it[False]}, fMP {it[True]}")
+        del Ad, S
+    head = out["3T"]["runs"]["rule"]
+    return {
+        "metric": METRIC, "value": head["ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "apply_arith": "stored inverses (rule map) / paper-mode BJAC(2, 2)", "data": "synthetic",
+        "config": {"workload": f"rhd3t_like_{N}^3_interlaced_b48", "tol": out["3T"]["tol"]},
+        "speedup_vs_fp64": out["3T"]["runs"]["fp64"]["ms"] / head["ms"], "rhd": out, "pdiag_sweep": sweep,
+    }
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=None, help="grid edge (diff3d 128, aniso 160, selector 192)")
-    ap.add_argument("--workload", default="diff3d", choices=("diff3d", "batched", "aniso", "selector", "paper"))
+    ap.add_argument("--workload", default="diff3d",
+                    choices=("diff3d", "batched", "aniso", "selector", "paper", "rhd"))
     ap.add_argument("--nsys", type=int, default=256, help="batched: number of systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
@@ -602,6 +684,8 @@ def main():
         line = bench_batched(args)
     elif args.workload == "paper":
         line = bench_paper(args)
+    elif args.workload == "rhd":
+        line = bench_rhd(args)
     else:
         args.N = args.N or (160 if args.workload == "aniso" else 192)
         line = bench_policies(args)

@@ -300,3 +300,82 @@ def stack_batch(systems: list) -> StackedBatch:
     b = np.concatenate([np.ascontiguousarray(bs.B).ravel() for bs in systems])
     A = CSR(int(sys_row[-1]), row_ptr.astype(np.int32), col_idx.astype(np.int32), val)
     return StackedBatch(A, bp.astype(np.int32), sys_row.astype(np.int32), sys_m, b)
+
+
+# ------------------------------------------- radiation-diffusion-like systems
+def rhd3t_like(N: int, seed=0, interlace=True) -> CSR:
+    """Synthetic coupled three-temperature system with the block structure of
+    eq. 4-3: each diagonal block a 7-point
+    diffusion operator plus a positive diagonal (heat capacity over time step
+    and the exchange terms), the couplings D_RE = D_ER = -w_er and D_EI = D_IE =
+    -w_ei diagonal. The RHD3D matrices themselves are not available. As in
+    Table 4.3, the diffusion coefficients vary mildly inside each temperature
+    (the single-temperature rows stay below multiscale strength 10) while the
+    exchange coefficients and the temperatures' diffusion scales differ by many
+    decades, which spreads the coupled rows' strength (eq. 4-5) over 1 to 10^12:
+      K_r = 10^(3 + U(-1/2, 1/2)), K_e = 10^U(-1/2, 1/2), K_i = 10^(-5 + U(-1/2, 1/2)),
+      w_er = 10^U(-2, 0), w_ei = 10^U(0, 6), c_r = 10^U(-2, 0), c_e, c_i = 10^U(-1, 1).
+    The radiation block is dominated by its diffusion (its smallest
+    eigenvalues near 3 pi^2 K_r / (N+1)^2 compete with c_r + w_er), so its
+    single-temperature system needs hundreds of iterations like RHD3D-1T.
+    Symmetric, strictly diagonally dominant, off-diagonals <= 0 (an M-matrix).
+    nnz = 3 (N^3 + 6 N^2 (N - 1)) + 4 N^3 (52,133,888 at N = 128).
+    Ordering: interlace=False is eq. 4-3's [T_r; T_e; T_i]; interlace=True
+    (default) numbers the three temperatures of a cell consecutively (a
+    symmetric permutation of it), so that contiguous row blocks hold the
+    exchange couplings, which reach 10^6 times the smallest diagonal terms
+    and which row blocks of the [T_r; T_e; T_i] ordering cannot see."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    shape = (N, N, N)
+    K = [10.0 ** (m + rng.uniform(-0.5, 0.5, size=shape)) for m in (3.0, 0.0, -5.0)]
+    w_er = (10.0 ** rng.uniform(-2, 0, size=shape)).ravel()
+    w_ei = (10.0 ** rng.uniform(0, 6, size=shape)).ravel()
+    c = [(10.0 ** rng.uniform(lo, hi, size=shape)).ravel() for lo, hi in ((-2, 0), (-1, 1), (-1, 1))]
+    L = [diffusion3d(k).to_scipy() for k in K]
+    diag_add = [c[0] + w_er, c[1] + w_er + w_ei, c[2] + w_ei]
+    blocks = [[(L[i] + sp.diags(diag_add[i])) if i == j else None for j in range(3)] for i in range(3)]
+    Der = sp.diags(-w_er)
+    Dei = sp.diags(-w_ei)
+    blocks[0][1] = Der
+    blocks[1][0] = Der
+    blocks[1][2] = Dei
+    blocks[2][1] = Dei
+    S = sp.bmat(blocks, format="csr")
+    n = S.shape[0]
+    if interlace:
+        m = N ** 3
+        new = np.empty(n, dtype=np.int64)            # new index of old unknown (temperature t, cell i)
+        cell = np.arange(m)
+        for t in range(3):
+            new[t * m + cell] = 3 * cell + t
+        P = sp.csr_matrix((np.ones(n), (new, np.arange(n))), shape=(n, n))
+        S = (P @ S @ P.T).tocsr()
+    S.sort_indices()
+    A = CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64))
+    A.meta.update(shape=(3,) + shape, kind="rhd3t_like", interlace=bool(interlace))
+    return A
+
+
+def rhd1t_like(N: int, seed=0) -> CSR:
+    """The single-temperature reduction: the radiation block A_R of
+    rhd3t_like (same fields and draws)."""
+    A3 = rhd3t_like(N, seed, interlace=False)
+    n = N ** 3
+    rp = A3.row_ptr[:n + 1].astype(np.int64)
+    keep = A3.col_idx[:rp[-1]] < n
+    rows = np.repeat(np.arange(n), np.diff(rp))[keep]
+    return _csr_from_coo(n, rows, A3.col_idx[:rp[-1]][keep].astype(np.int64), A3.val[:rp[-1]][keep])
+
+
+def with_pdiag(A: CSR, p: float) -> CSR:
+    """Sec. 4.5.2's diagonal-dominance control: every diagonal entry gains
+    p times the row's sum of off-diagonal magnitudes."""
+    rp = A.row_ptr.astype(np.int64)
+    rows = np.repeat(np.arange(A.n), np.diff(rp))
+    off = rows != A.col_idx
+    s = np.bincount(rows[off], weights=np.abs(A.val[off]), minlength=A.n)
+    val = A.val.copy()
+    d = ~off
+    val[d] = val[d] + p * s[rows[d]]
+    return CSR(A.n, A.row_ptr.copy(), A.col_idx.copy(), val, dict(A.meta, pdiag=p))

@@ -129,3 +129,45 @@ def test_config_shapes():
     sysl = gen.config4(0, nsys=3, edge=(8, 12))
     for s in sysl:
         assert 1 <= s.B.shape[1] <= 8 and s.B.shape[0] == s.A.n
+
+
+def test_rhd3t_like_structure_and_nnz_formula():
+    # eq. 4-3: three 7-point blocks plus four diagonal couplings
+    N = 7
+    A = gen.rhd3t_like(N, seed=1, interlace=False)
+    n = N ** 3
+    assert A.n == 3 * n
+    assert A.nnz == 3 * (N ** 3 + 6 * N ** 2 * (N - 1)) + 4 * N ** 3
+    assert 3 * (128 ** 3 + 6 * 128 ** 2 * 127) + 4 * 128 ** 3 == 52_133_888
+    S = A.to_scipy()
+    assert abs(S - S.T).max() == 0.0
+    # the R-I blocks do not couple; R-E and E-I couple only on the diagonal
+    assert S[:n, 2 * n:].nnz == 0
+    RE = S[:n, n:2 * n].tocoo()
+    assert np.all(RE.row == RE.col) and np.all(RE.data < 0)
+    # M-matrix with strict diagonal dominance
+    d = S.diagonal()
+    off = abs(S).sum(axis=1).A1 - np.abs(d)
+    assert np.all(d > off)
+    assert np.all(S.data[S.nonzero()[0] != S.nonzero()[1]] <= 0)
+    # the single-temperature matrix is the R block
+    B = gen.rhd1t_like(N, seed=1).to_scipy()
+    assert abs(B - S[:n, :n]).max() == 0.0
+    # the interlaced ordering is the symmetric permutation cell-major
+    I = gen.rhd3t_like(N, seed=1).to_scipy()
+    perm = np.concatenate([np.arange(n) + t * n for t in range(3)]).reshape(3, n).T.ravel()
+    assert abs(I - S[perm][:, perm]).max() == 0.0
+
+
+def test_pdiag_adds_scaled_offdiagonal_sums():
+    # Sec. 4.5.2: a_ii += P_diag * sum_{j != i} |a_ij|
+    A = gen.rhd1t_like(6, seed=2)
+    S = A.to_scipy()
+    off = abs(S).sum(axis=1).A1 - np.abs(S.diagonal())
+    for p in (0.0, 1.0, 8.0):
+        P = gen.with_pdiag(A, p).to_scipy()
+        # (the two sides sum the row in different orders: a few ulps)
+        np.testing.assert_allclose(P.diagonal(), S.diagonal() + p * off, rtol=8e-15)
+        D = (P - S).tocsr()
+        D.eliminate_zeros()
+        assert np.all(D.nonzero()[0] == D.nonzero()[1])
