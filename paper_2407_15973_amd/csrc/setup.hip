@@ -157,24 +157,28 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
 
   // --- FP64 Gauss-Jordan sweep, no pivoting (pivots of an SPD block are the
   // positive Schur-complement diagonals). Pivot row k is broadcast from lane k.
+  // The columns rotate left by one per step, so the pivot column is always
+  // row[0] and the step loop needs no run-time register index (it stays a
+  // loop: a fully unrolled B x B sweep spills and overflows the instruction
+  // cache for B = 48, 64); after B steps the columns are back in place. Each
+  // entry sees the same operations in the same order as the unrotated sweep.
   bool ok = true;
-#pragma unroll
+#pragma unroll 1
   for (int kk = 0; kk < B; ++kk) {
-    double piv = bcast(row[kk], kk);
+    double piv = bcast(row[0], kk);
     if (!(piv > 0.0)) {
       ok = false;
       piv = 1.0;
     }
     const double inv = 1.0 / piv;
-    const double m = row[kk] * inv;
+    const double m = row[0] * inv;
     const bool isk = lane == kk;
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      if (j == kk) continue;
+    for (int j = 1; j < B; ++j) {
       const double pj = bcast(row[j], kk);
-      row[j] = isk ? pj * inv : fma(-m, pj, row[j]);
+      row[j - 1] = isk ? pj * inv : fma(-m, pj, row[j]);
     }
-    row[kk] = isk ? inv : -m;
+    row[B - 1] = isk ? inv : -m;
   }
   if (!ok && lane == 0) {
     a.flags[k] = 1;
