@@ -245,3 +245,42 @@ def test_profile_mode_runs_the_same_iterations():
     n_it = rp.kernel_ms["spmv"][1]
     assert n_it == res.iters and rp.kernel_ms["apply"][1] == n_it
     assert rp.kernel_ms["spmv"][0] > 0 and rp.kernel_ms["apply"][0] > 0
+
+
+def test_full_size_batched_workload_sampled():
+    # the 256-system batch the benchmark times (69 M rows, 1,114 columns), FP16
+    # inverses: the multi-column products of sampled blocks against the oracle,
+    # every column converged, and the FP64 true residual of sampled systems
+    st = gen.stack_batch(gen.config4(seed=0))
+    Ad = mb.DeviceCSR(st.A, dev())
+    M = mb.BlockJacobi(Ad, st.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    nb = len(st.block_ptr) - 1
+    rng = np.random.default_rng(12)
+    # multi-column application on the whole batch, 8 columns, sampled blocks
+    R = rng.uniform(-1, 1, (st.A.n, 8))
+    Z = M.apply_multi(tensor(R)).cpu().numpy()
+    ks = rng.choice(nb, size=32, replace=False)
+    sub = np.concatenate([[0], np.cumsum(np.diff(st.block_ptr)[ks])]).astype(np.int32)
+    rows = np.concatenate([np.arange(st.block_ptr[k], st.block_ptr[k + 1]) for k in ks])
+    S = st.A.to_scipy()[rows][:, rows]
+    Asub = gen.CSR(len(rows), S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    H = OB.invert_blocks(Asub, sub)
+    store = OB.store_blocks(H, np.full(len(ks), OPr.FP16, np.uint8))
+    bmax = int(np.max(np.diff(sub)))
+    for c in range(8):
+        ref = OB.apply(store, sub, R[rows, c])
+        bound = (gamma(bmax, 2.0 ** -24) + 2.0 ** -10) * OB.apply_abs(store, sub, R[rows, c])
+        assert np.all(np.abs(Z[rows, c] - ref) <= bound), c
+    del Z, R
+    bs = mb.BatchSolver(Ad, M, st.sys_row, st.sys_m)
+    res = bs.solve(tensor(st.b), tol=1e-10, maxit=5000)
+    assert res.status == mb.OK and np.all(res.col_status == mb.OK) and np.all(res.col_relres <= 1e-10)
+    x = res.x.cpu().numpy()
+    for s in rng.choice(len(st.sys_m), size=6, replace=False):
+        r0, r1 = int(st.sys_row[s]), int(st.sys_row[s + 1])
+        m = int(st.sys_m[s])
+        A_s = _sub_csr(st.A, r0, r1)
+        X = x[st.system_slice(s)].reshape(r1 - r0, m)
+        Bm = st.b[st.system_slice(s)].reshape(r1 - r0, m)
+        for c in range(m):
+            assert OP.true_relres(A_s, X[:, c], Bm[:, c]) <= 2e-10, (s, c)
