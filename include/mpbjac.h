@@ -260,11 +260,12 @@ int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *
 typedef struct {
   int32_t chunk_rows;   /* rows per matrix-vector chunk (>= 64; 0 = 128)      */
   int32_t wg_per_cu;    /* workgroups of 256 threads per compute unit in the
-                           persistent launches (1..32; 0 = 8; the matrix-
-                           vector launch is also capped at what is resident) */
+                           persistent launches (1..32; 0 = 32); at most 8192
+                           workgroups, the matrix-vector launch at most what
+                           is resident at once                                */
   int32_t spmv_ilp;     /* matrix-vector elements per lane in flight (1 or 2;
-                           0 = 2)                                             */
-  int32_t apply_rows;   /* padded rows per apply chunk (>= 64; 0 = 1024).
+                           0 = 1)                                             */
+  int32_t apply_rows;   /* padded rows per apply chunk (>= 64; 0 = 512).
                            Chunks never cross systems.                        */
 } bjac_batch_cfg;
 

@@ -55,9 +55,8 @@ __device__ __forceinline__ void bwave_lds_sync() {
 }
 
 // Wave slot of this wave in a grid whose size is a multiple of 8: workgroup g
-// runs on XCD g mod 8, so slots are numbered XCD by XCD and each XCD's waves
-// own one contiguous run of chunks (and of rows), keeping the SpMV's
-// neighbour rows in that XCD's L2.
+// runs on XCD g mod 8, so slots are numbered XCD by XCD and the apply's
+// contiguous runs of chunks (one per slot) group by XCD.
 __device__ __forceinline__ int wave_slot(int wv) {
   const int G = gridDim.x, g = blockIdx.x;
   return (((g & 7) * (G >> 3)) + (g >> 3)) * 4 + wv;
@@ -65,7 +64,6 @@ __device__ __forceinline__ int wave_slot(int wv) {
 
 // ------------------------------------------------------------------ SpMV
 struct BSpmvArgs {
-  int ilp;               // elements per lane in flight (1 or 2)
   BTables t;
   const int32_t *rp, *ci;
   const double *v;
@@ -74,7 +72,7 @@ struct BSpmvArgs {
   const double *beta;
   double *part;          // [nch][8]
   const int32_t *n_active;
-  const int32_t *sched;   // [waves + 1] first chunk of each wave slot
+  const int32_t *sched;   // [9] chunk run of each XCD
 };
 
 // floor(e / m) for 0 <= e < 4096 and 1 <= m <= 8 (multiply by ceil(2^16/m);
@@ -856,7 +854,7 @@ struct BCtx {
   BState st{};
   DevMap map{};
   int G1 = 8, G2 = 8;
-  int ilp = 2;
+  int ilp = 1;
   const int32_t *sched1 = nullptr, *sched2 = nullptr;
   const bjac_csr *A = nullptr;
   const bjac_handle *M = nullptr;
@@ -864,11 +862,12 @@ struct BCtx {
   double *x = nullptr;
 };
 
+// defaults: the shape the autotuner picked for the 256-system workload
 static void cfg_defaults(const bjac_batch_cfg *cfg, int &chunk_rows, int &wg_per_cu, int &ilp, int &apply_rows) {
   chunk_rows = cfg && cfg->chunk_rows > 0 ? cfg->chunk_rows : 128;
-  apply_rows = cfg && cfg->apply_rows > 0 ? cfg->apply_rows : 1024;
-  wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 8;
-  ilp = cfg && cfg->spmv_ilp > 0 ? cfg->spmv_ilp : 2;
+  apply_rows = cfg && cfg->apply_rows > 0 ? cfg->apply_rows : 512;
+  wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 32;
+  ilp = cfg && cfg->spmv_ilp > 0 ? cfg->spmv_ilp : 1;
 }
 
 static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
@@ -948,7 +947,6 @@ static void benq_spmv_k(const BCtx &c, const double *pold, double *pnew, hipStre
   a.part = c.w.part1;
   a.n_active = c.w.n_active;
   a.sched = c.sched1;
-  a.ilp = c.ilp;
   if (c.ilp == 1)
     hipLaunchKernelGGL(bspmv_kernel<1>, dim3(c.G1), dim3(256), 0, s, a);
   else
