@@ -94,6 +94,24 @@ METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP6
 # restarts from the true residual (at most this many times) when it is above
 VERIFY = 3
 
+# HBM bytes per launch of the two per-iteration kernels of the default
+# workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
+# profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
+# for the kernel sources they were measured on: reported when the digest of
+# those sources matches, null otherwise.
+TRAFFIC = {"sources_sha256": "60bc5f4fc3e25516df297942fea4160176585786d9eb4c02f43c02058ca12684",
+           "spmv": 277648286, "apply": 252405049}
+TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
+
+
+def measured_traffic(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2407_15973_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return TRAFFIC.get(kernel) if h.hexdigest() == TRAFFIC["sources_sha256"] else None
+
 
 def stream_ceilings(dev, gib=1):
     """Achievable streaming rates of this GPU, measured with PyTorch's own
@@ -199,7 +217,8 @@ def bench_diff3d(args):
     iter_bytes = kb["spmv"] + kb["apply"]
     iter_us16 = solve16 * 1e3 / max(1, r16.iters)
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": f"{dom}_kernel",
+                "frac": dk["gbs"] / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom) if args.N == 128 else None, "kernel": f"{dom}_kernel",
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     pair_gbs = iter_bytes / ((kern["spmv"]["avg_us"] + kern["apply"]["avg_us"]) * 1e-6) / 1e9
 
