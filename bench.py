@@ -423,20 +423,18 @@ def bench_batched(args):
 # ------------------------------------------- per-block rule / learned selector
 def train_selector(dev):
     """Selector trained on labels the solver generates on the 2D Poisson and
-    3D log-uniform families (seeds 0-1, 32^3 grids at contrasts 2 and 0)."""
+    3D diffusion families (selector.training_problems: seeds 0-1, 32^3 grids
+    at coefficient contrasts 10^0 to 10^5)."""
     import numpy as np
 
     from paper_2407_15973_amd import binding as mb
-    from paper_2407_15973_amd import gen
     from paper_2407_15973_amd import selector as sel
-    train = [gen.config1(s) for s in range(2)]
-    train += [gen.config2(seed=s, N=32, contrast=c) for c in (2.0, 0.0) for s in range(2)]
     F, Y = [], []
-    for p in train:
+    for p in sel.training_problems():
         ls = sel.make_labels(mb.DeviceCSR(p.A, dev), p.block_ptr, p.b, tol=p.tol, maxit=p.maxit)
         F.append(ls.features)
         Y.append(ls.labels)
-    return sel.train(np.concatenate(F), np.concatenate(Y), steps=300, lr=3e-3)
+    return sel.train(np.concatenate(F), np.concatenate(Y), steps=400, lr=3e-3)
 
 
 def bench_policies(args):

@@ -48,6 +48,20 @@ class LabelSet:
     runs: list = field(default_factory=list)
 
 
+TRAIN_CONTRASTS = (0.0, 2.0, 3.0, 4.0, 5.0)
+
+
+def training_problems(seeds=(0, 1), N=32):
+    """The training family: config 1 (2D Poisson) and config 2's 3D
+    diffusion generator at point-coefficient contrasts 10^+-c. Up to c = 3
+    every block tolerates FP16; at c = 4, 5 the all-FP16 map breaks down and
+    the labels become mostly FP32 with FP16 for the best-conditioned blocks."""
+    from . import gen
+    probs = [gen.config1(s) for s in seeds]
+    probs += [gen.config2(seed=s, N=N, contrast=c) for c in TRAIN_CONTRASTS for s in seeds]
+    return probs
+
+
 def make_labels(A: mb.DeviceCSR, block_ptr, b, tol=1e-10, maxit=5000, delay=0.05, solver=None,
                 etas=ETAS) -> LabelSet:
     import torch
@@ -56,6 +70,8 @@ def make_labels(A: mb.DeviceCSR, block_ptr, b, tol=1e-10, maxit=5000, delay=0.05
     M64 = mb.BlockJacobi(A, block_ptr, mb.Policy(mode=mb.UNIFORM))
     feat = M64.features()
     r64 = solver.solve(A, M64, bt, tol=tol, maxit=maxit, raise_on_error=False)
+    if r64.status != mb.OK:
+        raise ValueError("the FP64 reference solve did not converge: no delay to measure against")
     it64 = r64.iters
     kappa1 = 10.0 ** feat[:, 13].astype(np.float64)
     runs, seen = [], {}
