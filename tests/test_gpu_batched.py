@@ -284,3 +284,27 @@ def test_full_size_batched_workload_sampled():
         Bm = st.b[st.system_slice(s)].reshape(r1 - r0, m)
         for c in range(m):
             assert OP.true_relres(A_s, X[:, c], Bm[:, c]) <= 2e-10, (s, c)
+
+
+def test_batched_tiny_and_ragged_systems():
+    # systems of 1, 2, 5, 17 and 70 rows, 1 and 8 columns, one block per
+    # system where it fits (blocks never cross systems)
+    rng = np.random.default_rng(13)
+    systems = []
+    for n, m in ((1, 1), (2, 8), (5, 3), (17, 8), (70, 1)):
+        A = gen.poisson2d(n, 1) if n > 1 else gen._csr_from_coo(1, np.array([0]), np.array([0]), np.array([3.0]))
+        bp = gen.uniform_blocks(n, 64) if n > 64 else np.array([0, n], np.int32)
+        systems.append(gen.BatchSystem(A, bp, rng.uniform(-1, 1, (n, m))))
+    st = gen.stack_batch(systems)
+    M, bs, res = _run(st, mb.Policy())
+    assert res.status == mb.OK
+    x = res.x.cpu().numpy()
+    col = 0
+    for s, bsys in enumerate(systems):
+        X = x[st.system_slice(s)].reshape(bsys.A.n, -1)
+        for c in range(bsys.B.shape[1]):
+            assert OP.true_relres(bsys.A, X[:, c], bsys.B[:, c]) <= 2e-10
+            # one block per system of <= 64 rows is an exact solve: one iteration
+            if bsys.A.n <= 64:
+                assert res.col_iters[col] == 1
+            col += 1

@@ -249,3 +249,35 @@ def test_full_size_config2_sampled_parity():
     res = mb.Solver(p.A.n, dev()).solve(Ad, M, tensor(p.b), tol=1e-10, maxit=5000)
     assert res.status == mb.OK
     assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10
+
+
+def test_single_block_is_an_exact_solve():
+    # block size n (Sec. 3.1 with one block): M^-1 = A^-1 and PCG converges in
+    # one iteration with the FP64 map
+    A = gen.poisson2d(8, 8)
+    rng = np.random.default_rng(21)
+    b = rng.uniform(-1, 1, A.n)
+    res, _ = _gpu_solve(A, np.array([0, A.n], np.int32), b, mb.Policy(), 1e-10, 10)
+    assert res.status == mb.OK and res.iters == 1
+    assert OP.true_relres(A, res.x.cpu().numpy(), b) <= 1e-12
+
+
+def test_unit_blocks_are_point_jacobi():
+    # block size 1: the preconditioner is D^-1; iteration counts as the oracle's
+    # point-Jacobi PCG
+    rng = np.random.default_rng(22)
+    A = gen.diffusion3d(gen.kappa_loguniform((9, 8, 7), rng))
+    b = rng.uniform(-1, 1, A.n)
+    bp = np.arange(A.n + 1, dtype=np.int32)
+    res, _ = _gpu_solve(A, bp, b, mb.Policy(), 1e-10, 2000)
+    d = A.to_scipy().diagonal()
+    S = A.to_scipy()
+    ref = OP.pcg(lambda v: S @ v, b, lambda r: r / d, 1e-10, 2000)
+    assert res.status == mb.OK and abs(res.iters - ref.iters) <= 2
+
+
+def test_one_row_system():
+    A = gen._csr_from_coo(1, np.array([0]), np.array([0]), np.array([4.0]))
+    res, _ = _gpu_solve(A, np.array([0, 1], np.int32), np.array([2.0]), mb.Policy(mode=mb.FIXED, low=mb.FP16), 1e-12, 5)
+    assert res.status == mb.OK and res.iters == 1
+    assert abs(res.x.cpu().numpy()[0] - 0.5) <= 1e-15
