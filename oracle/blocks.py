@@ -241,6 +241,63 @@ def store_blocks(H, tags):
     return [P.store_block(Hk, int(t)) + (int(t),) for Hk, t in zip(H, tags)]
 
 
+# ------------------------------------------------- band-truncated storage
+# Cheaper storage of the same preconditioner (not in the paper; the paper's
+# M^-1(p_l) stores the whole block inverse in p_l, Sec. 3.2). The inverse of a
+# diagonally dominant banded block decays away from its diagonal, so most
+# entries are below the resolution of a 16- or 32-bit format relative to the
+# block. Band storage keeps the diagonals |i - j| <= w of each block, with the
+# smallest w whose dropped part is no larger, in Frobenius norm, than the unit
+# roundoff of the block's format times the whole inverse:
+#     sum_{|i-j| > w} H_ij^2 <= u_p^2 * sum_ij H_ij^2.
+# The kept band is symmetric, taken from the upper triangle
+# (entry (i, j) -> H[min(i, j), max(i, j)]), and rounded with the same scale
+# as full storage (the block's max|H_ij|).
+UNIT_ROUNDOFF = {P.FP64: 2.0 ** -53, P.FP32: 2.0 ** -24, P.BF16: 2.0 ** -8, P.FP16: 2.0 ** -11}
+
+
+def band_width(H: np.ndarray, rtol: float) -> int:
+    """Smallest w >= 0 with sum_{|i-j| > w} H_ij^2 <= rtol^2 sum_ij H_ij^2."""
+    H = np.asarray(H, dtype=np.float64)
+    b = H.shape[0]
+    dist = np.abs(np.subtract.outer(np.arange(b), np.arange(b)))
+    total = float(np.sum(H * H))
+    for w in range(b):
+        dropped = float(np.sum(np.where(dist > w, H * H, 0.0)))
+        if dropped <= rtol * rtol * total:
+            return w
+    return b - 1
+
+
+def band_part(H: np.ndarray, w: int) -> np.ndarray:
+    """Symmetric band of H from its upper triangle: (i, j) with |i - j| <= w
+    takes H[min(i, j), max(i, j)], every other entry is zero."""
+    H = np.asarray(H, dtype=np.float64)
+    U = np.triu(H)
+    S = U + np.triu(H, 1).T
+    dist = np.abs(np.subtract.outer(np.arange(H.shape[0]), np.arange(H.shape[0])))
+    return np.where(dist <= w, S, 0.0)
+
+
+def store_blocks_band(H, tags, rtol=None):
+    """Emulated band storage: list of (Hhat, s, tag, w), Hhat dense with zeros
+    outside the band. ``rtol`` None takes each block's unit roundoff."""
+    out = []
+    for Hk, t in zip(H, tags):
+        t = int(t)
+        w = band_width(Hk, UNIT_ROUNDOFF[t] if rtol is None else rtol)
+        s = P.block_scale(float(np.max(np.abs(Hk))), t)
+        out.append((P.round_to_format(band_part(Hk, w) / s, t), s, t, w))
+    return out
+
+
+def band_bytes(store, block_ptr) -> int:
+    """Stored bytes of a band map in the GPU layout: block k keeps w_k + 1
+    diagonals of bpad_k entries (bpad = size rounded up to 16)."""
+    sizes = block_sizes(block_ptr)
+    return int(sum(((int(b) + 15) // 16 * 16) * (e[3] + 1) * P.BYTES[e[2]] for b, e in zip(sizes, store)))
+
+
 def apply(store, block_ptr, r):
     """z = M^-1 r for k = 1 (eq. 3-1): per block z_blk = s * Hhat r_in with
     r_in = r for FP64 blocks and the FP32 copy of r otherwise (Algorithm 3.1,
@@ -249,7 +306,8 @@ def apply(store, block_ptr, r):
     r = np.asarray(r, dtype=np.float64)
     z = np.empty_like(r)
     r32 = P.rhat(r)
-    for k, (Hh, s, t) in enumerate(store):
+    for k, e in enumerate(store):
+        Hh, s, t = e[:3]
         a, b = bp[k], bp[k + 1]
         rin = r[a:b] if t == P.FP64 else r32[a:b]
         z[a:b] = s * (Hh @ rin)
@@ -261,7 +319,8 @@ def apply_abs(store, block_ptr, r):
     bp = np.asarray(block_ptr, dtype=np.int64)
     r32 = P.rhat(r)
     out = np.empty_like(np.asarray(r, dtype=np.float64))
-    for k, (Hh, s, t) in enumerate(store):
+    for k, e in enumerate(store):
+        Hh, s, t = e[:3]
         a, b = bp[k], bp[k + 1]
         rin = r[a:b] if t == P.FP64 else r32[a:b]
         out[a:b] = s * (np.abs(Hh) @ np.abs(rin))

@@ -111,14 +111,19 @@ class BJAC:
     precision map ``tags`` (eq. 3-1 with k = 1, Algorithm 3.1 for reduced
     blocks). ``high`` is the all-FP64 map used by the adaptive switch."""
 
-    def __init__(self, A, block_ptr, tags=None, H=None):
+    def __init__(self, A, block_ptr, tags=None, H=None, band=False, band_rtol=None):
         self.A = A
         self.block_ptr = np.asarray(block_ptr, dtype=np.int64)
         self.H = B.invert_blocks(A, block_ptr) if H is None else H
         nb = len(self.block_ptr) - 1
         self.tags = np.zeros(nb, dtype=np.uint8) if tags is None else np.asarray(tags, dtype=np.uint8)
-        self.store = B.store_blocks(self.H, self.tags)
-        self.store_high = B.store_blocks(self.H, np.zeros(nb, dtype=np.uint8))
+        if band:
+            # band-truncated storage of both maps (see blocks.band_width)
+            self.store = B.store_blocks_band(self.H, self.tags, band_rtol)
+            self.store_high = B.store_blocks_band(self.H, np.zeros(nb, dtype=np.uint8), band_rtol)
+        else:
+            self.store = B.store_blocks(self.H, self.tags)
+            self.store_high = B.store_blocks(self.H, np.zeros(nb, dtype=np.uint8))
 
     def low(self, r):
         return B.apply(self.store, self.block_ptr, r)

@@ -155,3 +155,95 @@ def test_apply_fp64_equals_dense_inverse_and_low_bound():
         z = OB.apply(OB.store_blocks(H, tags), bp, r)
         bound = (2 * u + u * u) * (np.abs(Dinv) @ np.abs(r)) + 1e-300
         assert np.all(np.abs(z - z64) <= bound * 1.0001 + 2.0 ** -38 * np.abs(Dinv).max() * 64)
+
+
+# ---------------------------------------------------- band-truncated storage
+def _geometric_tail(n, rho, a):
+    """sum_{d=a}^{n-1} 2 (n - d) rho^(2d) in closed form: with x = rho^2,
+    k = n - d, y = 1/x and m = n - a, it is 2 x^n sum_{k=1}^{m} k y^k and
+    sum_{k=1}^{m} k y^k = y (1 - (m+1) y^m + m y^(m+1)) / (1 - y)^2."""
+    if a >= n:
+        return 0.0
+    x = rho * rho
+    y = 1.0 / x
+    m = n - a
+    return 2.0 * x ** n * y * (1.0 - (m + 1) * y ** m + m * y ** (m + 1)) / (1.0 - y) ** 2
+
+
+@pytest.mark.parametrize("n,rho,u", [(32, 0.3, 2.0 ** -11), (48, 0.5, 2.0 ** -24), (64, 0.17, 2.0 ** -8),
+                                     (16, 0.9, 2.0 ** -11)])
+def test_band_width_geometric_closed_form(n, rho, u):
+    # H_ij = rho^|i-j|: the energy of diagonal d is 2 (n - d) rho^(2d) (d >= 1)
+    # and n for d = 0; the width is the first w whose closed-form tail beyond w
+    # is within u^2 of the closed-form total
+    idx = np.arange(n)
+    H = rho ** np.abs(np.subtract.outer(idx, idx))
+    total = n + _geometric_tail(n, rho, 1)
+    want = next(w for w in range(n) if _geometric_tail(n, rho, w + 1) <= u * u * total * (1 + 1e-12))
+    # the closed form and the explicit sum agree to rounding: skip near-ties
+    margin = abs(_geometric_tail(n, rho, want + 1) - u * u * total) / (u * u * total)
+    assert margin > 1e-9
+    assert OB.band_width(H, u) == want
+
+
+def test_band_width_minimal_and_bounded_brute_force():
+    rng = np.random.default_rng(7)
+    A = gen.diffusion3d(gen.kappa_loguniform((8, 6, 5), rng))
+    H = OB.invert_blocks(A, gen.uniform_blocks(A.n, 16))
+    for Hk in H:
+        for u in (2.0 ** -11, 2.0 ** -24, 1e-3):
+            w = OB.band_width(Hk, u)
+            b = Hk.shape[0]
+            dropped = [Hk[i, j] ** 2 for i in range(b) for j in range(b) if abs(i - j) > w]
+            assert np.sqrt(sum(dropped)) <= u * np.linalg.norm(Hk, "fro") * (1 + 1e-12)
+            if w > 0:
+                more = [Hk[i, j] ** 2 for i in range(b) for j in range(b) if abs(i - j) > w - 1]
+                assert np.sqrt(sum(more)) > u * np.linalg.norm(Hk, "fro")
+
+
+def test_band_exact_zero_structure():
+    # a diagonal matrix keeps one diagonal; a tridiagonal one at most three,
+    # however small the tolerance; the band part mirrors the upper triangle
+    rng = np.random.default_rng(8)
+    D = np.diag(rng.uniform(1, 2, 20))
+    assert OB.band_width(D, 1e-300) == 0
+    T = np.diag(rng.uniform(3, 4, 20)) + np.diag(rng.uniform(-1, 0, 19), 1)
+    T = T + np.triu(T, 1).T
+    assert OB.band_width(T, 1e-300) == 1
+    M = rng.standard_normal((10, 10))
+    Bm = OB.band_part(M, 2)
+    assert np.array_equal(Bm, Bm.T)
+    for i in range(10):
+        for j in range(10):
+            want = M[min(i, j), max(i, j)] if abs(i - j) <= 2 else 0.0
+            assert Bm[i, j] == want
+
+
+def test_band_store_scale_and_bytes():
+    rng = np.random.default_rng(9)
+    A = gen.diffusion3d(gen.kappa_loguniform((8, 8, 8), rng))
+    bp = gen.uniform_blocks(A.n, 32)
+    H = OB.invert_blocks(A, bp)
+    tags = np.array([P.FP16, P.FP32, P.BF16, P.FP64] * (len(H) // 4), dtype=np.uint8)
+    st = OB.store_blocks_band(H, tags)
+    for Hk, t, (Hh, s, tt, w) in zip(H, tags, st):
+        assert tt == t and s == P.block_scale(float(np.max(np.abs(Hk))), int(t))
+        # in-band entries are the format's rounding of the (mirrored) inverse
+        Bk = OB.band_part(Hk, w)
+        assert np.array_equal(Hh, P.round_to_format(Bk / s, int(t)))
+        assert w == OB.band_width(Hk, OB.UNIT_ROUNDOFF[int(t)])
+    # w + 1 diagonals of 32 entries per block
+    assert OB.band_bytes(st, bp) == sum(32 * (e[3] + 1) * P.BYTES[e[2]] for e in st)
+
+
+def test_band_with_vanishing_tolerance_is_full_symmetrised_storage():
+    rng = np.random.default_rng(10)
+    A = gen.diffusion3d(gen.kappa_loguniform((6, 5, 4), rng))
+    bp = gen.uniform_blocks(A.n, 24)
+    H = OB.invert_blocks(A, bp)
+    tags = np.full(len(H), P.FP16, dtype=np.uint8)
+    st = OB.store_blocks_band(H, tags, rtol=1e-300)
+    for Hk, (Hh, s, t, w) in zip(H, st):
+        assert w == Hk.shape[0] - 1
+        Sym = np.triu(Hk) + np.triu(Hk, 1).T
+        assert np.array_equal(Hh, P.round_to_format(Sym / s, P.FP16))

@@ -218,3 +218,19 @@ def test_paper_mode_const_replication():
     r32 = OP.solve_poly(A, bp, b, 2, 2, low=True, tol=1e-10)
     assert abs(r64.iters - 148) <= 0.05 * 148
     assert abs(r32.iters - 165) <= 0.05 * 165 and r32.iters > r64.iters
+
+
+def test_band_storage_at_unit_roundoff_keeps_iterations():
+    # truncation below each format's unit roundoff perturbs M no more than the
+    # rounding already does: the PCG iteration counts stay within one
+    rng = np.random.default_rng(11)
+    A = gen.diffusion3d(gen.kappa_loguniform((12, 10, 8), rng))
+    bp = gen.uniform_blocks(A.n, 12)
+    b = rng.uniform(-1, 1, A.n)
+    H = OB.invert_blocks(A, bp)
+    for t in (P.FP64, P.FP32, P.FP16):
+        tags = np.full(len(H), t, dtype=np.uint8)
+        full = OP.solve_bjac(A, bp, b, M=OP.BJAC(A, bp, tags, H=H), tol=1e-10)
+        band = OP.solve_bjac(A, bp, b, M=OP.BJAC(A, bp, tags, H=H, band=True), tol=1e-10)
+        assert full.status == OP.CONVERGED and band.status == OP.CONVERGED
+        assert abs(full.iters - band.iters) <= 1
