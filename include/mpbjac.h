@@ -72,6 +72,25 @@ typedef enum {
   BJAC_TEMPORAL_LH = 2    /* Algorithm 3.3: low map while relres >= adp_tol */
 } bjac_temporal;
 
+/* ---- storage of the block inverses ------------------------------------
+ * FULL: every stored block keeps all b^2 entries of its inverse (Sec. 3.2's
+ * M^-1(p_l): the inverse rounded to the block's format).
+ * BAND: a cheaper storage of the same inverses (not in the paper). Block k
+ * keeps the diagonals |i - j| <= w_k of its inverse H, with the smallest w_k
+ * such that sum_{|i-j| > w_k} H_ij^2 <= tau^2 sum_ij H_ij^2, where tau is
+ * policy.band_rtol, or, when band_rtol <= 0, the unit roundoff of the block's
+ * format (2^-53, 2^-24, 2^-8, 2^-11 for FP64, FP32, BF16, FP16): the dropped
+ * part is then no larger than the rounding the format already makes. The kept
+ * band is symmetric, taken from H's upper triangle, with the same scale and
+ * rounding as FULL. The inverse of a diagonally dominant banded block decays
+ * away from its diagonal, so w_k is usually far below b_k: the application
+ * reads (w_k + 1) / bpad_k of FULL's bytes. Band handles serve bjac_apply and
+ * pcg_solve; the batched entry points and bjac_apply_multi reject them. */
+typedef enum {
+  BJAC_STORE_FULL = 0,
+  BJAC_STORE_BAND = 1
+} bjac_storage;
+
 /* Square CSR matrix, all arrays device memory, caller-owned, read-only.
  * row_ptr[n+1] (row_ptr[0] = 0, non-decreasing), col_idx[nnz] in [0, n),
  * val[nnz] FP64. Columns need not be sorted. A must be symmetric positive
@@ -88,12 +107,14 @@ typedef struct {
   int32_t mode;                  /* bjac_mode                                  */
   int32_t low;                   /* bjac_prec used by BJAC_FIXED               */
   int32_t temporal;              /* bjac_temporal                              */
-  int32_t reserved;
+  int32_t storage;               /* bjac_storage                               */
   double adp_tol;                /* threshold of the temporal switch           */
   double theta;                  /* RULE: kappa_1 * u <= theta (default 1e-2)  */
   double d16;                    /* RULE: min row dominance for FP16 (1.0)     */
   const float *mlp_blob;         /* LEARNED: device, BJAC_MLP_NBLOB floats     */
   const uint8_t *explicit_tags;  /* EXPLICIT: host, nb entries of bjac_prec    */
+  double band_rtol;              /* BAND: tolerance tau of the dropped part
+                                    (<= 0: each block's unit roundoff)         */
 } bjac_policy;
 
 typedef struct bjac_handle bjac_handle;
@@ -174,6 +195,10 @@ int bjac_get_features(const bjac_handle *h, float *features);
  * numbers (b x b, row-major) and its scale s (the block represents s * out).
  * which = 0: low map, 1: all-FP64 map (temporal handles only). */
 int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block, double *out, double *scale);
+/* BAND handles: copies the half-bandwidth w_k of every block of map `which`
+ * (0 low, 1 all-FP64 map of temporal handles) to HOST memory w[nb]. FULL and
+ * paper-mode handles: BJAC_EINVAL. */
+int bjac_get_band(const bjac_handle *h, int32_t which, uint8_t *w);
 
 /* ---- paper-mode BJAC(k, t) (Sec. 3.1 eq. 3-1 to 3-3; Sec. 3.2) ----------
  * The preconditioner as the paper defines it for large blocks (one per

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmpbjac.so")
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 UNIFORM, FIXED, RULE, LEARNED, EXPLICIT = 0, 1, 2, 3, 4
 TEMPORAL_NONE, TEMPORAL_HL, TEMPORAL_LH = 0, 1, 2
+STORE_FULL, STORE_BAND = 0, 1
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 MLP_NPARAM = 5443
 MLP_NBLOB = MLP_NPARAM + 32
@@ -28,7 +29,7 @@ NFEAT = 16
 # exported symbols declared in include/mpbjac.h
 SYMBOLS = (
     "bjac_abi_version", "bjac_strerror", "bjac_setup_query", "bjac_setup", "bjac_destroy",
-    "bjac_get_info", "bjac_get_tags", "bjac_get_features", "bjac_get_block", "bjac_apply",
+    "bjac_get_info", "bjac_get_tags", "bjac_get_features", "bjac_get_block", "bjac_get_band", "bjac_apply",
     "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
     "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
@@ -42,9 +43,9 @@ class bjac_csr(C.Structure):
 
 
 class bjac_policy(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("low", C.c_int32), ("temporal", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("mode", C.c_int32), ("low", C.c_int32), ("temporal", C.c_int32), ("storage", C.c_int32),
                 ("adp_tol", C.c_double), ("theta", C.c_double), ("d16", C.c_double),
-                ("mlp_blob", C.c_void_p), ("explicit_tags", C.c_void_p)]
+                ("mlp_blob", C.c_void_p), ("explicit_tags", C.c_void_p), ("band_rtol", C.c_double)]
 
 
 class bjac_info(C.Structure):
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
         "bjac_get_tags": (C.c_int, [vp, vp]),
         "bjac_get_features": (C.c_int, [vp, vp]),
         "bjac_get_block": (C.c_int, [vp, i32, i32, vp, P(dbl)]),
+        "bjac_get_band": (C.c_int, [vp, i32, vp]),
         "bjac_apply": (C.c_int, [vp, i32, vp, vp, vp]),
         "bjac_spmv": (C.c_int, [P(bjac_csr), vp, vp, vp]),
         "bjac_round": (C.c_int, [vp, vp, i64, i32, dbl, vp]),
@@ -194,13 +196,15 @@ class Policy:
     d16: float = 1.0
     mlp_blob: object = None          # device float tensor [MLP_NBLOB]
     explicit_tags: object = None     # numpy uint8 [nb]
+    storage: int = STORE_FULL        # STORE_BAND: band-truncated inverses
+    band_rtol: float = 0.0           # <= 0: each block's unit roundoff
 
     def c(self):
         tags = None if self.explicit_tags is None else np.ascontiguousarray(self.explicit_tags, dtype=np.uint8)
         self._tags_keep = tags
-        return bjac_policy(self.mode, self.low, self.temporal, 0, self.adp_tol, self.theta, self.d16,
+        return bjac_policy(self.mode, self.low, self.temporal, self.storage, self.adp_tol, self.theta, self.d16,
                            self.mlp_blob.data_ptr() if self.mlp_blob is not None else None,
-                           tags.ctypes.data if tags is not None else None)
+                           tags.ctypes.data if tags is not None else None, self.band_rtol)
 
 
 class BlockJacobi:
@@ -253,6 +257,12 @@ class BlockJacobi:
         sc = C.c_double()
         _check(load().bjac_get_block(self.h, which, k, out.ctypes.data, C.byref(sc)), "bjac_get_block")
         return out, sc.value
+
+    def band_widths(self, which: int = 0) -> np.ndarray:
+        """Half-bandwidth of every stored block (band storage only)."""
+        out = np.empty(self.nb, dtype=np.uint8)
+        _check(load().bjac_get_band(self.h, which, out.ctypes.data), "bjac_get_band")
+        return out
 
     def apply(self, r, which: int = 0):
         z = _torch().empty_like(r)

@@ -44,12 +44,13 @@ struct alignas(64) PcgState {
 enum StateStatus { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_BREAKDOWN = -3, ST_SYNC_FAIL = -4 };
 
 // One stored precision map: byte offsets (from the workspace base) and scale
-// of every block.
+// of every block; band storage adds each block's half-bandwidth.
 struct DevMap {
   const uint8_t *base;
   const int64_t *off;
   const double *scale;
   const uint8_t *tag;
+  const uint8_t *w = nullptr;   // band storage: diagonals 0..w[k] kept; null: full blocks
 };
 
 }  // namespace mpb
@@ -77,6 +78,10 @@ struct bjac_handle {
   int64_t *off_lo = nullptr, *off_hi = nullptr;
   double *scale_lo = nullptr, *scale_hi = nullptr;
   uint8_t *tag_lo = nullptr, *tag_hi = nullptr;
+  // band storage (BJAC_STORE_BAND): half-bandwidth of every block per map
+  int32_t storage = 0;
+  uint8_t *w_lo = nullptr, *w_hi = nullptr;
+  std::vector<uint8_t> h_w_lo, h_w_hi;
   float *feat = nullptr;         // [nb*16]
   int32_t *flags = nullptr;      // [nb] non-SPD marks
   // host copies

@@ -5,6 +5,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -35,6 +36,11 @@ struct SetupArgs {
   double *scale_lo;
   const int64_t *off_hi;  // pack the all-FP64 map when non-null
   double *scale_hi;
+  // band storage: widths per format (first pass), chosen widths (packing pass)
+  uint8_t *wband;         // [nb*4] when non-null: w of each format, indexed by Prec
+  double band_rtol;       // <= 0: the format's unit roundoff
+  const uint8_t *w_lo;    // packing: band store of the low map when non-null
+  const uint8_t *w_hi;    // packing: band store of the all-FP64 map when non-null
 };
 
 constexpr double kDomCap = 1e8;
@@ -96,6 +102,44 @@ __device__ __forceinline__ void store_block(uint8_t *dst, int prec, const double
     case PBF16: store_rows<B, PBF16>(dst, row, lane, inv_s); break;
     default: store_rows<B, P16>(dst, row, lane, inv_s); break;
   }
+}
+
+// Band storage of one padded block: lane li writes E(d, li) = row[li + d]
+// (times inv_s, rounded) for d = 0..w as entry d * B + li, zero where
+// li + d >= B. The column index is a compile-time register index.
+template <int P>
+__device__ __forceinline__ void put_elem(uint8_t *p, double v) {
+  if constexpr (P == P64) *(double *)p = v;
+  else if constexpr (P == P32) *(uint32_t *)p = to_f32_bits(v);
+  else *(uint16_t *)p = (uint16_t)to_bits<P>(v);
+}
+
+template <int B, int P>
+__device__ __forceinline__ void store_band_rows(uint8_t *dst, const double (&row)[B], int lane, double inv_s, int w) {
+  constexpr int BY = prec_bytes(P);
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    const int d = j - lane;
+    if (d >= 0 && d <= w) put_elem<P>(dst + ((int64_t)d * B + lane) * BY, row[j] * inv_s);
+  }
+  for (int d = B - lane; d <= w; ++d) put_elem<P>(dst + ((int64_t)d * B + lane) * BY, 0.0);
+}
+
+template <int B>
+__device__ __forceinline__ void store_band(uint8_t *dst, int prec, const double (&row)[B], int lane, double inv_s,
+                                           int w) {
+  if (lane >= B) return;
+  switch (prec) {
+    case P64: store_band_rows<B, P64>(dst, row, lane, 1.0, w); break;
+    case P32: store_band_rows<B, P32>(dst, row, lane, inv_s, w); break;
+    case PBF16: store_band_rows<B, PBF16>(dst, row, lane, inv_s, w); break;
+    default: store_band_rows<B, P16>(dst, row, lane, inv_s, w); break;
+  }
+}
+
+// Unit roundoff of each storage format, indexed by Prec.
+__device__ __forceinline__ double unit_roundoff(int p) {
+  return p == P64 ? 0x1p-53 : (p == P32 ? 0x1p-24 : (p == PBF16 ? 0x1p-8 : 0x1p-11));
 }
 
 __device__ __forceinline__ int ceil_log2(double v) {
@@ -250,6 +294,32 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     a.feat[(int64_t)k * 16 + lane] = (float)f;
   }
 
+  // --- band widths: for each format the smallest w with
+  // sum_{|i-j| > w} H_ij^2 <= tau^2 sum H_ij^2 (binary search; the dropped sum
+  // shrinks as w grows, and every lane holds the same wave total)
+  if (a.wband) {
+    double t2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j)
+      if (real && j < b) t2 = fma(row[j], row[j], t2);
+    const double total = wave_sum(t2);
+    for (int f = 0; f < 4; ++f) {
+      const double u = a.band_rtol > 0.0 ? a.band_rtol : unit_roundoff(f);
+      const double thr = u * u * total;
+      int lo = 0, hi = b - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          if (real && j < b && abs(j - lane) > mid) t = fma(row[j], row[j], t);
+        if (wave_sum(t) <= thr) hi = mid;
+        else lo = mid + 1;
+      }
+      if (lane == 0) a.wband[(int64_t)k * 4 + f] = (uint8_t)lo;
+    }
+  }
+
   // --- precision of this block
   int tag;
   if (a.tag_mode == TAG_CONST) {
@@ -271,13 +341,17 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     for (int j = 0; j < B; ++j) row[j] = 0.0;
   }
   if (a.off_hi) {
-    store_block<B>(a.base + a.off_hi[k], P64, row, lane, 1.0);
+    if (a.w_hi) store_band<B>(a.base + a.off_hi[k], P64, row, lane, 1.0, a.w_hi[k]);
+    else store_block<B>(a.base + a.off_hi[k], P64, row, lane, 1.0);
     if (lane == 0) a.scale_hi[k] = 1.0;
   }
   if (a.off_lo) {
     double sc = 1.0;
     if (tag == P16 || tag == PBF16) sc = ldexp(1.0, ceil_log2(hmax) - kScaleTopExp);
-    if (!(a.off_hi && tag == P64)) store_block<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc);
+    if (!(a.off_hi && tag == P64)) {
+      if (a.w_lo) store_band<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc, a.w_lo[k]);
+      else store_block<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc);
+    }
     if (lane == 0) a.scale_lo[k] = sc;
   }
 }
@@ -327,6 +401,8 @@ static int make_plan(const bjac_csr *A, const int32_t *bp, int32_t nb, const bja
   if (pol->mode == BJAC_FIXED && (pol->low < BJAC_FP64 || pol->low > BJAC_FP16)) return BJAC_EINVAL;
   if (pol->mode == BJAC_EXPLICIT && !pol->explicit_tags) return BJAC_EINVAL;
   if (pol->mode == BJAC_LEARNED && !pol->mlp_blob) return BJAC_EINVAL;
+  if (pol->storage != BJAC_STORE_FULL && pol->storage != BJAC_STORE_BAND) return BJAC_EINVAL;
+  if (!(pol->band_rtol < 1.0)) return BJAC_EINVAL;  // NaN or >= 1
   pl.n = A->n;
   pl.nb = nb;
   pl.sizes.resize(nb);
@@ -386,6 +462,7 @@ struct Layout {
   int64_t *off_lo, *off_hi;
   double *scale_lo, *scale_hi;
   uint8_t *tag_lo, *tag_hi, *arena;
+  uint8_t *wband, *w_lo, *w_hi;
   float *feat;
   size_t bytes;
 };
@@ -407,6 +484,9 @@ static Layout carve(void *ws, const Plan &pl) {
   L.tag_lo = c.take<uint8_t>(nb);
   L.tag_hi = c.take<uint8_t>(nb);
   L.feat = c.take<float>((size_t)nb * 16);
+  L.wband = c.take<uint8_t>((size_t)nb * 4);
+  L.w_lo = c.take<uint8_t>(nb);
+  L.w_hi = c.take<uint8_t>(nb);
   L.arena = c.take<uint8_t>((size_t)(pl.high_bytes + pl.low_bound) + 256);
   L.bytes = c.used;
   return L;
@@ -494,66 +574,91 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   a.base = (uint8_t *)workspace;
   a.feat = L.feat;
 
-  // precision map on the host
-  std::vector<uint8_t> tags(nb, 0);
+  // precision map (and, for band storage, the widths) on the host
+  const bool band = policy->storage == BJAC_STORE_BAND;
+  a.band_rtol = policy->band_rtol;
+  std::vector<uint8_t> tags(nb, 0), wb;
   const int mode = policy->mode;
-  if (mode == BJAC_RULE || mode == BJAC_LEARNED) {
+  const bool data_map = mode == BJAC_RULE || mode == BJAC_LEARNED;
+  if (data_map || band) {
     SetupArgs p1 = a;
     p1.tag_mode = TAG_RULE;
     p1.tag_out = (mode == BJAC_RULE) ? L.tag_lo : nullptr;
+    p1.wband = band ? L.wband : nullptr;
     if ((rc = launch_setup(p1, cls, L.blist, st))) return fail(rc);
     if (mode == BJAC_LEARNED && (rc = launch_mlp_select(L.feat, nb, policy->mlp_blob, L.tag_lo, st)))
       return fail(rc);
-    if (hipMemcpyAsync(tags.data(), L.tag_lo, nb, hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
-      return fail(BJAC_EHIP);
-  } else if (mode == BJAC_FIXED) {
+    if (data_map && hipMemcpyAsync(tags.data(), L.tag_lo, nb, hipMemcpyDeviceToHost, st)) return fail(BJAC_EHIP);
+    if (band) {
+      wb.resize((size_t)nb * 4);
+      if (hipMemcpyAsync(wb.data(), L.wband, wb.size(), hipMemcpyDeviceToHost, st)) return fail(BJAC_EHIP);
+    }
+    if (hipStreamSynchronize(st)) return fail(BJAC_EHIP);
+  }
+  if (mode == BJAC_FIXED) {
     std::fill(tags.begin(), tags.end(), (uint8_t)policy->low);
   } else if (mode == BJAC_EXPLICIT) {
     std::memcpy(tags.data(), policy->explicit_tags, nb);
   }
+  // stored bytes of block k in format p: B^2 entries, or w + 1 diagonals of B
+  auto width = [&](int32_t k, int p) -> int { return band ? wb[(size_t)k * 4 + p] : 0; };
+  auto blk_bytes = [&](int32_t k, int p) -> int64_t {
+    const int64_t B = pl.bpad[k];
+    return (band ? B * (width(k, p) + 1) : B * B) * prec_bytes(p);
+  };
   // offsets: the FP64 map first (temporal), then the low map; in temporal
   // handles FP64 blocks of the low map alias the FP64 map
   std::vector<int64_t> off_lo(nb), off_hi(nb, 0);
   const int64_t arena0 = L.arena - (uint8_t *)workspace;
   int64_t o = arena0;
+  int64_t hi_bytes = 0;
   if (pl.temporal) {
     for (int32_t k = 0; k < nb; ++k) {
-      const int64_t B = pl.bpad[k];
       off_hi[k] = o;
-      o += B * B * 8;
+      o += blk_bytes(k, P64);
     }
+    hi_bytes = o - arena0;
   }
-  int64_t lo_bytes = 0;
+  int64_t lo_bytes = 0, lo_all = 0;
   for (int32_t k = 0; k < nb; ++k) {
-    const int64_t B = pl.bpad[k];
+    const int64_t bb = blk_bytes(k, tags[k]);
+    lo_all += bb;
     if (pl.temporal && tags[k] == P64) {
       off_lo[k] = off_hi[k];
     } else {
       off_lo[k] = o;
-      o += B * B * prec_bytes(tags[k]);
-      lo_bytes += B * B * prec_bytes(tags[k]);
+      o += bb;
+      lo_bytes += bb;
     }
     h->hist[tags[k]]++;
   }
   if (o - arena0 > pl.high_bytes + pl.low_bound) return fail(BJAC_EINVAL);
-  h->low_bytes = pl.temporal ? 0 : lo_bytes;
-  if (pl.temporal) {
-    h->low_bytes = 0;
-    for (int32_t k = 0; k < nb; ++k) {
-      const int64_t B = pl.bpad[k];
-      h->low_bytes += B * B * prec_bytes(tags[k]);
-    }
-  }
-  h->high_bytes = pl.high_bytes;
+  h->low_bytes = pl.temporal ? lo_all : lo_bytes;
+  h->high_bytes = hi_bytes;
   if (hipMemcpyAsync(L.off_lo, off_lo.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(L.tag_lo, tags.data(), nb, hipMemcpyHostToDevice, st))
     return fail(BJAC_EHIP);
+  if (band) {
+    h->h_w_lo.resize(nb);
+    h->h_w_hi.resize(nb);
+    for (int32_t k = 0; k < nb; ++k) {
+      h->h_w_lo[k] = (uint8_t)width(k, tags[k]);
+      h->h_w_hi[k] = (uint8_t)width(k, P64);
+    }
+    if (hipMemcpyAsync(L.w_lo, h->h_w_lo.data(), nb, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(L.w_hi, h->h_w_hi.data(), nb, hipMemcpyHostToDevice, st))
+      return fail(BJAC_EHIP);
+    h->storage = BJAC_STORE_BAND;
+    h->w_lo = L.w_lo;
+    h->w_hi = pl.temporal ? L.w_hi : nullptr;
+  }
   if (pl.temporal) {
     std::vector<uint8_t> t64(nb, 0);
     if (hipMemcpyAsync(L.off_hi, off_hi.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(L.tag_hi, t64.data(), nb, hipMemcpyHostToDevice, st) || hipStreamSynchronize(st))
       return fail(BJAC_EHIP);
   }
+  if (band && hipStreamSynchronize(st)) return fail(BJAC_EHIP);
 
   SetupArgs p2 = a;
   p2.tag_mode = TAG_ARRAY;
@@ -562,6 +667,8 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   p2.scale_lo = L.scale_lo;
   p2.off_hi = pl.temporal ? L.off_hi : nullptr;
   p2.scale_hi = L.scale_hi;
+  p2.w_lo = band ? L.w_lo : nullptr;
+  p2.w_hi = (band && pl.temporal) ? L.w_hi : nullptr;
   if ((rc = launch_setup(p2, cls, L.blist, st))) return fail(rc);
   int32_t bad = 0;
   if (hipMemcpyAsync(&bad, L.any_bad, sizeof(int32_t), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
@@ -574,14 +681,14 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   bool rows_uniform = pl.uniform_b > 0;
   for (int32_t k = 0; k + 1 < nb && rows_uniform; ++k) rows_uniform = pl.sizes[k] == pl.uniform_b;
   h->rows_uniform = rows_uniform;
-  if (rows_uniform && h->uprec_lo >= 0) {
+  if (rows_uniform && h->uprec_lo >= 0 && !band) {
     const int64_t stride = (int64_t)pl.uniform_b * pl.uniform_b * prec_bytes(h->uprec_lo);
     bool contig = true;
     for (int32_t k = 0; k < nb && contig; ++k) contig = off_lo[k] == off_lo[0] + k * stride;
     h->fast_lo = contig;
     h->lo_off0 = off_lo[0];
   }
-  if (rows_uniform && pl.temporal) {
+  if (rows_uniform && pl.temporal && !band) {
     const int64_t stride = (int64_t)pl.uniform_b * pl.uniform_b * 8;
     bool contig = true;
     for (int32_t k = 0; k < nb && contig; ++k) contig = off_hi[k] == off_hi[0] + k * stride;
@@ -654,14 +761,33 @@ extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block
   const int prec = which == 1 ? P64 : h->h_tag_lo[block];
   const int64_t off = which == 1 ? h->h_off_hi[block] : h->h_off_lo[block];
   const int BY = prec_bytes(prec), V = 16 / BY;
-  std::vector<uint8_t> raw((size_t)B * B * BY);
+  const bool band = h->storage == BJAC_STORE_BAND;
+  const int w = band ? (which == 1 ? h->h_w_hi[block] : h->h_w_lo[block]) : 0;
+  std::vector<uint8_t> raw((size_t)B * (band ? w + 1 : B) * BY);
   double sc = 1.0;
   MPB_HIP(hipMemcpyAsync(raw.data(), h->ws + off, raw.size(), hipMemcpyDeviceToHost, h->stream));
   MPB_HIP(hipMemcpyAsync(&sc, (which == 1 ? h->scale_hi : h->scale_lo) + block, sizeof(double),
                          hipMemcpyDeviceToHost, h->stream));
   MPB_HIP(hipStreamSynchronize(h->stream));
-  for (int i = 0; i < b; ++i)
-    for (int j = 0; j < b; ++j) out[(size_t)i * b + j] = decode(raw.data() + layout_elem(B, V, i, j) * BY, prec);
+  for (int i = 0; i < b; ++i) {
+    for (int j = 0; j < b; ++j) {
+      if (!band) {
+        out[(size_t)i * b + j] = decode(raw.data() + layout_elem(B, V, i, j) * BY, prec);
+      } else {
+        const int d = std::abs(i - j);
+        out[(size_t)i * b + j] = d > w ? 0.0 : decode(raw.data() + ((size_t)d * B + std::min(i, j)) * BY, prec);
+      }
+    }
+  }
   if (scale) *scale = sc;
+  return BJAC_OK;
+}
+
+extern "C" int bjac_get_band(const bjac_handle *h, int32_t which, uint8_t *w) {
+  if (!h || !w || h->kind != 0 || h->storage != BJAC_STORE_BAND) return BJAC_EINVAL;
+  if (which == 1 && !h->w_hi) return BJAC_EINVAL;
+  if (which != 0 && which != 1) return BJAC_EINVAL;
+  const std::vector<uint8_t> &src = which == 1 ? h->h_w_hi : h->h_w_lo;
+  std::memcpy(w, src.data(), h->nb);
   return BJAC_OK;
 }

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstring>
 #include <unordered_map>
 #include <vector>
@@ -653,6 +654,163 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
+// Band-stored maps: block k keeps the diagonals d = 0..w_k of its symmetric
+// inverse, diagonal d as bpad_k entries E(d, j) = H[j][j + d] (zero where
+// j + d >= b_k) at base + off[k] + (d * bpad_k + j) * bytes. Lane li of a
+// block forms
+//   z_li = s_k (sum_{d=0}^{w_k} E(d, li) r_{li+d} + sum_{d=1}^{w_k} E(d, li-d) r_{li-d})
+// and loads only its own E(d, li): E(d, li - d) and r_{li+-d} are the values
+// of lanes li -+ d, moved across the wave. The blocks of a wave tile sit on
+// consecutive lanes, so lane li - d belongs to the same block exactly when
+// li >= d, and E(d, li) = 0 wherever li + d leaves the block. Diagonals are
+// loaded eight at a time, all in flight before the first product; the lane
+// moves run in wave-uniform control flow.
+template <int P>
+__device__ __forceinline__ float band_load32(const uint8_t *p) {
+  if constexpr (P == P32) return *(const float *)p;
+  else if constexpr (P == PBF16) return __uint_as_float((uint32_t)(*(const uint16_t *)p) << 16);
+  else return f16_bits(*(const uint16_t *)p);
+}
+
+__device__ __forceinline__ double band_load_any(const uint8_t *blk, int64_t idx, int prec) {
+  switch (prec) {
+    case P64: return ((const double *)blk)[idx];
+    case P32: return (double)((const float *)blk)[idx];
+    case PBF16: return (double)__uint_as_float((uint32_t)((const uint16_t *)blk)[idx] << 16);
+    default: return (double)f16_bits(((const uint16_t *)blk)[idx]);
+  }
+}
+
+__device__ __forceinline__ double fma_t(double x, double y, double z) { return fma(x, y, z); }
+__device__ __forceinline__ float fma_t(float x, float y, float z) { return fmaf(x, y, z); }
+
+// PU: the precision of every block of the map, or -1 (per-block tags; FP64
+// blocks in FP64, the others in FP32 on the FP32 copy of r).
+template <int MODE, int PU>
+__global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
+  using T = ModeTraits<MODE>;
+  constexpr int DC = 8;
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (apply_skip<MODE>(a)) return;
+  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const int lane = threadIdx.x & 63;
+  double rr = 0.0, rz = 0.0;
+  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+    const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
+    const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
+    const int kl = k0 + min(lane, nk - 1);
+    const int mB = a.bpad[kl], mrow = a.blk_row[kl], mrow1 = a.blk_row[kl + 1];
+    const int64_t moff = a.map.off[kl];
+    const double msc = a.map.scale[kl];
+    const int mtag = a.map.tag[kl], mw = a.map.w[kl];
+    int cum = 0, row0 = 0, bsz = 0, li = -1, Bp = 0, wl = -1, tg = 0, wmax = 0;
+    int64_t off = 0;
+    double sc = 1.0;
+    for (int i = 0; i < nk; ++i) {
+      const int Bi = readlane_i(mB, i);
+      const int wi = readlane_i(mw, i);
+      const int64_t oi = readlane_l(moff, i);
+      const double si = bcast(msc, i);
+      const int ti = readlane_i(mtag, i);
+      const int r0i = readlane_i(mrow, i);
+      const int r1i = readlane_i(mrow1, i);
+      wmax = max(wmax, wi);
+      if (lane >= cum && lane < cum + Bi) {
+        li = lane - cum;
+        row0 = r0i;
+        bsz = r1i - r0i;
+        Bp = Bi;
+        wl = wi;
+        off = oi;
+        sc = si;
+        tg = ti;
+      }
+      cum += Bi;
+    }
+    const bool real = li >= 0 && li < bsz;
+    const int grow = row0 + li;
+    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    const uint8_t *__restrict__ blk = a.map.base + off;
+    double zv;
+    if constexpr (PU >= 0) {
+      using CT = std::conditional_t<PU == P64, double, float>;
+      constexpr int BY = prec_bytes(PU);
+      CT rc;
+      if constexpr (PU == P64) rc = rv;
+      else rc = __double2float_rn(rv);
+      CT acc = CT(0);
+      for (int d0 = 0; d0 <= wmax; d0 += DC) {
+        CT e[DC];
+#pragma unroll
+        for (int u = 0; u < DC; ++u) {
+          const int d = d0 + u;
+          e[u] = CT(0);
+          if (li >= 0 && d <= wl) {
+            const uint8_t *p = blk + ((int64_t)d * Bp + li) * BY;
+            if constexpr (PU == P64) e[u] = *(const double *)p;
+            else e[u] = band_load32<PU>(p);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < DC; ++u) {
+          const int d = d0 + u;
+          if (d > wmax) break;
+          if (d == 0) {
+            acc = fma_t(e[u], rc, acc);
+            continue;
+          }
+          const CT rup = __shfl_down(rc, d, kWave);
+          const CT elo = __shfl_up(e[u], d, kWave);
+          const CT rdn = __shfl_up(rc, d, kWave);
+          acc = fma_t(e[u], rup, acc);
+          if (li >= d) acc = fma_t(elo, rdn, acc);
+        }
+      }
+      zv = (PU == P64) ? (double)acc : (double)acc * sc;
+    } else {
+      const bool f64 = tg == P64;
+      const float r32 = __double2float_rn(rv);
+      double acc64 = 0.0;
+      float acc32 = 0.0f;
+      for (int d0 = 0; d0 <= wmax; d0 += DC) {
+        double e[DC];
+#pragma unroll
+        for (int u = 0; u < DC; ++u) {
+          const int d = d0 + u;
+          e[u] = (li >= 0 && d <= wl) ? band_load_any(blk, (int64_t)d * Bp + li, tg) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < DC; ++u) {
+          const int d = d0 + u;
+          if (d > wmax) break;
+          if (d == 0) {
+            if (f64) acc64 = fma(e[u], rv, acc64);
+            else acc32 = fmaf((float)e[u], r32, acc32);
+            continue;
+          }
+          const double rup = __shfl_down(rv, d, kWave);
+          const double elo = __shfl_up(e[u], d, kWave);
+          const double rdn = __shfl_up(rv, d, kWave);
+          if (f64) {
+            acc64 = fma(e[u], rup, acc64);
+            if (li >= d) acc64 = fma(elo, rdn, acc64);
+          } else {
+            acc32 = fmaf((float)e[u], __double2float_rn(rup), acc32);
+            if (li >= d) acc32 = fmaf((float)elo, __double2float_rn(rdn), acc32);
+          }
+        }
+      }
+      zv = f64 ? acc64 : (double)acc32 * sc;
+    }
+    if (real) {
+      a.z[grow] = zv;
+      rz = fma(rv, zv, rz);
+    }
+  }
+  if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
+}
+
 // ------------------------------------------------------------ small kernels
 __global__ void state_init_kernel(PcgState *st, double tol, int maxit, double adp_tol, int temporal,
                                   double *relres_hist, uint8_t *high_hist) {
@@ -967,11 +1125,11 @@ struct MapSel {
 };
 
 static MapSel sel_lo(const bjac_handle *h) {
-  return MapSel{DevMap{h->ws, h->off_lo, h->scale_lo, h->tag_lo}, h->uprec_lo, h->fast_lo, h->lo_off0};
+  return MapSel{DevMap{h->ws, h->off_lo, h->scale_lo, h->tag_lo, h->w_lo}, h->uprec_lo, h->fast_lo, h->lo_off0};
 }
 static MapSel sel_hi(const bjac_handle *h) {
   if (!h->off_hi) return sel_lo(h);
-  return MapSel{DevMap{h->ws, h->off_hi, h->scale_hi, h->tag_hi}, (int)P64, h->fast_hi, h->hi_off0};
+  return MapSel{DevMap{h->ws, h->off_hi, h->scale_hi, h->tag_hi, h->w_hi}, (int)P64, h->fast_hi, h->hi_off0};
 }
 
 template <class K>
@@ -990,7 +1148,24 @@ static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
 }
 
 template <int MODE>
+static void launch_band(int prec, hipStream_t s, const ApplyArgs &a) {
+  switch (prec) {
+    case P64: launch_persistent(apply_band_kernel<MODE, P64>, s, a); break;
+    case P32: launch_persistent(apply_band_kernel<MODE, P32>, s, a); break;
+    case PBF16: launch_persistent(apply_band_kernel<MODE, PBF16>, s, a); break;
+    case P16: launch_persistent(apply_band_kernel<MODE, P16>, s, a); break;
+    default: launch_persistent(apply_band_kernel<MODE, -1>, s, a); break;
+  }
+}
+
+template <int MODE>
 static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, const ApplyArgs &a) {
+  if constexpr (MODE != M_UPD) {
+    if (m.map.w) {
+      launch_band<MODE>(m.prec, s, a);
+      return;
+    }
+  }
   // the update-only mode reads no map: any fast instance serves
   const bool fast = MODE == M_UPD ? h->rows_uniform : m.fast;
   const int prec = MODE == M_UPD ? (int)P16 : m.prec;

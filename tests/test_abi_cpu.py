@@ -36,7 +36,7 @@ def test_library_loads_and_exports_all_symbols():
 def test_struct_sizes_match_header_layout():
     import ctypes as C
     assert C.sizeof(binding.bjac_csr) == 40
-    assert C.sizeof(binding.bjac_policy) == 56
+    assert C.sizeof(binding.bjac_policy) == 64
     assert C.sizeof(binding.bjac_solve_opts) == 40
     assert C.sizeof(binding.bjac_stats) == 88
     assert C.sizeof(binding.bjac_info) == 64
