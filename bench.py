@@ -25,6 +25,10 @@ Other workloads (each prints its own line of the same form):
   --workload rhd       synthetic radiation-diffusion-like systems at 128^3:
                        coupled 3T (eq. 4-3, 6.3M rows) and 1T, stored
                        inverses and paper mode, and a P_diag sweep (Sec. 4.5.2)
+  --workload band      128^3 log-uniform diffusion, blocks of 32: full vs
+                       band-truncated storage of the inverses (diagonals
+                       kept down to the format's unit roundoff), FP64 /
+                       FP32 / FP16
   --workload paper     the paper's own setting (Sec. 4.2, Table 4.2): 128^3
                        Diff3D-Const / Dis(1000) / Ani(s), f = 1, 32 slabs,
                        BJAC(k=2, t=2) uniform FP64 vs fMP FP32 vs aMP(hl/lh)
@@ -56,11 +60,12 @@ def spmv_bytes(n, nnz):
     return 12 * nnz + 4 * (n + 1) + 32 * n
 
 
-def apply_bytes(n, nb, ntiles, stored_bytes):
+def apply_bytes(n, nb, ntiles, stored_bytes, band=False):
     """Algorithmic bytes of one fused update + apply launch: the stored block
-    inverses, per-block metadata (offset 8, scale 8, tag 1, row start 4), the
-    tile list, and x, r read+written, p, q read, z written."""
-    return stored_bytes + 21 * nb + 4 * (ntiles + 1) + 56 * n
+    inverses, per-block metadata (offset 8, scale 8, tag 1, row start 4, and
+    the half-bandwidth 1 for band storage), the tile list, and x, r
+    read+written, p, q read, z written."""
+    return stored_bytes + (22 if band else 21) * nb + 4 * (ntiles + 1) + 56 * n
 
 
 def cpu_baseline(p, iters_hint, budget_iters=8):
@@ -526,6 +531,100 @@ def bench_policies(args):
     }
 
 
+# ------------------------------------------------ band-truncated storage
+def bench_band(args):
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    N = args.N or 128
+    log("building the workload")
+    p = gen.config2(seed=0, N=N, b=32)
+    n, nnz, nb = p.A.n, p.A.nnz, len(p.block_ptr) - 1
+    A = mb.DeviceCSR(p.A, dev)
+    b = torch.as_tensor(p.b, device=dev)
+    solver = mb.Solver(n, dev)
+    band = dict(storage=mb.STORE_BAND)
+    pols = {"fp64_full": mb.Policy(mode=mb.UNIFORM), "fp16_full": mb.Policy(mode=mb.FIXED, low=mb.FP16),
+            "fp64_band": mb.Policy(mode=mb.UNIFORM, **band), "fp32_band": mb.Policy(mode=mb.FIXED, low=mb.FP32, **band),
+            "fp16_band": mb.Policy(mode=mb.FIXED, low=mb.FP16, **band)}
+    head = "fp16_band"
+
+    def step(policy, profile=False):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        M = mb.BlockJacobi(A, p.block_ptr, policy)
+        e1.record()
+        res = solver.solve(A, M, b, tol=p.tol, maxit=p.maxit, profile=profile, verify=0 if profile else VERIFY)
+        e2.record()
+        return M, res, (e0, e1, e2)
+
+    S = p.A.to_scipy()
+    bn = float(np.linalg.norm(p.b))
+    rows, kern_all = {}, {}
+    for name, pol in pols.items():
+        for _ in range(args.warmup):
+            step(pol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [step(pol) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        M, res, ev = runs[-1]
+        info = M.info()
+        is_band = pol.storage == mb.STORE_BAND
+        w = M.band_widths() if is_band else None
+        rows[name] = {"ms_per_step": ms, "iters": res.iters, "status": res.status, "restarts": res.restarts,
+                      "true_relres": float(np.linalg.norm(p.b - S @ res.x.cpu().numpy()) / bn),
+                      "setup_ms": float(np.median([r[2][0].elapsed_time(r[2][1]) for r in runs])),
+                      "solve_ms": float(np.median([r[2][1].elapsed_time(r[2][2]) for r in runs])),
+                      "stored_bytes": info["low_bytes"],
+                      "mean_width": float(w.mean()) if is_band else None,
+                      "max_width": int(w.max()) if is_band else None}
+        # per-kernel event timing of the same solve
+        _, rp, _ = step(pol, profile=True)
+        kb = {"spmv": spmv_bytes(n, nnz),
+              "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"], band=is_band)}
+        kern = {}
+        for kname in ("spmv", "apply"):
+            tot, cnt = rp.kernel_ms[kname]
+            avg_ms = tot / max(1, cnt)
+            kern[kname] = {"launches": cnt, "avg_us": avg_ms * 1e3, "bytes": kb[kname],
+                           "gbs": kb[kname] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
+        kern_all[name] = kern
+        rows[name]["apply_us"] = kern["apply"]["avg_us"]
+        rows[name]["apply_gbs"] = kern["apply"]["gbs"]
+        log(f"{name}: {ms:.1f} ms/step, {res.iters} iterations, stored {info['low_bytes'] / 1e6:.1f} MB, "
+            f"apply {kern['apply']['avg_us']:.1f} us ({kern['apply']['gbs']:.0f} GB/s)")
+        del M, runs
+    kern = kern_all[head]
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": f"{dom}_kernel",
+                "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(p, rows[head]["iters"])
+    hv = rows[head]
+    return {
+        "metric": METRIC, "value": hv["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "apply_arith": "band-truncated fp16-stored block inverses, f32 accumulation",
+        "config": {"workload": f"diff3d_loguniform_{N}^3_b32_band", "n": n, "nnz": nnz, "blocks": nb,
+                   "block_rows": 32, "precision_map": "fp16 fixed, band storage", "tol": p.tol, "seed": 0},
+        "policies": rows, "speedup_vs_fp64_full": rows["fp64_full"]["ms_per_step"] / hv["ms_per_step"],
+        "speedup_vs_fp16_full": rows["fp16_full"]["ms_per_step"] / hv["ms_per_step"],
+        "delay_iters": hv["iters"] - rows["fp64_full"]["iters"],
+        "kernels": kern_all, "roofline": roofline, "cpu_baseline": cpu,
+    }
+
+
 # ------------------------------------------------- the paper's own setting
 # Iteration counts printed by the paper (Table 4.2; Sec. 4.5.1 for Ani(s)),
 # BJAC k = t = 2 on 32 blocks, tol 1e-10, fp32 low precision, Diff3D 128^3.
@@ -684,7 +783,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=None, help="grid edge (diff3d 128, aniso 160, selector 192)")
     ap.add_argument("--workload", default="diff3d",
-                    choices=("diff3d", "batched", "aniso", "selector", "paper", "rhd"))
+                    choices=("diff3d", "batched", "aniso", "selector", "paper", "rhd", "band"))
     ap.add_argument("--nsys", type=int, default=256, help="batched: number of systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",
@@ -703,6 +802,8 @@ def main():
         line = bench_paper(args)
     elif args.workload == "rhd":
         line = bench_rhd(args)
+    elif args.workload == "band":
+        line = bench_band(args)
     else:
         args.N = args.N or (160 if args.workload == "aniso" else 192)
         line = bench_policies(args)

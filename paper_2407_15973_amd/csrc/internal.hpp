@@ -15,7 +15,8 @@ constexpr int kWaveRows = 64;       // padded rows of one apply wave tile
 constexpr int kSpmvRows = 64;       // rows of one SpMV wave tile
 constexpr int kSpmvNnzCap = 448;    // CSR entries staged in LDS per SpMV wave tile
 constexpr int kMaxGrid = 2048;      // persistent workgroups (multiple of 8)
-constexpr int kGridPerCu = 4;       // persistent workgroups per compute unit
+constexpr int kGridPerCu = 3;       // persistent workgroups per compute unit (measured: more
+                                    // resident streams lower the HBM rate of these kernels)
 
 // Device-resident PCG scalars. Written only by the last workgroup of each
 // kernel (ticket pattern) and by the init kernel.

@@ -107,17 +107,6 @@ __device__ __forceinline__ void publish(double *slot, double v) {
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double collect(double *slot, bool &ok) {
-  uint64_t u;
-  int spins = 0;
-  do {
-    u = __hip_atomic_load((uint64_t *)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } while (u == kEmpty && ++spins < kSpinCap);
-  ok = ok && u != kEmpty;
-  __hip_atomic_store((uint64_t *)slot, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)u);
-}
-
 // Returns true in every thread of the workgroup that took the last ticket.
 __device__ __forceinline__ bool last_workgroup(uint32_t *ticket, int *sh_flag) {
   __syncthreads();
@@ -129,15 +118,56 @@ __device__ __forceinline__ bool last_workgroup(uint32_t *ticket, int *sh_flag) {
   return *sh_flag != 0;
 }
 
-// Deterministic fixed-order sum of the n published partials (stride `stride`)
-// by the last workgroup; result valid in thread 0. ok_out (thread 0) turns
-// false if a slot never filled.
-__device__ __forceinline__ double sum_partials(double *p, int n, int stride, double *sh, int *ok_out) {
-  double s = 0.0;
+// Deterministic fixed-order sums of NS interleaved sets of n published
+// partials (partial i of set s at p[i * stride + s]) by the last workgroup;
+// results valid in thread 0. ok_out (thread 0) turns false if a slot never
+// filled. Every thread first issues the loads of all its slots (at most
+// kMaxGrid / 256 per set; indices past n re-read slot n - 1 and are ignored),
+// so the collection costs one memory round trip rather than one per slot;
+// only slots still empty are polled again.
+template <int NS>
+__device__ __forceinline__ void sum_partials_n(double *p, int n, int stride, double *sh, int *ok_out,
+                                               double (&out)[NS]) {
+  constexpr int K = kMaxGrid / 256;
+  uint64_t u[K][NS];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = min((int)threadIdx.x + 256 * k, n - 1);
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+      u[k][q] = __hip_atomic_load((uint64_t *)(p + (int64_t)i * stride + q), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  }
+  double acc[NS];
+#pragma unroll
+  for (int q = 0; q < NS; ++q) acc[q] = 0.0;
   bool ok = true;
-  for (int i = threadIdx.x; i < n; i += 256) s += collect(p + (int64_t)i * stride, ok);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = (int)threadIdx.x + 256 * k;
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        double *slot = p + (int64_t)i * stride + q;
+        uint64_t v = u[k][q];
+        int spins = 0;
+        while (v == kEmpty && ++spins < kSpinCap)
+          v = __hip_atomic_load((uint64_t *)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = ok && v != kEmpty;
+        __hip_atomic_store((uint64_t *)slot, kEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        acc[q] += __longlong_as_double((long long)v);
+      }
+    }
+  }
   if (!ok) atomicAnd(ok_out, 0);
-  return block_sum(s, sh);
+#pragma unroll
+  for (int q = 0; q < NS; ++q) out[q] = block_sum(acc[q], sh);
+}
+
+__device__ __forceinline__ double sum_partials(double *p, int n, int stride, double *sh, int *ok_out) {
+  double out[1];
+  sum_partials_n<1>(p, n, stride, sh, ok_out, out);
+  return out[0];
 }
 
 __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
@@ -453,8 +483,17 @@ __device__ __forceinline__ void apply_epilogue(const ApplyArgs &a, double rr, do
   }
   uint32_t *ticket = T::UPD ? &a.st->ticket_b : &a.st->ticket_c;
   if (last_workgroup(ticket, flag)) {
-    const double trr = T::UPD ? sum_partials(a.part, gridDim.x, 2, sh, flag + 1) : 0.0;
-    const double trz = T::APP ? sum_partials(a.part + 1, gridDim.x, 2, sh, flag + 1) : 0.0;
+    double trr = 0.0, trz = 0.0;
+    if constexpr (T::UPD && T::APP) {
+      double both[2];
+      sum_partials_n<2>(a.part, gridDim.x, 2, sh, flag + 1, both);
+      trr = both[0];
+      trz = both[1];
+    } else if constexpr (T::UPD) {
+      trr = sum_partials(a.part, gridDim.x, 2, sh, flag + 1);
+    } else {
+      trz = sum_partials(a.part + 1, gridDim.x, 2, sh, flag + 1);
+    }
     if (threadIdx.x == 0) {
       PcgState *st = a.st;
       if (!flag[1]) {
@@ -665,31 +704,128 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
 // li >= d, and E(d, li) = 0 wherever li + d leaves the block. Diagonals are
 // loaded eight at a time, all in flight before the first product; the lane
 // moves run in wave-uniform control flow.
-template <int P>
-__device__ __forceinline__ float band_load32(const uint8_t *p) {
-  if constexpr (P == P32) return *(const float *)p;
-  else if constexpr (P == PBF16) return __uint_as_float((uint32_t)(*(const uint16_t *)p) << 16);
-  else return f16_bits(*(const uint16_t *)p);
-}
-
-__device__ __forceinline__ double band_load_any(const uint8_t *blk, int64_t idx, int prec) {
-  switch (prec) {
-    case P64: return ((const double *)blk)[idx];
-    case P32: return (double)((const float *)blk)[idx];
-    case PBF16: return (double)__uint_as_float((uint32_t)((const uint16_t *)blk)[idx] << 16);
-    default: return (double)f16_bits(((const uint16_t *)blk)[idx]);
-  }
-}
-
 __device__ __forceinline__ double fma_t(double x, double y, double z) { return fma(x, y, z); }
 __device__ __forceinline__ float fma_t(float x, float y, float z) { return fmaf(x, y, z); }
 
+// The band product of one lane: li is the lane's row in its block (-1: no
+// block), Bp the block's padded size, wl its half-bandwidth, wmax the largest
+// half-bandwidth of the wave (wave-uniform), tg its precision, sc its scale.
 // PU: the precision of every block of the map, or -1 (per-block tags; FP64
 // blocks in FP64, the others in FP32 on the FP32 copy of r).
+// Eight diagonals are taken per round, with no branch inside a round: the
+// loads read positions clamped into the lane's own block (d -> min(d, w),
+// li -> max(li, 0)), so all eight are in flight together, and entries past
+// the lane's width are zeroed (a branch would let the compiler sink loads
+// behind it and wait for each in turn). The lane moves go four at a time.
+template <int PU>
+__device__ __forceinline__ double band_product(const uint8_t *__restrict__ blk, int Bp, int li, int wl, int wmax,
+                                               int tg, double sc, double rv) {
+  constexpr int DC = 8, DQ = 4;
+  const int wc = max(wl, 0), lc = max(li, 0);
+  if constexpr (PU >= 0) {
+    using CT = std::conditional_t<PU == P64, double, float>;
+    using RT = std::conditional_t<PU == P64, uint64_t, std::conditional_t<PU == P32, uint32_t, uint16_t>>;
+    constexpr int BY = prec_bytes(PU);
+    CT rc;
+    if constexpr (PU == P64) rc = rv;
+    else rc = __double2float_rn(rv);
+    CT acc = CT(0);
+    for (int d0 = 0; d0 <= wmax; d0 += DC) {
+      RT raw[DC];
+#pragma unroll
+      for (int u = 0; u < DC; ++u)
+        raw[u] = *(const RT *)(blk + ((int64_t)min(d0 + u, wc) * Bp + lc) * BY);
+      CT e[DC];
+#pragma unroll
+      for (int u = 0; u < DC; ++u) {
+        CT v;
+        if constexpr (PU == P64) v = __longlong_as_double((long long)raw[u]);
+        else if constexpr (PU == P32) v = __uint_as_float(raw[u]);
+        else if constexpr (PU == PBF16) v = __uint_as_float((uint32_t)raw[u] << 16);
+        else v = f16_bits(raw[u]);
+        e[u] = (li >= 0 && d0 + u <= wl) ? v : CT(0);
+      }
+#pragma unroll
+      for (int g = 0; g < DC; g += DQ) {
+        CT rup[DQ], rdn[DQ], elo[DQ];
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const int d = d0 + g + q;
+          rup[q] = __shfl_down(rc, d, kWave);
+          rdn[q] = __shfl_up(rc, d, kWave);
+          elo[q] = __shfl_up(e[g + q], d, kWave);
+        }
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const int d = d0 + g + q;
+          acc = fma_t(e[g + q], rup[q], acc);
+          if (d >= 1 && li >= d) acc = fma_t(elo[q], rdn[q], acc);
+        }
+      }
+    }
+    return (PU == P64) ? (double)acc : (double)acc * sc;
+  } else {
+    // the 8-byte-aligned word holding the entry (every block starts on a
+    // 32-byte boundary and spans a multiple of 32 bytes, so the word lies in
+    // the block), then the entry picked out of it by format
+    const bool f64 = tg == P64;
+    const int BY = prec_bytes(tg);
+    const float r32 = __double2float_rn(rv);
+    double acc64 = 0.0;
+    float acc32 = 0.0f;
+    for (int d0 = 0; d0 <= wmax; d0 += DC) {
+      uint2 raw[DC];
+      int64_t bo[DC];
+#pragma unroll
+      for (int u = 0; u < DC; ++u) {
+        bo[u] = ((int64_t)min(d0 + u, wc) * Bp + lc) * BY;
+        raw[u] = *(const uint2 *)(blk + (bo[u] & ~(int64_t)7));
+      }
+      double e[DC];
+#pragma unroll
+      for (int u = 0; u < DC; ++u) {
+        const int b4 = (int)(bo[u] & 7);
+        const uint32_t w32 = (b4 & 4) ? raw[u].y : raw[u].x;
+        const uint32_t h16 = (b4 & 2) ? (w32 >> 16) : (w32 & 0xffffu);
+        double v;
+        if (tg == P64) v = __hiloint2double((int)raw[u].y, (int)raw[u].x);
+        else if (tg == P32) v = (double)__uint_as_float(w32);
+        else if (tg == PBF16) v = (double)__uint_as_float(h16 << 16);
+        else v = (double)f16_bits((uint16_t)h16);
+        e[u] = (li >= 0 && d0 + u <= wl) ? v : 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < DC; g += DQ) {
+        double rup[DQ], rdn[DQ], elo[DQ];
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const int d = d0 + g + q;
+          rup[q] = __shfl_down(rv, d, kWave);
+          rdn[q] = __shfl_up(rv, d, kWave);
+          elo[q] = __shfl_up(e[g + q], d, kWave);
+        }
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const int d = d0 + g + q;
+          const bool lower = d >= 1 && li >= d;
+          if (f64) {
+            acc64 = fma(e[g + q], rup[q], acc64);
+            if (lower) acc64 = fma(elo[q], rdn[q], acc64);
+          } else {
+            acc32 = fmaf((float)e[g + q], __double2float_rn(rup[q]), acc32);
+            if (lower) acc32 = fmaf((float)elo[q], __double2float_rn(rdn[q]), acc32);
+          }
+        }
+      }
+    }
+    return f64 ? acc64 : (double)acc32 * sc;
+  }
+}
+
+// Generic band path: blocks of different sizes; the wave tiles of the setup.
 template <int MODE, int PU>
 __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
   using T = ModeTraits<MODE>;
-  constexpr int DC = 8;
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
@@ -731,78 +867,45 @@ __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
     const bool real = li >= 0 && li < bsz;
     const int grow = row0 + li;
     const double rv = row_update<MODE>(a, alpha, real, grow, rr);
-    const uint8_t *__restrict__ blk = a.map.base + off;
-    double zv;
-    if constexpr (PU >= 0) {
-      using CT = std::conditional_t<PU == P64, double, float>;
-      constexpr int BY = prec_bytes(PU);
-      CT rc;
-      if constexpr (PU == P64) rc = rv;
-      else rc = __double2float_rn(rv);
-      CT acc = CT(0);
-      for (int d0 = 0; d0 <= wmax; d0 += DC) {
-        CT e[DC];
-#pragma unroll
-        for (int u = 0; u < DC; ++u) {
-          const int d = d0 + u;
-          e[u] = CT(0);
-          if (li >= 0 && d <= wl) {
-            const uint8_t *p = blk + ((int64_t)d * Bp + li) * BY;
-            if constexpr (PU == P64) e[u] = *(const double *)p;
-            else e[u] = band_load32<PU>(p);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < DC; ++u) {
-          const int d = d0 + u;
-          if (d > wmax) break;
-          if (d == 0) {
-            acc = fma_t(e[u], rc, acc);
-            continue;
-          }
-          const CT rup = __shfl_down(rc, d, kWave);
-          const CT elo = __shfl_up(e[u], d, kWave);
-          const CT rdn = __shfl_up(rc, d, kWave);
-          acc = fma_t(e[u], rup, acc);
-          if (li >= d) acc = fma_t(elo, rdn, acc);
-        }
-      }
-      zv = (PU == P64) ? (double)acc : (double)acc * sc;
-    } else {
-      const bool f64 = tg == P64;
-      const float r32 = __double2float_rn(rv);
-      double acc64 = 0.0;
-      float acc32 = 0.0f;
-      for (int d0 = 0; d0 <= wmax; d0 += DC) {
-        double e[DC];
-#pragma unroll
-        for (int u = 0; u < DC; ++u) {
-          const int d = d0 + u;
-          e[u] = (li >= 0 && d <= wl) ? band_load_any(blk, (int64_t)d * Bp + li, tg) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < DC; ++u) {
-          const int d = d0 + u;
-          if (d > wmax) break;
-          if (d == 0) {
-            if (f64) acc64 = fma(e[u], rv, acc64);
-            else acc32 = fmaf((float)e[u], r32, acc32);
-            continue;
-          }
-          const double rup = __shfl_down(rv, d, kWave);
-          const double elo = __shfl_up(e[u], d, kWave);
-          const double rdn = __shfl_up(rv, d, kWave);
-          if (f64) {
-            acc64 = fma(e[u], rup, acc64);
-            if (li >= d) acc64 = fma(elo, rdn, acc64);
-          } else {
-            acc32 = fmaf((float)e[u], __double2float_rn(rup), acc32);
-            if (li >= d) acc32 = fmaf((float)elo, __double2float_rn(rdn), acc32);
-          }
-        }
-      }
-      zv = f64 ? acc64 : (double)acc32 * sc;
+    const double zv = band_product<PU>(a.map.base + off, Bp, li, wl, wmax, tg, sc, rv);
+    if (real) {
+      a.z[grow] = zv;
+      rz = fma(rv, zv, rz);
     }
+  }
+  if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
+}
+
+// Fast band path: every block but the last has B rows (B = 16, 32, 48, 64),
+// so rows and blocks of a wave tile are arithmetic; each lane loads its own
+// block's offset, width and scale together with its vector entries.
+template <int B, int MODE, int PU>
+__global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
+  using T = ModeTraits<MODE>;
+  constexpr int NB = 64 / B;
+  constexpr int R = NB * B;
+  __shared__ double sh[4];
+  __shared__ int flag[2];
+  if (apply_skip<MODE>(a)) return;
+  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int j = lane / B, li0 = lane - j * B;
+  double rr = 0.0, rz = 0.0;
+  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+    const int kb = it.t * NB + j;
+    const int kc = min(kb, a.nb - 1);
+    const int grow = kb * B + li0;
+    const bool inb = lane < R && kb < a.nb;
+    const bool real = inb && grow < a.n;
+    const int64_t off = a.map.off[kc];
+    const int wl = inb ? (int)a.map.w[kc] : -1;
+    const double sc = PU == P64 ? 1.0 : a.map.scale[kc];
+    const int tg = PU >= 0 ? PU : (int)a.map.tag[kc];
+    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    int wmax = 0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) wmax = max(wmax, readlane_i(wl, q * B));
+    const double zv = band_product<PU>(a.map.base + off, B, inb ? li0 : -1, wl, wmax, tg, sc, rv);
     if (real) {
       a.z[grow] = zv;
       rz = fma(rv, zv, rz);
@@ -1147,8 +1250,30 @@ static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
   }
 }
 
+template <int MODE, int B>
+static void launch_band_fast(int prec, hipStream_t s, const ApplyArgs &a) {
+  switch (prec) {
+    case P64: launch_persistent(apply_band_fast_kernel<B, MODE, P64>, s, a); break;
+    case P32: launch_persistent(apply_band_fast_kernel<B, MODE, P32>, s, a); break;
+    case PBF16: launch_persistent(apply_band_fast_kernel<B, MODE, PBF16>, s, a); break;
+    case P16: launch_persistent(apply_band_fast_kernel<B, MODE, P16>, s, a); break;
+    default: launch_persistent(apply_band_fast_kernel<B, MODE, -1>, s, a); break;
+  }
+}
+
+// Band maps: the arithmetic tile path when every block but the last has the
+// common padded size, else the setup's tile list.
 template <int MODE>
-static void launch_band(int prec, hipStream_t s, const ApplyArgs &a) {
+static void launch_band(const bjac_handle *h, int prec, hipStream_t s, const ApplyArgs &a) {
+  if (h->rows_uniform && h->uniform_b) {
+    switch (h->uniform_b) {
+      case 16: launch_band_fast<MODE, 16>(prec, s, a); break;
+      case 32: launch_band_fast<MODE, 32>(prec, s, a); break;
+      case 48: launch_band_fast<MODE, 48>(prec, s, a); break;
+      default: launch_band_fast<MODE, 64>(prec, s, a); break;
+    }
+    return;
+  }
   switch (prec) {
     case P64: launch_persistent(apply_band_kernel<MODE, P64>, s, a); break;
     case P32: launch_persistent(apply_band_kernel<MODE, P32>, s, a); break;
@@ -1162,7 +1287,7 @@ template <int MODE>
 static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, const ApplyArgs &a) {
   if constexpr (MODE != M_UPD) {
     if (m.map.w) {
-      launch_band<MODE>(m.prec, s, a);
+      launch_band<MODE>(h, m.prec, s, a);
       return;
     }
   }
