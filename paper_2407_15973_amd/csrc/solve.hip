@@ -244,6 +244,9 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   double *sv = svs[wv];
   int *sc = scs[wv];
   double dot = 0.0;
+  bool s_has = false;   // q and p_new of the previous tile, stored after this tile's loads
+  int s_row = 0;
+  double s_q = 0.0, s_p = 0.0;
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int r0 = it.t * 64;
     const int r1 = min(a.n, r0 + 64);
@@ -266,6 +269,11 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
         vv[k] = vv_g[e0 + i];
         cc[k] = ci[e0 + i];
       }
+      if (s_has) {
+        a.q[s_row] = s_q;
+        if (PCG) a.pnew[s_row] = s_p;
+        s_has = false;
+      }
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         const int i = lane + 64 * k;
@@ -280,14 +288,22 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
     } else {
       acc = row_dot<PCG, false>(z, pold, ci, vv_g, beta, s, len, row, prow, found);
     }
-    if (has) {
-      a.q[row] = acc;
-      if (PCG) {
-        const double pr = found ? prow : fma(beta, pold[row], z[row]);
-        a.pnew[row] = pr;
-        dot = fma(pr, acc, dot);
-      }
+    if (s_has) {
+      a.q[s_row] = s_q;
+      if (PCG) a.pnew[s_row] = s_p;
     }
+    s_has = has;
+    s_row = row;
+    s_q = acc;
+    if (has && PCG) {
+      const double pr = found ? prow : fma(beta, pold[row], z[row]);
+      s_p = pr;
+      dot = fma(pr, acc, dot);
+    }
+  }
+  if (s_has) {
+    a.q[s_row] = s_q;
+    if (PCG) a.pnew[s_row] = s_p;
   }
   if (!PCG) return;
   const double bs = block_sum(dot, sh);
@@ -450,24 +466,43 @@ struct ModeTraits {
   static constexpr bool PCG = MODE != M_APP;
 };
 
-// Row phase of one lane: x += alpha p and r -= alpha q (update modes) or read r.
+// Row phase of one lane (x += alpha p, r -= alpha q in the update modes, else
+// read r), split into loads and stores: the kernels hold a tile's stores back
+// until the next tile's loads are out, because a wait for loads also waits for
+// every store issued before them (one counter), so storing at the end of a
+// tile would add a store round trip to every tile. Loads read a row clamped
+// into [0, n) and are zeroed for lanes without a row, so no branch separates
+// them.
+struct RowIn {
+  double x, p, q, r;
+};
+
 template <int MODE>
-__device__ __forceinline__ double row_update(const ApplyArgs &a, double alpha, bool real, int grow, double &rr) {
-  double rv = 0.0;
-  if (real) {
-    if constexpr (ModeTraits<MODE>::UPD) {
-      const double pv = a.p[grow], qv = a.q[grow], xv = a.x[grow], r0 = a.r[grow];
-      a.x[grow] = fma(alpha, pv, xv);
-      rv = fma(-alpha, qv, r0);
-      a.r[grow] = rv;
-      rr = fma(rv, rv, rr);
-    } else if constexpr (MODE == M_APP) {
-      rv = a.rin[grow];
-    } else {
-      rv = a.r[grow];
-    }
+__device__ __forceinline__ RowIn row_load(const ApplyArgs &a, bool real, int grow) {
+  const int gc = min(max(grow, 0), a.n - 1);
+  RowIn v{0.0, 0.0, 0.0, 0.0};
+  if constexpr (ModeTraits<MODE>::UPD) {
+    v.x = a.x[gc];
+    v.p = a.p[gc];
+    v.q = a.q[gc];
+    v.r = a.r[gc];
+  } else if constexpr (MODE == M_APP) {
+    v.r = a.rin[gc];
+  } else {
+    v.r = a.r[gc];
   }
-  return rv;
+  if (!real) v = RowIn{0.0, 0.0, 0.0, 0.0};
+  return v;
+}
+
+template <int MODE>
+__device__ __forceinline__ void row_store(const ApplyArgs &a, bool real, int grow, double xn, double rn, double zn) {
+  if (!real) return;
+  if constexpr (ModeTraits<MODE>::UPD) {
+    a.x[grow] = xn;
+    a.r[grow] = rn;
+  }
+  if constexpr (ModeTraits<MODE>::APP) a.z[grow] = zn;
 }
 
 // Reductions and the state machine at the end of a PCG launch.
@@ -545,6 +580,9 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
   double *zt = zts[wv];
   const int j = lane / B, li = lane - j * B;
   double rr = 0.0, rz = 0.0;
+  bool s_real = false;   // results of the previous tile, stored after this tile's loads
+  int s_grow = 0;
+  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = it.t * NB;
     const int kb = k0 + j;
@@ -559,7 +597,14 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
         for (int u = 0; u < MT; ++u) fr[u].load(base + (int64_t)min(k0 + u / MPB, a.nb - 1) * BLK, u % MPB, lane);
       }
     }
-    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    const RowIn v = row_load<MODE>(a, real, grow);
+    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+    double rv = v.r, xn = 0.0, zv_out = 0.0;
+    if constexpr (T::UPD) {
+      xn = fma(alpha, v.p, v.x);
+      rv = fma(-alpha, v.q, v.r);
+      rr = fma(rv, rv, rr);
+    }
     if constexpr (T::APP) {
       if (lane < R) {
         r64[lane] = rv;
@@ -585,12 +630,17 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
       }
       wave_lds_sync();
       if (real) {
-        const double zv = zt[lane];
-        a.z[grow] = zv;
-        rz = fma(rv, zv, rz);
+        zv_out = zt[lane];
+        rz = fma(rv, zv_out, rz);
       }
     }
+    s_real = real;
+    s_grow = grow;
+    s_x = xn;
+    s_r = rv;
+    s_z = zv_out;
   }
+  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -632,6 +682,9 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
   double *r64 = r64s[wv];
   double *zt = zts[wv];
   double rr = 0.0, rz = 0.0;
+  bool s_real = false;   // results of the previous tile, stored after this tile's loads
+  int s_grow = 0;
+  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
     const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
@@ -657,7 +710,14 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
     }
     const bool real = li >= 0 && li < bsz;
     const int grow = row0 + li;
-    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    const RowIn v = row_load<MODE>(a, real, grow);
+    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+    double rv = v.r, xn = 0.0, zv_out = 0.0;
+    if constexpr (T::UPD) {
+      xn = fma(alpha, v.p, v.x);
+      rv = fma(-alpha, v.q, v.r);
+      rr = fma(rv, rv, rr);
+    }
     if constexpr (T::APP) {
       if (lane < cum) {
         r64[lane] = rv;
@@ -684,12 +744,17 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
       }
       wave_lds_sync();
       if (real) {
-        const double zv = zt[lane];
-        a.z[grow] = zv;
-        rz = fma(rv, zv, rz);
+        zv_out = zt[lane];
+        rz = fma(rv, zv_out, rz);
       }
     }
+    s_real = real;
+    s_grow = grow;
+    s_x = xn;
+    s_r = rv;
+    s_z = zv_out;
   }
+  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -717,32 +782,60 @@ __device__ __forceinline__ float fma_t(float x, float y, float z) { return fmaf(
 // li -> max(li, 0)), so all eight are in flight together, and entries past
 // the lane's width are zeroed (a branch would let the compiler sink loads
 // behind it and wait for each in turn). The lane moves go four at a time.
+// A mixed map loads the 8-byte-aligned word holding each entry (every block
+// starts on a 32-byte boundary and spans a multiple of 32 bytes, so the word
+// lies in the block) and picks the entry out of it by format.
+constexpr int kBandRound = 8;
+
+template <int PU>
+struct BandRaw {
+  using T = std::conditional_t<PU == P64, uint64_t,
+                               std::conditional_t<PU == P32, uint32_t, std::conditional_t<PU >= 0, uint16_t, uint2>>>;
+  T v[kBandRound];
+};
+
+template <int PU>
+__device__ __forceinline__ void band_load_round(BandRaw<PU> &raw, const uint8_t *__restrict__ blk, int Bp, int lc,
+                                                int wc, int d0, int tg) {
+  using RT = typename BandRaw<PU>::T;
+  if constexpr (PU >= 0) {
+    constexpr int BY = prec_bytes(PU);
+#pragma unroll
+    for (int u = 0; u < kBandRound; ++u) raw.v[u] = *(const RT *)(blk + ((int64_t)min(d0 + u, wc) * Bp + lc) * BY);
+  } else {
+    const int BY = prec_bytes(tg);
+#pragma unroll
+    for (int u = 0; u < kBandRound; ++u) {
+      const int64_t bo = ((int64_t)min(d0 + u, wc) * Bp + lc) * BY;
+      raw.v[u] = *(const uint2 *)(blk + (bo & ~(int64_t)7));
+    }
+  }
+}
+
+// raw0: the first round (diagonals 0..7), already loaded by the caller.
 template <int PU>
 __device__ __forceinline__ double band_product(const uint8_t *__restrict__ blk, int Bp, int li, int wl, int wmax,
-                                               int tg, double sc, double rv) {
-  constexpr int DC = 8, DQ = 4;
+                                               int tg, double sc, double rv, const BandRaw<PU> &raw0) {
+  constexpr int DC = kBandRound, DQ = 4;
   const int wc = max(wl, 0), lc = max(li, 0);
   if constexpr (PU >= 0) {
     using CT = std::conditional_t<PU == P64, double, float>;
-    using RT = std::conditional_t<PU == P64, uint64_t, std::conditional_t<PU == P32, uint32_t, uint16_t>>;
-    constexpr int BY = prec_bytes(PU);
     CT rc;
     if constexpr (PU == P64) rc = rv;
     else rc = __double2float_rn(rv);
     CT acc = CT(0);
     for (int d0 = 0; d0 <= wmax; d0 += DC) {
-      RT raw[DC];
-#pragma unroll
-      for (int u = 0; u < DC; ++u)
-        raw[u] = *(const RT *)(blk + ((int64_t)min(d0 + u, wc) * Bp + lc) * BY);
+      BandRaw<PU> rn;
+      if (d0 > 0) band_load_round<PU>(rn, blk, Bp, lc, wc, d0, tg);
+      const BandRaw<PU> &raw = d0 > 0 ? rn : raw0;
       CT e[DC];
 #pragma unroll
       for (int u = 0; u < DC; ++u) {
         CT v;
-        if constexpr (PU == P64) v = __longlong_as_double((long long)raw[u]);
-        else if constexpr (PU == P32) v = __uint_as_float(raw[u]);
-        else if constexpr (PU == PBF16) v = __uint_as_float((uint32_t)raw[u] << 16);
-        else v = f16_bits(raw[u]);
+        if constexpr (PU == P64) v = __longlong_as_double((long long)raw.v[u]);
+        else if constexpr (PU == P32) v = __uint_as_float(raw.v[u]);
+        else if constexpr (PU == PBF16) v = __uint_as_float((uint32_t)raw.v[u] << 16);
+        else v = f16_bits(raw.v[u]);
         e[u] = (li >= 0 && d0 + u <= wl) ? v : CT(0);
       }
 #pragma unroll
@@ -765,30 +858,23 @@ __device__ __forceinline__ double band_product(const uint8_t *__restrict__ blk, 
     }
     return (PU == P64) ? (double)acc : (double)acc * sc;
   } else {
-    // the 8-byte-aligned word holding the entry (every block starts on a
-    // 32-byte boundary and spans a multiple of 32 bytes, so the word lies in
-    // the block), then the entry picked out of it by format
     const bool f64 = tg == P64;
     const int BY = prec_bytes(tg);
     const float r32 = __double2float_rn(rv);
     double acc64 = 0.0;
     float acc32 = 0.0f;
     for (int d0 = 0; d0 <= wmax; d0 += DC) {
-      uint2 raw[DC];
-      int64_t bo[DC];
-#pragma unroll
-      for (int u = 0; u < DC; ++u) {
-        bo[u] = ((int64_t)min(d0 + u, wc) * Bp + lc) * BY;
-        raw[u] = *(const uint2 *)(blk + (bo[u] & ~(int64_t)7));
-      }
+      BandRaw<PU> rn;
+      if (d0 > 0) band_load_round<PU>(rn, blk, Bp, lc, wc, d0, tg);
+      const BandRaw<PU> &raw = d0 > 0 ? rn : raw0;
       double e[DC];
 #pragma unroll
       for (int u = 0; u < DC; ++u) {
-        const int b4 = (int)(bo[u] & 7);
-        const uint32_t w32 = (b4 & 4) ? raw[u].y : raw[u].x;
+        const int b4 = (int)((((int64_t)min(d0 + u, wc) * Bp + lc) * BY) & 7);
+        const uint32_t w32 = (b4 & 4) ? raw.v[u].y : raw.v[u].x;
         const uint32_t h16 = (b4 & 2) ? (w32 >> 16) : (w32 & 0xffffu);
         double v;
-        if (tg == P64) v = __hiloint2double((int)raw[u].y, (int)raw[u].x);
+        if (tg == P64) v = __hiloint2double((int)raw.v[u].y, (int)raw.v[u].x);
         else if (tg == P32) v = (double)__uint_as_float(w32);
         else if (tg == PBF16) v = (double)__uint_as_float(h16 << 16);
         else v = (double)f16_bits((uint16_t)h16);
@@ -832,6 +918,9 @@ __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
   const double alpha = T::UPD ? a.st->alpha : 0.0;
   const int lane = threadIdx.x & 63;
   double rr = 0.0, rz = 0.0;
+  bool s_real = false;   // results of the previous tile, stored after this tile's loads
+  int s_grow = 0;
+  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
     const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
@@ -866,19 +955,32 @@ __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
     }
     const bool real = li >= 0 && li < bsz;
     const int grow = row0 + li;
-    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
-    const double zv = band_product<PU>(a.map.base + off, Bp, li, wl, wmax, tg, sc, rv);
-    if (real) {
-      a.z[grow] = zv;
-      rz = fma(rv, zv, rz);
+    BandRaw<PU> raw0;
+    band_load_round<PU>(raw0, a.map.base + off, Bp, max(li, 0), max(wl, 0), 0, tg);
+    const RowIn v = row_load<MODE>(a, real, grow);
+    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+    double rv = v.r, xn = 0.0;
+    if constexpr (T::UPD) {
+      xn = fma(alpha, v.p, v.x);
+      rv = fma(-alpha, v.q, v.r);
+      rr = fma(rv, rv, rr);
     }
+    const double zv = band_product<PU>(a.map.base + off, Bp, li, wl, wmax, tg, sc, rv, raw0);
+    if (real) rz = fma(rv, zv, rz);
+    s_real = real;
+    s_grow = grow;
+    s_x = xn;
+    s_r = rv;
+    s_z = zv;
   }
+  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
 // Fast band path: every block but the last has B rows (B = 16, 32, 48, 64),
-// so rows and blocks of a wave tile are arithmetic; each lane loads its own
-// block's offset, width and scale together with its vector entries.
+// so rows and blocks of a wave tile are arithmetic. Each lane fetches the
+// offset and width of its block in the wave's next tile one tile ahead, so the
+// diagonal loads of a tile go out together with its vector loads.
 template <int B, int MODE, int PU>
 __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
   using T = ModeTraits<MODE>;
@@ -891,26 +993,49 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
   const int lane = threadIdx.x & 63;
   const int j = lane / B, li0 = lane - j * B;
   double rr = 0.0, rz = 0.0;
-  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+  WaveIter it(a.ntiles);
+  // block indices are clamped to the last block, so every fetch is in bounds
+  int kn = min(it.t * NB + j, a.nb - 1);
+  int64_t off_n = a.map.off[kn];
+  int w_n = a.map.w[kn];
+  bool s_real = false;   // results of the previous tile, stored after this tile's loads
+  int s_grow = 0;
+  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
+  for (; it.t < it.end; it.t += it.step) {
     const int kb = it.t * NB + j;
     const int kc = min(kb, a.nb - 1);
     const int grow = kb * B + li0;
     const bool inb = lane < R && kb < a.nb;
     const bool real = inb && grow < a.n;
-    const int64_t off = a.map.off[kc];
-    const int wl = inb ? (int)a.map.w[kc] : -1;
+    const int64_t off = off_n;
+    const int wl = inb ? w_n : -1;
+    kn = min((it.t + it.step) * NB + j, a.nb - 1);
+    off_n = a.map.off[kn];
+    w_n = a.map.w[kn];
     const double sc = PU == P64 ? 1.0 : a.map.scale[kc];
     const int tg = PU >= 0 ? PU : (int)a.map.tag[kc];
-    const double rv = row_update<MODE>(a, alpha, real, grow, rr);
+    BandRaw<PU> raw0;
+    band_load_round<PU>(raw0, a.map.base + off, B, inb ? li0 : 0, max(wl, 0), 0, tg);
+    const RowIn v = row_load<MODE>(a, real, grow);
+    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);   // the previous tile's results
+    double rv = v.r, xn = 0.0;
+    if constexpr (T::UPD) {
+      xn = fma(alpha, v.p, v.x);
+      rv = fma(-alpha, v.q, v.r);
+      rr = fma(rv, rv, rr);
+    }
     int wmax = 0;
 #pragma unroll
     for (int q = 0; q < NB; ++q) wmax = max(wmax, readlane_i(wl, q * B));
-    const double zv = band_product<PU>(a.map.base + off, B, inb ? li0 : -1, wl, wmax, tg, sc, rv);
-    if (real) {
-      a.z[grow] = zv;
-      rz = fma(rv, zv, rz);
-    }
+    const double zv = band_product<PU>(a.map.base + off, B, inb ? li0 : -1, wl, wmax, tg, sc, rv, raw0);
+    if (real) rz = fma(rv, zv, rz);
+    s_real = real;
+    s_grow = grow;
+    s_x = xn;
+    s_r = rv;
+    s_z = zv;
   }
+  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
