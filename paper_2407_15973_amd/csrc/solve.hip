@@ -247,15 +247,27 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   bool s_has = false;   // q and p_new of the previous tile, stored after this tile's loads
   int s_row = 0;
   double s_q = 0.0, s_p = 0.0;
-  for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
+  // row pointers of a lane's row in tile t (tile clamped into range, row into
+  // the tile), fetched one tile ahead
+  auto fetch_rp = [&](int t, int &s_out, int &e_out) {
+    const int tc = min(t, a.ntiles - 1);
+    const int rc = min(tc * 64 + lane, min(a.n, tc * 64 + 64) - 1);
+    s_out = rp[rc];
+    e_out = rp[rc + 1];
+  };
+  WaveIter it(a.ntiles);
+  int s_nx, e_nx;
+  fetch_rp(it.t, s_nx, e_nx);
+  for (; it.t < it.end; it.t += it.step) {
     const int r0 = it.t * 64;
     const int r1 = min(a.n, r0 + 64);
     const int row = r0 + lane;
     const bool has = row < r1;
-    const int rowc = min(row, r1 - 1);
-    const int s = rp[rowc], e = rp[rowc + 1];
-    const int e0 = __builtin_amdgcn_readfirstlane(rp[r0]);
-    const int cnt = __builtin_amdgcn_readfirstlane(rp[r1]) - e0;
+    const int s = s_nx, e = e_nx;
+    fetch_rp(it.t + it.step, s_nx, e_nx);
+    // rp[r0] is lane 0's start, rp[r1] the end of the tile's last row
+    const int e0 = __builtin_amdgcn_readlane(s, 0);
+    const int cnt = __builtin_amdgcn_readlane(e, r1 - 1 - r0) - e0;
     const int len = has ? e - s : 0;
     double acc = 0.0, prow = 0.0;
     bool found = false;
