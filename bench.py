@@ -104,8 +104,8 @@ VERIFY = 3
 # profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
 # for the kernel sources they were measured on: reported when the digest of
 # those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "60bc5f4fc3e25516df297942fea4160176585786d9eb4c02f43c02058ca12684",
-           "spmv": 277648286, "apply": 252405049}
+TRAFFIC = {"sources_sha256": "d925479d105dcfbde814e41610eeff6a0e5728e8fe49261c28fe2337292b49c9",
+           "spmv": 279752684, "apply": 252366991}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
@@ -603,8 +603,10 @@ def bench_band(args):
     kern = kern_all[head]
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     dk = kern[dom]
+    # the SpMV is the same kernel as in the default workload: its measured traffic applies
+    traffic = measured_traffic(dom) if (N == 128 and dom == "spmv") else None
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": f"{dom}_kernel",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": f"{dom}_kernel",
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     cpu = None
     if not args.no_cpu_baseline:
