@@ -149,8 +149,8 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         const int i = min(lane + 64 * k, cnt - 1);
-        vv[k] = a.v[e0 + i];
-        cc[k] = a.ci[e0 + i];
+        vv[k] = __builtin_nontemporal_load(a.v + e0 + i);     // read once per product:
+        cc[k] = __builtin_nontemporal_load(a.ci + e0 + i);    // do not displace the vectors
       }
 #pragma unroll
       for (int k = 0; k < NL; ++k) {

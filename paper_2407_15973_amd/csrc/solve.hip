@@ -272,14 +272,18 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
     double acc = 0.0, prow = 0.0;
     bool found = false;
     if (cnt > 0 && cnt <= CAP) {
-      // coalesced staging of the tile's CSR entries into this wave's LDS
+      // coalesced staging of the tile's CSR entries into this wave's LDS. The
+      // matrix is read once per product: non-temporal loads keep it from
+      // displacing the vectors, which the next kernel then finds in the
+      // last-level cache (measured: SpMV unchanged, fused apply 51 -> 46 us at
+      // 128^3; the same hint on the stored inverses made the apply slower)
       double vv[NL];
       int cc[NL];
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         const int i = min(lane + 64 * k, cnt - 1);
-        vv[k] = vv_g[e0 + i];
-        cc[k] = ci[e0 + i];
+        vv[k] = __builtin_nontemporal_load(vv_g + e0 + i);
+        cc[k] = __builtin_nontemporal_load(ci + e0 + i);
       }
       if (s_has) {
         a.q[s_row] = s_q;
