@@ -219,3 +219,65 @@ def test_band_errors():
     bs = mb.BatchSolver(Ad, M, np.array([0, A.n], np.int32), np.array([1], np.int32))
     with pytest.raises(mb.MpbjacError):
         bs.solve(tensor(np.ones(A.n)))
+
+
+def test_band_full_width_equals_full_storage():
+    # a vanishing tolerance keeps every diagonal (w = b - 1: eight rounds of
+    # eight diagonals for 64-row blocks); the band application then multiplies
+    # the symmetrised full inverse: within rounding of the full-storage result
+    A, bp, rng = _case(seed=14, shape=(16, 16, 8), b=64)
+    Ad = mb.DeviceCSR(A, dev())
+    for prec in (OPr.FP32, OPr.FP64):
+        pol = dict(mode=mb.FIXED, low=prec) if prec != OPr.FP64 else dict(mode=mb.UNIFORM)
+        Mb = mb.BlockJacobi(Ad, bp, _band_policy(band_rtol=1e-300, **pol))
+        Mf = mb.BlockJacobi(Ad, bp, mb.Policy(**pol))
+        assert np.all(Mb.band_widths() == np.diff(bp) - 1)
+        r = rng.uniform(-1, 1, A.n)
+        zb = Mb.apply(tensor(r)).cpu().numpy()
+        zf = Mf.apply(tensor(r)).cpu().numpy()
+        H = OB.invert_blocks(A, bp)
+        store = OB.store_blocks(H, np.full(len(H), prec, np.uint8))
+        u = 2.0 ** -24 if prec == OPr.FP32 else 2.0 ** -53
+        # both within the accumulation bound of the same products, plus the
+        # asymmetry of the computed inverse (the band mirrors its upper triangle)
+        kap = max(np.linalg.cond(h, 1) for h in H)
+        bound = (2 * gamma(64, u) + ULP_REL[prec] + 16 * 64 * kap * 2.0 ** -53) * OB.apply_abs(store, bp, r)
+        assert np.all(np.abs(zb - zf) <= bound + 1e-300)
+
+
+def test_band_full_size_sampled_parity():
+    # the 128^3 benchmark workload with FP16 band storage: sampled blocks
+    # against the oracle (widths, stored values, application rows), and the
+    # PCG iteration count of full storage (truncation at u_16 leaves it)
+    p = gen.config2(seed=0)
+    nb = len(p.block_ptr) - 1
+    Ad = mb.DeviceCSR(p.A, dev())
+    M = mb.BlockJacobi(Ad, p.block_ptr, _band_policy(mode=mb.FIXED, low=mb.FP16))
+    rng = np.random.default_rng(15)
+    ks = rng.choice(nb, size=48, replace=False)
+    sub = np.concatenate([[0], np.cumsum(np.diff(p.block_ptr)[ks])]).astype(np.int32)
+    rows = np.concatenate([np.arange(p.block_ptr[k], p.block_ptr[k + 1]) for k in ks])
+    S = p.A.to_scipy()[rows][:, rows]
+    Asub = gen.CSR(len(rows), S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    H = OB.invert_blocks(Asub, sub)
+    tags = np.full(len(ks), OPr.FP16, np.uint8)
+    wg = M.band_widths()[ks]
+    ref = OB.store_blocks_band(H, tags)
+    for j in range(len(ks)):
+        assert _width_agrees(H[j], int(wg[j]), ref[j][3], 2.0 ** -11)
+    store = [(OPr.round_to_format(OB.band_part(Hk, int(w)) / s, OPr.FP16), s, OPr.FP16, int(w))
+             for Hk, w, (_, s, _, _) in zip(H, wg, ref)]
+    r = rng.uniform(-1, 1, p.A.n)
+    z = M.apply(tensor(r)).cpu().numpy()
+    zref = OB.apply(store, sub, r[rows])
+    assert np.all(np.abs(z[rows] - zref) <= _apply_bound(store, sub, r[rows], tags, H) + 1e-300)
+    for j, k in enumerate(ks[:8]):
+        got, s = M.block(int(k))
+        assert s == store[j][1] and np.all(np.abs(got - store[j][0]) <= ulp(store[j][0], OPr.FP16) * 1.0000001)
+    S = mb.Solver(p.A.n, dev())
+    res = S.solve(Ad, M, tensor(p.b), tol=1e-10, maxit=5000)
+    Mf = mb.BlockJacobi(Ad, p.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    res_f = S.solve(Ad, Mf, tensor(p.b), tol=1e-10, maxit=5000)
+    print(f"128^3 FP16: band {res.iters} iterations, full {res_f.iters}")
+    assert res.status == mb.OK and abs(res.iters - res_f.iters) <= 2
+    assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10
