@@ -639,6 +639,23 @@ PAPER_TABLE_4_2 = {
 PAPER_ANI = {1000: (327, 327), 100: (321, 321), 10: (205, 205), 4: (179, 179), 2: (159, 177), 1: (148, 165)}
 
 
+def poly_apply_bytes(n, nnz, k, t, tb):
+    """Algorithmic bytes of one paper-mode application BJAC(k, t) with values
+    of tb bytes: the first sweep from y = 0 (r, 1/a_ii read; v, y written),
+    t - 1 block sweeps per outer step (row pointers, block ranges, the CSR
+    entries, v, y, 1/a_ii read and y written; the last sweep of a later step
+    also reads the step's start), k - 1 residuals A z (CSR, v, z, 1/a_ii read;
+    w, y written), and the widening of z with (r, z)."""
+    csr = 4 * (n + 1) + (4 + tb) * nnz
+    first = (8 + 3 * tb) * n
+    sweep = csr + 8 * n + 4 * tb * n
+    resid = csr + 5 * tb * n + (tb * n if t == 1 else 0)
+    finish = (16 + tb) * n
+    sweeps = (t - 1) * k
+    adds = (k - 1) if t > 1 else 0
+    return first + sweeps * sweep + adds * tb * n + (k - 1) * resid + finish
+
+
 def bench_paper(args):
     import numpy as np
     import torch
@@ -690,14 +707,34 @@ def bench_paper(args):
         if name == "Const":
             head_ms = row["fMP"]["ms"]
             speed = row["uniform"]["ms"] / row["fMP"]["ms"]
+            # per-kernel event timing of the same solves
+            kern = {}
+            for pname, low in (("fMP", True), ("uniform", False)):
+                M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low)
+                rp = S.solve(Ad, M, b, tol=1e-10, maxit=2000, profile=True)
+                kb = {"spmv": spmv_bytes(A.n, A.nnz), "apply": poly_apply_bytes(A.n, A.nnz, 2, 2, 4 if low else 8),
+                      "update": 48 * A.n}
+                for kname in ("spmv", "apply", "update"):
+                    tot, cnt = rp.kernel_ms[kname]
+                    avg_ms = tot / max(1, cnt)
+                    kern[f"{pname}_{kname}"] = {"launches": cnt, "avg_us": avg_ms * 1e3, "bytes": kb[kname],
+                                                "gbs": kb[kname] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
+                log(f"  profile {pname}: " + ", ".join(f"{kn} {kern[pname + '_' + kn]['avg_us']:.1f} us"
+                                                       for kn in ("spmv", "apply", "update")))
         del Ad, S
         torch.cuda.empty_cache()
+    # the application (five kernels: first sweep, block sweep, residual, block
+    # sweep, widening) dominates; its bytes over its event-timed duration
+    dk = kern["fMP_apply"]
+    roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": "paper-mode application (FP32)",
+                "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     return {
         "metric": METRIC, "value": head_ms, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "apply_arith": "paper-mode BJAC(2, 2): FP32 (fMP) or FP64 application", "data": "synthetic",
         "config": {"workload": f"paper_mode_diff3d_{N}^3_32slabs_k2t2_f1", "tol": 1e-10},
-        "speedup_vs_fp64": speed, "runs": runs,
+        "speedup_vs_fp64": speed, "runs": runs, "kernels": kern, "roofline": roofline, "cpu_baseline": None,
     }
 
 

@@ -157,7 +157,9 @@ typedef struct {
   int32_t high_applications;     /* applications that used the FP64 map       */
   int32_t graph_launches;
   double solve_ms;               /* wall time of the solve on the stream       */
-  /* profile mode only: summed kernel durations over the iterations that ran */
+  /* profile mode only: summed kernel durations over the iterations that ran.
+     apply_ms covers the application (with the x / r update when fused);
+     update_ms the separate update launch of adaptive and paper-mode handles */
   double spmv_ms, apply_ms, update_ms;
   int32_t n_spmv, n_apply, n_update;
   int32_t restarts;              /* verify: residual replacements performed    */

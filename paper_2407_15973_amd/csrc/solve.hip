@@ -1175,39 +1175,107 @@ __global__ __launch_bounds__(256) void poly_first_kernel(PolyArgs a, const doubl
   }
 }
 
-// yout = yin + D^-1 (v - D_b yin) [+ add]: D_b keeps the entries whose column
-// lies in the row's block
-template <class T>
-__global__ __launch_bounds__(256) void poly_sweep_kernel(PolyArgs a, const T *v, const T *yin, T *yout,
-                                                         const T *add) {
-  if (poly_skip(a)) return;
-  const T *val = (const T *)a.val, *dinv = (const T *)a.dinv;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
-    const int lo = a.rlo[i], hi = a.rhi[i];
-    T acc = 0;
-    for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
-      const int j = a.ci[k];
-      if (j >= lo && j < hi) acc += val[k] * yin[j];
+// The two CSR passes of an application, over wave tiles of 64 rows whose CSR
+// entries are staged in LDS with coalesced (non-temporal) loads, as in the PCG
+// SpMV; each lane then gathers its row's neighbours eight at a time with every
+// load in flight (index-clamped, masked entries multiplied by zero):
+//   PO_SWEEP: yout = yin + D^-1 (v - D_b yin) [+ add], D_b keeping the entries
+//             whose column lies in the row's block;
+//   PO_RESID: w = v - A z; y = D^-1 w; with zout (t = 1) zout = z + y.
+// Entries are summed in row order.
+enum PolyOp { PO_SWEEP = 0, PO_RESID = 1 };
+
+template <class T, int OP>
+__device__ __forceinline__ T poly_row_dot(const T *__restrict__ xin, const int *__restrict__ cidx,
+                                          const T *__restrict__ vals, int base, int len, int lo, int hi) {
+  constexpr int U = 8;
+  T acc = T(0);
+  for (int k0 = 0; k0 < len; k0 += U) {
+    int cs[U];
+    T vs[U], g[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int idx = base + min(k0 + k, len - 1);
+      cs[k] = cidx[idx];
+      const T vv = vals[idx];
+      const bool keep = k0 + k < len && (OP == PO_RESID || (cs[k] >= lo && cs[k] < hi));
+      vs[k] = keep ? vv : T(0);
     }
-    T yi = yin[i] + dinv[i] * (v[i] - acc);
-    if (add) yi = add[i] + yi;
-    yout[i] = yi;
+#pragma unroll
+    for (int k = 0; k < U; ++k) g[k] = xin[cs[k]];
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc = fma_t(vs[k], g[k], acc);
   }
+  return acc;
 }
 
-// w = v - A z; y = D^-1 w; with zout (t = 1): zout = z + y
-template <class T>
-__global__ __launch_bounds__(256) void poly_resid_kernel(PolyArgs a, const T *v, const T *z, T *w, T *y, T *zout) {
+template <class T, int OP>
+__global__ __launch_bounds__(256) void poly_csr_kernel(PolyArgs a, const T *v, const T *xin, T *o1, T *o2, T *o3,
+                                                       const T *add) {
+  constexpr int CAP = kSpmvNnzCap;
+  constexpr int NL = CAP / 64;
+  __shared__ T svs[4][CAP];
+  __shared__ int scs[4][CAP];
   if (poly_skip(a)) return;
-  const T *val = (const T *)a.val, *dinv = (const T *)a.dinv;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
-    T acc = 0;
-    for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) acc += val[k] * z[a.ci[k]];
-    const T wi = v[i] - acc;
-    w[i] = wi;
-    const T yi = dinv[i] * wi;
-    y[i] = yi;
-    if (zout) zout[i] = z[i] + yi;
+  const T *__restrict__ val = (const T *)a.val;
+  const T *__restrict__ dinv = (const T *)a.dinv;
+  const int32_t *__restrict__ rp = a.rp;
+  const int32_t *__restrict__ ci = a.ci;
+  const int n = (int)a.n;
+  const int ntiles = (n + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T *sv = svs[wv];
+  int *sc = scs[wv];
+  for (WaveIter it(ntiles); it.t < it.end; it.t += it.step) {
+    const int r0 = it.t * 64;
+    const int r1 = min(n, r0 + 64);
+    const int row = r0 + lane;
+    const bool has = row < r1;
+    const int rowc = min(row, r1 - 1);
+    const int s = rp[rowc], e = rp[rowc + 1];
+    const int e0 = __builtin_amdgcn_readlane(s, 0);
+    const int cnt = __builtin_amdgcn_readlane(e, r1 - 1 - r0) - e0;
+    const int len = has ? e - s : 0;
+    const int lo = OP == PO_SWEEP ? a.rlo[rowc] : 0;
+    const int hi = OP == PO_SWEEP ? a.rhi[rowc] : 0;
+    T acc;
+    if (cnt > 0 && cnt <= CAP) {
+      T vv[NL];
+      int cc[NL];
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const int i = min(lane + 64 * k, cnt - 1);
+        vv[k] = __builtin_nontemporal_load(val + e0 + i);
+        cc[k] = __builtin_nontemporal_load(ci + e0 + i);
+      }
+#pragma unroll
+      for (int k = 0; k < NL; ++k) {
+        const int i = lane + 64 * k;
+        if (i < cnt) {
+          sv[i] = vv[k];
+          sc[i] = cc[k];
+        }
+      }
+      wave_lds_sync();
+      acc = poly_row_dot<T, OP>(xin, sc, sv, s - e0, len, lo, hi);
+      wave_lds_sync();
+    } else {
+      acc = poly_row_dot<T, OP>(xin, ci, val, s, len, lo, hi);
+    }
+    if (has) {
+      if constexpr (OP == PO_SWEEP) {
+        T yi = xin[row] + dinv[row] * (v[row] - acc);
+        if (add) yi = add[row] + yi;
+        o1[row] = yi;
+      } else {
+        const T wi = v[row] - acc;
+        o1[row] = wi;
+        const T yi = dinv[row] * wi;
+        o2[row] = yi;
+        if (o3) o3[row] = xin[row] + yi;
+      }
+    }
   }
 }
 
@@ -1241,36 +1309,6 @@ __global__ __launch_bounds__(256) void poly_finish_kernel(PolyArgs a, const T *z
   }
 }
 
-// x += alpha p, r -= alpha q, (r, r) and the state transition after it
-__global__ __launch_bounds__(256) void poly_update_kernel(int64_t n, PcgState *st, double *x, double *r,
-                                                          const double *p, const double *q, double *part) {
-  __shared__ double sh[4];
-  __shared__ int flag[2];
-  if (st->status != ST_RUNNING) return;
-  const double alpha = st->alpha;
-  double rr = 0.0;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double pv = p[i], qv = q[i], xv = x[i], r0 = r[i];
-    x[i] = fma(alpha, pv, xv);
-    const double rv = fma(-alpha, qv, r0);
-    r[i] = rv;
-    rr = fma(rv, rv, rr);
-  }
-  const double brr = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    publish(part + 2 * blockIdx.x, brr);
-    flag[1] = 1;
-  }
-  if (last_workgroup(&st->ticket_b, flag)) {
-    const double trr = sum_partials(part, gridDim.x, 2, sh, flag + 1);
-    if (threadIdx.x == 0) {
-      if (!flag[1]) st->status = ST_SYNC_FAIL;
-      else after_update(st, trr);
-      __hip_atomic_store(&st->ticket_b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
 static int poly_grid(int64_t n) { return (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (n + 255) / 256)); }
 
 // One application z = M^-1 r of a paper-mode handle in precision T.
@@ -1279,6 +1317,9 @@ static void enqueue_poly_app(const bjac_handle *M, PolyArgs a, const double *r, 
                              hipStream_t s) {
   const int64_t n = M->n;
   const int G = poly_grid(n);
+  const int ntiles = (int)((n + 63) / 64);
+  const int GC = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_SWEEP>);
+  const int GR = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_RESID>);
   a.val = sizeof(T) == 4 ? (const void *)M->val32 : (const void *)M->pval;
   a.dinv = sizeof(T) == 4 ? (const void *)M->dinv32 : (const void *)M->dinv64;
   T *v = (T *)M->pbuf, *w = (T *)(M->pbuf + n), *ya = (T *)(M->pbuf + 2 * n), *yb = (T *)(M->pbuf + 3 * n);
@@ -1290,8 +1331,8 @@ static void enqueue_poly_app(const bjac_handle *M, PolyArgs a, const double *r, 
     T *in = ya, *spare = yb;
     for (int sw = 2; sw <= t; ++sw) {
       T *out = sw == t ? za : spare;
-      hipLaunchKernelGGL(poly_sweep_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)v, (const T *)in, out,
-                         (const T *)nullptr);
+      hipLaunchKernelGGL((poly_csr_kernel<T, PO_SWEEP>), dim3(GC), dim3(256), 0, s, a, (const T *)v, (const T *)in,
+                         out, (T *)nullptr, (T *)nullptr, (const T *)nullptr);
       spare = in;
       in = out;
     }
@@ -1299,13 +1340,13 @@ static void enqueue_poly_app(const bjac_handle *M, PolyArgs a, const double *r, 
   T *zc = za;
   for (int j = 2; j <= k; ++j) {
     T *zn = zc == za ? zb : za;
-    hipLaunchKernelGGL(poly_resid_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)v, (const T *)zc, w, ya,
-                       t == 1 ? zn : (T *)nullptr);
+    hipLaunchKernelGGL((poly_csr_kernel<T, PO_RESID>), dim3(GR), dim3(256), 0, s, a, (const T *)v, (const T *)zc,
+                       w, ya, t == 1 ? zn : (T *)nullptr, (const T *)nullptr);
     T *in = ya, *spare = yb;
     for (int sw = 2; sw <= t; ++sw) {
       T *out = sw == t ? zn : spare;
-      hipLaunchKernelGGL(poly_sweep_kernel<T>, dim3(G), dim3(256), 0, s, a, (const T *)w, (const T *)in, out,
-                         sw == t ? (const T *)zc : (const T *)nullptr);
+      hipLaunchKernelGGL((poly_csr_kernel<T, PO_SWEEP>), dim3(GC), dim3(256), 0, s, a, (const T *)w, (const T *)in,
+                         out, (T *)nullptr, (T *)nullptr, sw == t ? (const T *)zc : (const T *)nullptr);
       spare = in;
       in = out;
     }
@@ -1513,9 +1554,20 @@ static hipStream_t capture_stream() {
 static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs &w, bool temporal, const double *p,
                                  hipStream_t s, hipEvent_t *ev) {
   if (M->kind == 1) {
+    // the x / r update on 64-row wave tiles (the update mode of the block
+    // application kernels, which reads no map)
+    ApplyArgs ua{};
+    ua.ntiles = (int32_t)((M->n + 63) / 64);
+    ua.nb = ua.ntiles;
+    ua.n = (int32_t)M->n;
+    ua.x = x;
+    ua.r = w.r;
+    ua.p = p;
+    ua.q = w.q;
+    ua.st = w.st;
+    ua.part = w.part2;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(poly_update_kernel, dim3(poly_grid(M->n)), dim3(256), 0, s, (int64_t)M->n, w.st, x, w.r, p,
-                       (const double *)w.q, w.part2);
+    launch_persistent(apply_fast_kernel<64, P16, M_UPD>, s, ua);
     if (ev) (void)hipEventRecord(ev[1], s);
     if (temporal) {
       enqueue_poly_map(M, 1, w.st, w.r, w.z, w.part2, s);
@@ -1582,7 +1634,7 @@ static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, cons
       (void)hipEventElapsedTime(&b, e[1], e[2]);
       prof.t[0] += a;
       prof.n[0] += 1;
-      if (temporal) {
+      if (temporal || M->kind == 1) {   // separate update and application launches
         (void)hipEventElapsedTime(&c, e[2], e[3]);
         prof.t[2] += b;
         prof.n[2] += 1;
