@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "device_util.hpp"
@@ -391,6 +392,122 @@ __device__ __forceinline__ void bblock(int B, int prec, const uint8_t *blk, doub
   }
 }
 
+// Band-stored blocks: block i keeps diagonals d = 0..w_i, diagonal d as B_i
+// entries E_i(d, j) = H[j][j + d] (zero where j + d leaves the block). Lane lr
+// owns LDS row lr (row li = lr - cb_i of block i) and forms, for every column c,
+//   z = s_i (sum_{d<=w_i} E_i(d, li) r[lr + d][c] + sum_{1<=d<=w_i} E_i(d, li - d) r[lr - d][c])
+// on the FP32 copy of r with FP32 accumulation (FP64 for FP64 blocks). A lane
+// loads only its own E_i(d, li), once for all columns; E_i(d, li - d) is lane
+// lr - d's value, moved across the wave (the tile's blocks sit on consecutive
+// rows, so lane lr - d is in the same block exactly when li >= d). Eight
+// diagonals a round, loaded as the 8-byte-aligned words holding the entries
+// (every block starts on a 32-byte boundary and spans a multiple of 32 bytes)
+// from positions clamped into the block, all in flight together.
+__device__ __forceinline__ double bband_entry(uint2 w, int64_t bo, int prec) {
+  const int b4 = (int)(bo & 7);
+  const uint32_t w32 = (b4 & 4) ? w.y : w.x;
+  const uint32_t h16 = (b4 & 2) ? (w32 >> 16) : (w32 & 0xffffu);
+  if (prec == P64) return __hiloint2double((int)w.y, (int)w.x);
+  if (prec == P32) return (double)__uint_as_float(w32);
+  if (prec == PBF16) return (double)__uint_as_float(h16 << 16);
+  return (double)f16_bits((uint16_t)h16);
+}
+
+template <int BP>
+__device__ __forceinline__ void bband_tile(const BApplyArgs &a, int nk, const int (&cbo)[4], int cum, int M, int mB,
+                                           int mtag, int64_t moff, double msc, int mw, const double *r64,
+                                           const float *r32, double *zt, int lane) {
+  constexpr int DC = 8;
+  int Bv[4], tv[4], wv_[4];
+  int64_t ov[4];
+  double sv[4];
+  int wmax = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int src = min(i, max(nk - 1, 0));
+    Bv[i] = __builtin_amdgcn_readlane(mB, src);
+    tv[i] = __builtin_amdgcn_readlane(mtag, src);
+    wv_[i] = __builtin_amdgcn_readlane(mw, src);
+    const int lo = __builtin_amdgcn_readlane((int)(moff & 0xffffffff), src);
+    const int hi = __builtin_amdgcn_readlane((int)(moff >> 32), src);
+    ov[i] = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    sv[i] = bcast(msc, src);
+    if (i < nk) wmax = max(wmax, wv_[i]);
+  }
+  const int lr = lane;
+  const bool mine = lr < cum;
+  const int i = (lr >= cbo[1] && nk > 1) + (lr >= cbo[2] && nk > 2) + (lr >= cbo[3] && nk > 3);
+  const int B = i == 0 ? Bv[0] : i == 1 ? Bv[1] : i == 2 ? Bv[2] : Bv[3];
+  const int prec = BP >= 0 ? BP : (i == 0 ? tv[0] : i == 1 ? tv[1] : i == 2 ? tv[2] : tv[3]);
+  const int w = mine ? (i == 0 ? wv_[0] : i == 1 ? wv_[1] : i == 2 ? wv_[2] : wv_[3]) : -1;
+  const int64_t off = i == 0 ? ov[0] : i == 1 ? ov[1] : i == 2 ? ov[2] : ov[3];
+  const double sc = i == 0 ? sv[0] : i == 1 ? sv[1] : i == 2 ? sv[2] : sv[3];
+  const int cb = i == 0 ? cbo[0] : i == 1 ? cbo[1] : i == 2 ? cbo[2] : cbo[3];
+  const int li = mine ? lr - cb : 0;
+  const int wc = max(w, 0);
+  const int BY = prec_bytes(prec);
+  const bool f64 = prec == P64;
+  const uint8_t *blk = a.map.base + off;
+  using RT = std::conditional_t<BP == P64, uint64_t,
+                                std::conditional_t<BP == P32, uint32_t, std::conditional_t<BP >= 0, uint16_t, uint2>>>;
+  double acc64[kBCols];
+  float acc32[kBCols];
+#pragma unroll
+  for (int c = 0; c < kBCols; ++c) {
+    acc64[c] = 0.0;
+    acc32[c] = 0.0f;
+  }
+  for (int d0 = 0; d0 <= wmax; d0 += DC) {
+    RT hw[DC];
+    int64_t hb[DC];
+#pragma unroll
+    for (int u = 0; u < DC; ++u) {
+      hb[u] = ((int64_t)min(d0 + u, wc) * B + li) * BY;
+      if constexpr (BP >= 0) hw[u] = *(const RT *)(blk + hb[u]);
+      else hw[u] = *(const uint2 *)(blk + (hb[u] & ~(int64_t)7));
+    }
+#pragma unroll
+    for (int u = 0; u < DC; ++u) {
+      const int d = d0 + u;
+      double ev;
+      if constexpr (BP == P64) ev = __longlong_as_double((long long)hw[u]);
+      else if constexpr (BP == P32) ev = (double)__uint_as_float(hw[u]);
+      else if constexpr (BP == PBF16) ev = (double)__uint_as_float((uint32_t)hw[u] << 16);
+      else if constexpr (BP == P16) ev = (double)f16_bits(hw[u]);
+      else ev = bband_entry(hw[u], hb[u], prec);
+      const double eh = (mine && d <= w) ? ev : 0.0;
+      const double el = __shfl_up(eh, d, 64);
+      const bool lower = mine && d >= 1 && li >= d;
+      const int ru = min(lr + d, kBWaveRows - 1), rd = max(lr - d, 0);
+      // all eight columns (columns >= M and padding rows are zero in LDS)
+      if (f64) {
+#pragma unroll
+        for (int c = 0; c < kBCols; ++c) {
+          acc64[c] = fma(eh, r64[ru * kBCols + c], acc64[c]);
+          if (lower) acc64[c] = fma(el, r64[rd * kBCols + c], acc64[c]);
+        }
+      } else {
+        const float4 *pu = (const float4 *)(r32 + ru * kBCols);
+        const float4 *pd = (const float4 *)(r32 + rd * kBCols);
+        const float4 u0 = pu[0], u1 = pu[1], w0 = pd[0], w1 = pd[1];
+        const float ru8[kBCols] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        const float rd8[kBCols] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+        const float e32 = (float)eh, l32 = lower ? (float)el : 0.0f;
+#pragma unroll
+        for (int c = 0; c < kBCols; ++c) {
+          acc32[c] = fmaf(e32, ru8[c], acc32[c]);
+          acc32[c] = fmaf(l32, rd8[c], acc32[c]);
+        }
+      }
+    }
+  }
+  if (mine) {
+#pragma unroll
+    for (int c = 0; c < kBCols; ++c)
+      if (c < M) zt[lr * kBCols + c] = f64 ? acc64[c] : (double)acc32[c] * sc;
+  }
+}
+
 __device__ __forceinline__ int rl(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
 __device__ __forceinline__ int64_t rl64(int64_t v, int src) {
   const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), src);
@@ -408,9 +525,13 @@ __device__ __forceinline__ int64_t rl64(int64_t v, int src) {
 //     LDS columns as the B operand, results to LDS;
 //  3. (r, r) and (r, z) per column from LDS: lane l takes column l mod 8;
 //  4. element phase: z back to HBM, contiguous.
-template <bool UPD>
+// BP: kFullBlocks (stored full blocks, matrix-core products), -1 (band
+// storage, per-block precision) or the common precision of a band map.
+constexpr int kFullBlocks = -2;
+
+template <bool UPD, int BP>
 __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int kend, int rs, int64_t v0, int64_t xv0,
-                                              int M, const double *alpha_g, double *r64, double *zt,
+                                              int M, const double *alpha_g, double *r64, float *r32, double *zt,
                                               double &rr, double &rz) {
   const int lane = threadIdx.x & 63;
   // per element-slot column and alpha: element e = pass * 64 + lane has
@@ -423,6 +544,7 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
     const int64_t moff = a.map.off[kq];
     const double msc = a.map.scale[kq];
     const int mtag = a.map.tag[kq];
+    const int mw = BP != kFullBlocks ? (int)a.map.w[kq] : 0;
     int nk = 0, cum = 0;
     while (nk < 4 && k0 + nk < kend && cum + rl(mB, nk) <= kBWaveRows) {
       cum += rl(mB, nk);
@@ -445,6 +567,7 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
 #pragma unroll
     for (int c = 0; c < kBCols; ++c) {
       r64[lane * kBCols + c] = 0.0;
+      if constexpr (BP != kFullBlocks) r32[lane * kBCols + c] = 0.0f;
     }
     bwave_lds_sync();
     const int E = nreal * M;
@@ -468,16 +591,21 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
       const int cb_i = i == 0 ? cbo[0] : i == 1 ? cbo[1] : i == 2 ? cbo[2] : cbo[3];
       const int lr = row - bs_i + cb_i;
       r64[lr * kBCols + c] = rv;
+      if constexpr (BP != kFullBlocks) r32[lr * kBCols + c] = __double2float_rn(rv);   // the FP32 copy of r
     }
     bwave_lds_sync();
-    // 2. block products
-    for (int i = 0; i < nk; ++i) {
-      const int B = rl(mB, i);
-      const int prec = rl(mtag, i);
-      const uint8_t *blk = a.map.base + rl64(moff, i);
-      const double sc = bcast(msc, i);
-      const int cb = cbo[i];
-      bblock(B, prec, blk, sc, r64 + cb * kBCols, zt + cb * kBCols, lane);
+    // 2. block products (band storage: row by row, all columns)
+    if constexpr (BP != kFullBlocks) {
+      bband_tile<BP>(a, nk, cbo, cum, M, mB, mtag, moff, msc, mw, r64, r32, zt, lane);
+    } else {
+      for (int i = 0; i < nk; ++i) {
+        const int B = rl(mB, i);
+        const int prec = rl(mtag, i);
+        const uint8_t *blk = a.map.base + rl64(moff, i);
+        const double sc = bcast(msc, i);
+        const int cb = cbo[i];
+        bblock(B, prec, blk, sc, r64 + cb * kBCols, zt + cb * kBCols, lane);
+      }
     }
     bwave_lds_sync();
     // 3. per-column dots over the real rows of the tile: lane l sums column
@@ -511,14 +639,15 @@ __device__ __forceinline__ void bapply_blocks(const BApplyArgs &a, int k0, int k
   }
 }
 
-__device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M, double *r64,
+template <int BP>
+__device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M, double *r64, float *r32,
                                              double *zt) {
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ach_sys[ch]);
   const int c0 = a.t.sys_col[s];
   double rr = 0.0, rz = 0.0;
-  bapply_blocks<true>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], a.t.sys_xvec[s], M,
-                      a.alpha + c0, r64, zt, rr, rz);
+  bapply_blocks<true, BP>(a, a.t.ach_blk[ch], a.t.ach_blk[ch + 1], a.t.sys_row[s], a.t.sys_vec[s], a.t.sys_xvec[s], M,
+                      a.alpha + c0, r64, r32, zt, rr, rz);
   // column l mod 8 lives in lanes l, l + 8, ..., l + 56
 #pragma unroll
   for (int o = 8; o < 64; o <<= 1) {
@@ -531,29 +660,36 @@ __device__ __forceinline__ void bapply_chunk(const BApplyArgs &a, int ch, int M,
   }
 }
 
+template <int BP>
 __global__ __launch_bounds__(256) void bapply_kernel(BApplyArgs a) {
+  constexpr bool BAND = BP != kFullBlocks;
   __shared__ double r64s[4][kBWaveRows * kBCols];
   __shared__ double zts[4][kBWaveRows * kBCols];
+  __shared__ __align__(16) float r32s[BAND ? 4 : 1][BAND ? kBWaveRows * kBCols : 4];
   if (*a.n_active == 0) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int w = wave_slot(wv);
   const int ce = a.sched[w + 1];
   for (int ch = a.sched[w]; ch < ce; ++ch) {
     const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ach_sys[ch]]);
-    bapply_chunk(a, ch, m, r64s[wv], zts[wv]);
+    bapply_chunk<BP>(a, ch, m, r64s[wv], BAND ? r32s[BAND ? wv : 0] : nullptr, zts[wv]);
   }
 }
 
 // Z = M^-1 R for one n x m block of columns (no PCG): one wave per wave tile
 // of the handle's partition, grid-stride.
+template <int BP>
 __global__ __launch_bounds__(256) void bapply_multi_kernel(BApplyArgs a, const int32_t *tile_blk, int ntiles,
                                                            int m) {
+  constexpr bool BAND = BP != kFullBlocks;
   __shared__ double r64s[4][kBWaveRows * kBCols];
   __shared__ double zts[4][kBWaveRows * kBCols];
+  __shared__ __align__(16) float r32s[BAND ? 4 : 1][BAND ? kBWaveRows * kBCols : 4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double rr = 0.0, rz = 0.0;
   for (int t = blockIdx.x * 4 + wv; t < ntiles; t += gridDim.x * 4)
-    bapply_blocks<false>(a, tile_blk[t], tile_blk[t + 1], 0, 0, 0, m, nullptr, r64s[wv], zts[wv], rr, rz);
+    bapply_blocks<false, BP>(a, tile_blk[t], tile_blk[t + 1], 0, 0, 0, m, nullptr, r64s[wv],
+                               BAND ? r32s[BAND ? wv : 0] : nullptr, zts[wv], rr, rz);
 }
 
 // ------------------------------------------------------- per-system scalars
@@ -694,7 +830,7 @@ struct BPlan {
 static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const int32_t *sys_row,
                       const int32_t *sys_m, int chunk_rows, int apply_rows, BPlan &pl) {
   if (!M || S < 1 || !sys_row || !sys_m || sys_row[0] != 0 || sys_row[S] != M->n) return BJAC_EINVAL;
-  if (M->kind != 0 || M->storage != BJAC_STORE_FULL) return BJAC_EINVAL;  // full stored blocks only
+  if (M->kind != 0) return BJAC_EINVAL;  // stored block inverses only
   if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
   if (apply_rows < kBWaveRows || apply_rows > (1 << 20)) return BJAC_EINVAL;
   pl.S = S;
@@ -754,7 +890,8 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
     }
     rows += B;
     const int pb = tg.empty() ? 8 : (tg[k] == 0 ? 8 : (tg[k] == 1 ? 4 : 2));
-    pl.ach_cost.back() += (double)B * B * pb + (br[k + 1] - br[k]) * 56.0 * sys_m[s];
+    const double stored = M->storage == BJAC_STORE_BAND ? (double)B * (M->h_w_lo[k] + 1) : (double)B * B;
+    pl.ach_cost.back() += stored * pb + (br[k + 1] - br[k]) * 56.0 * sys_m[s];
   }
   while ((int)pl.sys_ach.size() < S + 1) pl.sys_ach.push_back((int32_t)pl.ach_sys.size());
   pl.ach_blk.push_back(M->nb);
@@ -926,7 +1063,7 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
   c.sched1 = c.w.tabs + o_s1;
   c.sched2 = c.w.tabs + o_s2;
   c.st = BState{c.w.rho, c.w.alpha, c.w.beta, c.w.rnorm0, c.w.relres, c.w.iter, c.w.status, c.w.n_active, tol, maxit};
-  c.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo};
+  c.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo, M->w_lo};
   c.A = A;
   c.M = M;
   c.b = b;
@@ -978,7 +1115,17 @@ static void benq_apply_k(const BCtx &c, const double *p, hipStream_t s) {
   a.part = c.w.part2;
   a.n_active = c.w.n_active;
   a.sched = c.sched2;
-  hipLaunchKernelGGL(bapply_kernel, dim3(c.G2), dim3(256), 0, s, a);
+  if (!a.map.w) {
+    hipLaunchKernelGGL(bapply_kernel<kFullBlocks>, dim3(c.G2), dim3(256), 0, s, a);
+    return;
+  }
+  switch (c.M->uprec_lo) {
+    case P64: hipLaunchKernelGGL(bapply_kernel<P64>, dim3(c.G2), dim3(256), 0, s, a); break;
+    case P32: hipLaunchKernelGGL(bapply_kernel<P32>, dim3(c.G2), dim3(256), 0, s, a); break;
+    case PBF16: hipLaunchKernelGGL(bapply_kernel<PBF16>, dim3(c.G2), dim3(256), 0, s, a); break;
+    case P16: hipLaunchKernelGGL(bapply_kernel<P16>, dim3(c.G2), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(bapply_kernel<-1>, dim3(c.G2), dim3(256), 0, s, a); break;
+  }
 }
 
 static void benq_apply_r(const BCtx &c, int init, hipStream_t s) {
@@ -1236,16 +1383,29 @@ extern "C" int pcg_batched_tune(const bjac_csr *A, const bjac_handle *M, int32_t
 
 extern "C" int bjac_apply_multi(const bjac_handle *M, const double *R, double *Z, int32_t m, void *stream) {
   if (!M || !R || !Z || R == Z || m < 1 || m > kBCols) return BJAC_EINVAL;
-  if (M->kind != 0 || M->storage != BJAC_STORE_FULL) return BJAC_EINVAL;
+  if (M->kind != 0) return BJAC_EINVAL;
   BApplyArgs a{};
   a.blk_row = M->blk_row;
   a.bpad = M->bpad;
-  a.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo};
+  a.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo, M->w_lo};
   a.r = const_cast<double *>(R);  // read only in this mode
   a.z = Z;
   const int G = std::max(1, std::min((M->ntiles + 3) / 4, 4 * cu_count()));
-  hipLaunchKernelGGL(bapply_multi_kernel, dim3(G), dim3(256), 0, (hipStream_t)stream, a,
-                     (const int32_t *)M->tile_blk, M->ntiles, (int)m);
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t *tb = (const int32_t *)M->tile_blk;
+  if (!a.map.w) {
+    hipLaunchKernelGGL(bapply_multi_kernel<kFullBlocks>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m);
+  } else {
+    switch (M->uprec_lo) {
+      case P64: hipLaunchKernelGGL(bapply_multi_kernel<P64>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m); break;
+      case P32: hipLaunchKernelGGL(bapply_multi_kernel<P32>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m); break;
+      case PBF16:
+        hipLaunchKernelGGL(bapply_multi_kernel<PBF16>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m);
+        break;
+      case P16: hipLaunchKernelGGL(bapply_multi_kernel<P16>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m); break;
+      default: hipLaunchKernelGGL(bapply_multi_kernel<-1>, dim3(G), dim3(256), 0, st, a, tb, M->ntiles, (int)m); break;
+    }
+  }
   MPB_HIP(hipGetLastError());
   return BJAC_OK;
 }

@@ -213,12 +213,10 @@ def test_band_errors():
         M.band_widths(1)                       # no FP64 map without the temporal switch
     with pytest.raises(mb.MpbjacError):
         mb.BlockJacobi(Ad, bp, mb.Policy()).band_widths()
-    # the batched path and the multi-column application take full blocks only
+    # paper-mode handles have no stored blocks: the multi-column entry points refuse them
+    P = mb.PaperBJAC(Ad, bp, k=1, t=1)
     with pytest.raises(mb.MpbjacError):
-        M.apply_multi(tensor(np.zeros((A.n, 2))))
-    bs = mb.BatchSolver(Ad, M, np.array([0, A.n], np.int32), np.array([1], np.int32))
-    with pytest.raises(mb.MpbjacError):
-        bs.solve(tensor(np.ones(A.n)))
+        P.apply_multi(tensor(np.zeros((A.n, 2))))
 
 
 def test_band_full_width_equals_full_storage():
@@ -281,3 +279,61 @@ def test_band_full_size_sampled_parity():
     print(f"128^3 FP16: band {res.iters} iterations, full {res_f.iters}")
     assert res.status == mb.OK and abs(res.iters - res_f.iters) <= 2
     assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10
+
+
+def _band_store(H, tags, wg):
+    return [(OPr.round_to_format(OB.band_part(Hk, int(w)) / OPr.block_scale(float(np.max(np.abs(Hk))), int(t)), int(t)),
+             OPr.block_scale(float(np.max(np.abs(Hk))), int(t)), int(t), int(w)) for Hk, t, w in zip(H, tags, wg)]
+
+
+@pytest.mark.parametrize("sizes,m", [((16, 32, 48, 64), 5), ((7, 33, 64, 16), 8), ((32,), 1)])
+def test_band_apply_multi_matches_oracle(sizes, m):
+    # several columns at once (the batched application's element-by-element
+    # band products): every column within the single-column bound
+    A, bp, rng = _case(seed=16, shape=(11, 9, 13), sizes=sizes)
+    nb = len(bp) - 1
+    tags = rng.choice([OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16], size=nb).astype(np.uint8)
+    M = mb.BlockJacobi(mb.DeviceCSR(A, dev()), bp, _band_policy(mode=mb.EXPLICIT, explicit_tags=tags))
+    H = OB.invert_blocks(A, bp)
+    store = _band_store(H, tags, M.band_widths())
+    R = rng.uniform(-1, 1, (A.n, m)) * np.exp(rng.uniform(-20, 0, (A.n, m)))
+    Z = M.apply_multi(tensor(R)).cpu().numpy()
+    for c in range(m):
+        ref = OB.apply(store, bp, R[:, c])
+        assert np.all(np.abs(Z[:, c] - ref) <= _apply_bound(store, bp, R[:, c], tags, H) + 1e-300), c
+
+
+def _sub_csr(A, r0, r1):
+    a, b = int(A.row_ptr[r0]), int(A.row_ptr[r1])
+    return gen.CSR(r1 - r0, (A.row_ptr[r0:r1 + 1] - a).astype(np.int32), (A.col_idx[a:b] - r0).astype(np.int32),
+                   A.val[a:b].copy())
+
+
+@pytest.mark.parametrize("prec", [OPr.FP16, OPr.FP64])
+def test_band_batched_pcg_matches_oracle(prec):
+    # batched systems with 1-8 right-hand sides and band storage: every column
+    # against the oracle's band PCG on its system
+    st = gen.stack_batch(gen.config4(3, nsys=5, edge=(5, 14), nrhs=(1, 8)))
+    Ad = mb.DeviceCSR(st.A, dev())
+    pol = _band_policy(mode=mb.FIXED, low=prec) if prec != OPr.FP64 else _band_policy(mode=mb.UNIFORM)
+    M = mb.BlockJacobi(Ad, st.block_ptr, pol)
+    bs = mb.BatchSolver(Ad, M, st.sys_row, st.sys_m)
+    res = bs.solve(tensor(st.b), tol=1e-10, maxit=3000)
+    assert res.status == mb.OK
+    x = res.x.cpu().numpy()
+    col = 0
+    for s in range(len(st.sys_m)):
+        r0, r1 = int(st.sys_row[s]), int(st.sys_row[s + 1])
+        m = int(st.sys_m[s])
+        k0, k1 = int(np.searchsorted(st.block_ptr, r0)), int(np.searchsorted(st.block_ptr, r1))
+        bp = (st.block_ptr[k0:k1 + 1] - r0).astype(np.int32)
+        sub = _sub_csr(st.A, r0, r1)
+        Mo = OP.BJAC(sub, bp, np.full(k1 - k0, prec, np.uint8), band=True)
+        Bs = st.b[st.system_slice(s)].reshape(r1 - r0, m)
+        xs = x[st.system_slice(s)].reshape(r1 - r0, m)
+        for c in range(m):
+            ref = OP.solve_bjac(sub, bp, Bs[:, c], tol=1e-10, maxit=3000, M=Mo)
+            assert ref.status == OP.CONVERGED and res.col_status[col] == mb.OK
+            assert abs(int(res.col_iters[col]) - ref.iters) <= max(3, int(0.05 * ref.iters)), (s, c)
+            assert OP.true_relres(sub, xs[:, c], Bs[:, c]) <= 2e-10
+            col += 1
