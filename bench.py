@@ -16,7 +16,8 @@ on a bounded sample on the host.
 Other workloads (each prints its own line of the same form):
   --workload batched   256 independent 7-point systems, edges U{32..96},
                        1-8 right-hand sides each, blocks from {16,32,48,64};
-                       FP16 block storage vs FP64, autotuned launch shape
+                       FP16 block storage vs FP64 (and FP16 band storage),
+                       autotuned launch shape
   --workload aniso     160^3 anisotropic (1e3) diffusion with 1e4 jumps on
                        16 random subcubes, blocks of 48: per-block rule vs
                        FP16 and FP64 storage
@@ -368,6 +369,10 @@ def bench_batched(args):
     log(f"timing {args.steps} steps, FP64 block storage")
     ms64, setup64, solve64, (M64, r64, _) = timed(pol64, args.steps)
     log(f"fp64: {ms64:.1f} ms/step (max {r64.iters} iterations)")
+    polb = mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_BAND)
+    log(f"timing {args.steps} steps, FP16 band storage")
+    msb, setupb, solveb, (Mb, rb, _) = timed(polb, args.steps)
+    log(f"fp16 band: {msb:.1f} ms/step (max {rb.iters} iterations)")
 
     # FP64 check of the returned solutions on a sample of systems
     x16 = r16.x.cpu().numpy()
@@ -419,6 +424,9 @@ def bench_batched(args):
         "status": r16.status, "status_fp64": r64.status,
         "setup_ms": setup16, "solve_ms": solve16, "fp64_ms_per_step": ms64, "fp64_setup_ms": setup64,
         "fp64_solve_ms": solve64, "speedup_vs_fp64": ms64 / ms16, "true_relres_sampled_max": worst,
+        "fp16_band_ms_per_step": msb, "fp16_band_setup_ms": setupb, "fp16_band_solve_ms": solveb,
+        "fp16_band_iters_max": rb.iters, "fp16_band_status": rb.status,
+        "fp16_band_stored_bytes": Mb.info()["low_bytes"], "fp16_stored_bytes": M16.info()["low_bytes"],
         "bytes_per_iter": iter_bytes, "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
         "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
         "autotune_ms_per_iter": entry["ms_per_iter"],

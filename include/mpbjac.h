@@ -84,8 +84,10 @@ typedef enum {
  * band is symmetric, taken from H's upper triangle, with the same scale and
  * rounding as FULL. The inverse of a diagonally dominant banded block decays
  * away from its diagonal, so w_k is usually far below b_k: the application
- * reads (w_k + 1) / bpad_k of FULL's bytes. Band handles serve bjac_apply and
- * pcg_solve; the batched entry points and bjac_apply_multi reject them. */
+ * reads (w_k + 1) / bpad_k of FULL's bytes. Band handles serve every entry
+ * point that takes a handle (bjac_apply, bjac_apply_multi, pcg_solve,
+ * pcg_solve_batched); the multi-column products then run on the vector units
+ * instead of the matrix cores. */
 typedef enum {
   BJAC_STORE_FULL = 0,
   BJAC_STORE_BAND = 1
