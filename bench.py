@@ -105,8 +105,8 @@ VERIFY = 3
 # profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
 # for the kernel sources they were measured on: reported when the digest of
 # those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "b58aceaf4fc77b32b24881816b2dd82353bc1ea22e1f39ee859e309d8a8d8af8",
-           "spmv": 266836594, "apply": 252364943}
+TRAFFIC = {"sources_sha256": "1b9d0ed161611cf7a75197ef4ae4a627866e907278767d8bf88a827892cb361e",
+           "spmv": 267551310, "apply": 252362895}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
