@@ -55,10 +55,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def spmv_bytes(n, nnz):
+def index_bytes(A):
+    """Bytes per column index the PCG SpMV reads: 2 when every entry lies within
+    32767 rows of its row (the solver's 16-bit row-relative copy), else 4."""
+    import numpy as np
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr.astype(np.int64)))
+    far = np.max(np.abs(A.col_idx.astype(np.int64) - rows)) if A.nnz else 0
+    return 2 if far <= 32767 else 4
+
+
+def spmv_bytes(n, nnz, ib=4):
     """Algorithmic bytes of one SpMV launch with the folded p update: CSR values
-    and column indices, row pointers, z and p_old read once, p_new and q written."""
-    return 12 * nnz + 4 * (n + 1) + 32 * n
+    and column indices (ib bytes each), row pointers, z and p_old read once,
+    p_new and q written."""
+    return (8 + ib) * nnz + 4 * (n + 1) + 32 * n
 
 
 def apply_bytes(n, nb, ntiles, stored_bytes, band=False):
@@ -211,7 +221,7 @@ def bench_diff3d(args):
     _, rp16, _ = step(pol16, profile=True)
     info16 = M16.info()
     ntiles = info16["ntiles"]
-    kb = {"spmv": spmv_bytes(n, nnz), "apply": apply_bytes(n, nb, ntiles, info16["low_bytes"])}
+    kb = {"spmv": spmv_bytes(n, nnz, index_bytes(p.A)), "apply": apply_bytes(n, nb, ntiles, info16["low_bytes"])}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp16.kernel_ms[name]
@@ -509,7 +519,7 @@ def bench_policies(args):
     log("profile pass")
     M, rp, _ = step(pols[head], profile=True)
     info = M.info()
-    kb = {"spmv": spmv_bytes(n, nnz), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
+    kb = {"spmv": spmv_bytes(n, nnz, index_bytes(p.A)), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp.kernel_ms[name]
@@ -572,6 +582,7 @@ def bench_band(args):
 
     S = p.A.to_scipy()
     bn = float(np.linalg.norm(p.b))
+    ib = index_bytes(p.A)
     rows, kern_all = {}, {}
     for name, pol in pols.items():
         for _ in range(args.warmup):
@@ -594,7 +605,7 @@ def bench_band(args):
                       "max_width": int(w.max()) if is_band else None}
         # per-kernel event timing of the same solve
         _, rp, _ = step(pol, profile=True)
-        kb = {"spmv": spmv_bytes(n, nnz),
+        kb = {"spmv": spmv_bytes(n, nnz, ib),
               "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"], band=is_band)}
         kern = {}
         for kname in ("spmv", "apply"):
@@ -720,7 +731,7 @@ def bench_paper(args):
             for pname, low in (("fMP", True), ("uniform", False)):
                 M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low)
                 rp = S.solve(Ad, M, b, tol=1e-10, maxit=2000, profile=True)
-                kb = {"spmv": spmv_bytes(A.n, A.nnz), "apply": poly_apply_bytes(A.n, A.nnz, 2, 2, 4 if low else 8),
+                kb = {"spmv": spmv_bytes(A.n, A.nnz, index_bytes(A)), "apply": poly_apply_bytes(A.n, A.nnz, 2, 2, 4 if low else 8),
                       "update": 48 * A.n}
                 for kname in ("spmv", "apply", "update"):
                     tot, cnt = rp.kernel_ms[kname]

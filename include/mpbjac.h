@@ -258,12 +258,19 @@ int bjac_round(const double *in, void *out, int64_t count, int32_t prec, double 
 
 /* ---- PCG (Sec. 3.2; Sec. 4.2 stopping test, x0 = 0) ---------------------
  * pcg_workspace_query: bytes of the solver workspace for n rows.
+ * pcg_workspace_query_csr: the same plus room for a 16-bit copy of A's
+ * column structure (2 bytes per non-zero). Given a workspace that large,
+ * pcg_solve writes col - row of every entry into it at the start of the call
+ * and its matrix-vector products read those 2 bytes instead of the 4-byte
+ * column index (when some entry lies more than 32767 rows from its row they
+ * keep the 4-byte indices); the iterates are the same either way.
  * pcg_solve: solves A x = b; b, x device FP64 [n] (x is overwritten). The
  * iterations run as captured HIP graphs of opts->chunk iterations with all
  * scalars on the device; the host reads one status word per graph launch.
  * Returns BJAC_OK, BJAC_NOT_CONVERGED, BJAC_EBREAKDOWN or an error; stats may
  * be NULL. The call synchronises the stream before it returns. */
 int pcg_workspace_query(int64_t n, size_t *workspace_bytes);
+int pcg_workspace_query_csr(const bjac_csr *A, size_t *workspace_bytes);
 int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *x,
               const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes,
               bjac_stats *stats, void *stream);

@@ -30,7 +30,7 @@ NFEAT = 16
 SYMBOLS = (
     "bjac_abi_version", "bjac_strerror", "bjac_setup_query", "bjac_setup", "bjac_destroy",
     "bjac_get_info", "bjac_get_tags", "bjac_get_features", "bjac_get_block", "bjac_get_band", "bjac_apply",
-    "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_solve", "bjac_mlp_forward",
+    "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_workspace_query_csr", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
     "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
     "bjac_poly_setup_query", "bjac_poly_setup",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "bjac_spmv": (C.c_int, [P(bjac_csr), vp, vp, vp]),
         "bjac_round": (C.c_int, [vp, vp, i64, i32, dbl, vp]),
         "pcg_workspace_query": (C.c_int, [i64, P(sz)]),
+        "pcg_workspace_query_csr": (C.c_int, [P(bjac_csr), P(sz)]),
         "pcg_solve": (C.c_int, [P(bjac_csr), vp, vp, vp, P(bjac_solve_opts), vp, sz, P(bjac_stats), vp]),
         "bjac_mlp_forward": (C.c_int, [vp, vp, i32, vp, vp, vp]),
         "bjac_mlp_workspace_query": (C.c_int, [i32, P(sz)]),
@@ -317,18 +318,26 @@ class SolveResult:
 
 
 class Solver:
-    """Reusable PCG workspace for one matrix size."""
+    """Reusable PCG workspace for one matrix size. ``compact_index`` (default)
+    grows it to hold the 16-bit copy of the matrix's column structure that the
+    SpMV reads (pcg_workspace_query_csr)."""
 
-    def __init__(self, n: int, device="cuda"):
+    def __init__(self, n: int, device="cuda", compact_index=True):
         torch = _torch()
         nbytes = C.c_size_t()
         _check(load().pcg_workspace_query(n, C.byref(nbytes)), "pcg_workspace_query")
         self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=device)
         self.n = n
+        self.compact_index = compact_index
 
     def solve(self, A: DeviceCSR, M: BlockJacobi, b, tol=1e-10, maxit=5000, chunk=16, history=False, x=None,
               raise_on_error=True, profile=False, verify=0) -> SolveResult:
         torch = _torch()
+        if self.compact_index:
+            nbytes = C.c_size_t()
+            _check(load().pcg_workspace_query_csr(C.byref(A.c), C.byref(nbytes)), "pcg_workspace_query_csr")
+            if self.ws.numel() < nbytes.value:
+                self.ws = torch.empty(nbytes.value, dtype=torch.uint8, device=self.ws.device)
         x = torch.empty_like(b) if x is None else x
         rh = torch.empty(maxit, dtype=torch.float64, device=b.device) if history else None
         hh = torch.zeros(maxit + 1, dtype=torch.uint8, device=b.device) if history else None

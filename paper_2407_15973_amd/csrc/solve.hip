@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <type_traits>
 #include <cstring>
 #include <unordered_map>
@@ -170,6 +171,25 @@ __device__ __forceinline__ double sum_partials(double *p, int n, int stride, dou
   return out[0];
 }
 
+static_assert(offsetof(PcgState, rel16) == offsetof(PcgState, status) + 4 && offsetof(PcgState, status) % 8 == 0,
+              "status and rel16 are read as one 8-byte word");
+
+// The 16-bit row-relative copy of A's column indices (col - row) used by the
+// PCG SpMV; any entry farther than 32767 rows from its row clears st->rel16,
+// and the products keep the 32-bit indices.
+__global__ __launch_bounds__(256) void off16_kernel(int n, const int32_t *rp, const int32_t *ci, int16_t *o,
+                                                    PcgState *st) {
+  bool ok = true;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int d = ci[k] - i;
+      ok = ok && d >= -32768 && d <= 32767;
+      o[k] = (int16_t)d;
+    }
+  }
+  if (!ok) __hip_atomic_store(&st->rel16, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) ((uint64_t *)p)[i] = kEmpty;
 }
@@ -186,6 +206,7 @@ struct SpmvArgs {
   double *pnew, *q;
   PcgState *st;
   double *part;
+  const int16_t *o16;   // PCG: col - row of every entry, valid while st->rel16
 };
 
 // Dot product of one CSR row with p_new = z + beta p_old (the p update of PCG
@@ -197,7 +218,7 @@ struct SpmvArgs {
 template <bool PCG, bool STAGED>
 __device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
                                           const int *__restrict__ cidx, const double *__restrict__ vals, double beta,
-                                          int base, int len, int row, double &prow, bool &found) {
+                                          int base, int len, int row, double &prow, bool &found, int roff) {
   constexpr int U = 8;
   double acc = 0.0;
   for (int k0 = 0; k0 < len; k0 += U) {
@@ -206,7 +227,7 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int idx = base + min(k0 + k, len - 1);
-      cs[k] = cidx[idx];
+      cs[k] = cidx[idx] + roff;   // roff = row when the indices are row-relative
       const double v = vals[idx];
       vs[k] = (k0 + k < len) ? v : 0.0;
     }
@@ -224,25 +245,20 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
   return acc;
 }
 
-template <bool PCG>
-__global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
+// The tiles of one wave; returns the wave's partial (p_new, q). REL: the
+// staged column indices are the 16-bit row-relative copy (one loop per
+// choice, decided once per launch).
+template <bool PCG, bool REL>
+__device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc) {
   constexpr int CAP = kSpmvNnzCap;
   constexpr int NL = CAP / 64;
-  __shared__ double svs[4][CAP];
-  __shared__ int scs[4][CAP];
-  __shared__ double sh[4];
-  __shared__ int flag, ok;
   const int32_t *__restrict__ rp = a.rp;
   const int32_t *__restrict__ ci = a.ci;
+  const int16_t *__restrict__ o16 = a.o16;
   const double *__restrict__ vv_g = a.v;
   const double *__restrict__ z = a.z;
   const double *__restrict__ pold = a.pold;
-  if (PCG && a.st->status != ST_RUNNING) return;
-  const double beta = PCG ? a.st->beta : 0.0;
   const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double *sv = svs[wv];
-  int *sc = scs[wv];
   double dot = 0.0;
   bool s_has = false;   // q and p_new of the previous tile, stored after this tile's loads
   int s_row = 0;
@@ -276,14 +292,17 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
       // matrix is read once per product: non-temporal loads keep it from
       // displacing the vectors, which the next kernel then finds in the
       // last-level cache (measured: SpMV unchanged, fused apply 51 -> 46 us at
-      // 128^3; the same hint on the stored inverses made the apply slower)
+      // 128^3; the same hint on the stored inverses made the apply slower).
+      // With the 16-bit row-relative copy of the indices the staged values
+      // are col - row, 2 bytes per entry instead of 4.
       double vv[NL];
       int cc[NL];
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
         const int i = min(lane + 64 * k, cnt - 1);
         vv[k] = __builtin_nontemporal_load(vv_g + e0 + i);
-        cc[k] = __builtin_nontemporal_load(ci + e0 + i);
+        if constexpr (REL) cc[k] = (int)__builtin_nontemporal_load(o16 + e0 + i);
+        else cc[k] = __builtin_nontemporal_load(ci + e0 + i);
       }
       if (s_has) {
         a.q[s_row] = s_q;
@@ -299,10 +318,10 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
         }
       }
       wave_lds_sync();
-      acc = row_dot<PCG, true>(z, pold, sc, sv, beta, s - e0, len, row, prow, found);
+      acc = row_dot<PCG, true>(z, pold, sc, sv, beta, s - e0, len, row, prow, found, REL ? row : 0);
       wave_lds_sync();
     } else {
-      acc = row_dot<PCG, false>(z, pold, ci, vv_g, beta, s, len, row, prow, found);
+      acc = row_dot<PCG, false>(z, pold, ci, vv_g, beta, s, len, row, prow, found, 0);
     }
     if (s_has) {
       a.q[s_row] = s_q;
@@ -320,6 +339,29 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   if (s_has) {
     a.q[s_row] = s_q;
     if (PCG) a.pnew[s_row] = s_p;
+  }
+  return dot;
+}
+
+template <bool PCG>
+__global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
+  constexpr int CAP = kSpmvNnzCap;
+  __shared__ double svs[4][CAP];
+  __shared__ int scs[4][CAP];
+  __shared__ double sh[4];
+  __shared__ int flag, ok;
+  // status and rel16 are adjacent: one load before the early exit
+  int2 sr = make_int2(ST_RUNNING, 0);
+  if (PCG) sr = *(const int2 *)&a.st->status;
+  if (PCG && sr.x != ST_RUNNING) return;
+  const double beta = PCG ? a.st->beta : 0.0;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double dot;
+  if constexpr (PCG) {
+    if (a.o16 && sr.y) dot = spmv_tiles<true, true>(a, beta, svs[wv], scs[wv]);
+    else dot = spmv_tiles<true, false>(a, beta, svs[wv], scs[wv]);
+  } else {
+    dot = spmv_tiles<false, false>(a, beta, svs[wv], scs[wv]);
   }
   if (!PCG) return;
   const double bs = block_sum(dot, sh);
@@ -1059,6 +1101,7 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
 __global__ void state_init_kernel(PcgState *st, double tol, int maxit, double adp_tol, int temporal,
                                   double *relres_hist, uint8_t *high_hist) {
   PcgState s{};
+  s.rel16 = 1;
   s.tol = tol;
   s.maxit = maxit;
   s.adp_tol = adp_tol;
@@ -1380,8 +1423,9 @@ static void enqueue_poly_map(const bjac_handle *M, int high, PcgState *st, const
 
 // ---------------------------------------------------------------- launchers
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
-                        PcgState *st, double *part, int mode, hipStream_t s) {
+                        PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr) {
   SpmvArgs a{};
+  a.o16 = o16;
   a.n = (int32_t)A->n;
   a.ntiles = (int)((A->n + kSpmvRows - 1) / kSpmvRows);
   a.rp = A->row_ptr;
@@ -1521,10 +1565,11 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
 struct SolveWs {
   double *r, *z, *pa, *pb, *q, *part1, *part2, *part3;
   PcgState *st;
+  int16_t *o16;   // [nnz] row-relative column indices, or null
   size_t bytes;
 };
 
-static SolveWs carve_solve(void *ws, int64_t n) {
+static SolveWs carve_solve(void *ws, int64_t n, int64_t nnz16 = 0) {
   Carver c(ws);
   SolveWs w{};
   w.r = c.take<double>(n);
@@ -1536,6 +1581,7 @@ static SolveWs carve_solve(void *ws, int64_t n) {
   w.part2 = w.part1 + kMaxGrid;
   w.part3 = c.take<double>(kMaxGrid);      // true-residual partials
   w.st = c.take<PcgState>(1);
+  w.o16 = nnz16 > 0 ? c.take<int16_t>(nnz16) : nullptr;
   w.bytes = c.used;
   return w;
 }
@@ -1596,7 +1642,7 @@ static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs 
 static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
                               const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
-  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s);
+  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16);
   enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr);
 }
 
@@ -1688,6 +1734,12 @@ extern "C" int pcg_workspace_query(int64_t n, size_t *workspace_bytes) {
   return BJAC_OK;
 }
 
+extern "C" int pcg_workspace_query_csr(const bjac_csr *A, size_t *workspace_bytes) {
+  if (!A || A->n < 1 || A->nnz < 0 || !workspace_bytes) return BJAC_EINVAL;
+  *workspace_bytes = carve_solve(nullptr, A->n, A->nnz).bytes;
+  return BJAC_OK;
+}
+
 extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double *b, double *x,
                          const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes, bjac_stats *stats,
                          void *stream) {
@@ -1695,7 +1747,9 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   if (A->n != Mc->n || !A->row_ptr || !A->col_idx || !A->val) return BJAC_EINVAL;
   if (!(opts->tol >= 0.0) || opts->maxit < 1) return BJAC_EINVAL;
   bjac_handle *M = const_cast<bjac_handle *>(Mc);
-  const SolveWs w = carve_solve(workspace, A->n);
+  // with room for the 16-bit index copy the products use it, else the CSR's own
+  SolveWs w = carve_solve(workspace, A->n, A->nnz);
+  if (w.bytes > workspace_bytes || A->nnz < 1) w = carve_solve(workspace, A->n);
   if (w.bytes > workspace_bytes) return BJAC_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
@@ -1708,6 +1762,9 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   MPB_HIP(hipEventRecord(e0, s));
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
                      M->policy.temporal, opts->relres_hist, opts->high_hist);
+  if (w.o16)
+    hipLaunchKernelGGL(off16_kernel, dim3(poly_grid(A->n)), dim3(256), 0, s, (int)A->n, A->row_ptr, A->col_idx, w.o16,
+                       w.st);
   hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q);
   hipLaunchKernelGGL(fill_empty_kernel, dim3(24), dim3(256), 0, s, w.part1, 3 * kMaxGrid);
   // first application z_0 = M^-1 r_0 (alpha = 0 leaves x = 0, r = b)
@@ -1716,7 +1773,8 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
 
   // captured chunk of iterations, cached in the handle per argument set
   std::vector<uintptr_t> key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val,
-                                (uintptr_t)A->n, (uintptr_t)x, (uintptr_t)workspace, (uintptr_t)chunk};
+                                (uintptr_t)A->n, (uintptr_t)x, (uintptr_t)workspace, (uintptr_t)chunk,
+                                (uintptr_t)w.o16};
   if (!opts->profile && (!M->gexec || M->gkey != key)) {
     if (M->gexec) {
       (void)hipGraphExecDestroy(M->gexec);

@@ -281,3 +281,37 @@ def test_one_row_system():
     res, _ = _gpu_solve(A, np.array([0, 1], np.int32), np.array([2.0]), mb.Policy(mode=mb.FIXED, low=mb.FP16), 1e-12, 5)
     assert res.status == mb.OK and res.iters == 1
     assert abs(res.x.cpu().numpy()[0] - 0.5) <= 1e-15
+
+
+def _solve_pair(A, bp, b, maxit, pol=None):
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, pol or mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    out = []
+    for compact in (True, False):
+        S = mb.Solver(A.n, dev(), compact_index=compact)
+        out.append(S.solve(Ad, M, tensor(b), tol=1e-10, maxit=maxit, history=True, raise_on_error=False))
+    return out
+
+
+def test_compact_column_index_gives_identical_iterates():
+    # the 16-bit row-relative copy of the column indices changes only the bytes
+    # the SpMV reads: the same products in the same order, identical iterates
+    rng = np.random.default_rng(23)
+    A = gen.diffusion3d(gen.kappa_loguniform((14, 12, 10), rng))
+    b = rng.uniform(-1, 1, A.n)
+    r1, r2 = _solve_pair(A, gen.uniform_blocks(A.n, 32), b, 2000)
+    assert r1.status == mb.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.relres_hist, r2.relres_hist)
+    assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
+
+
+def test_compact_column_index_falls_back_for_far_couplings():
+    # a 33000 x 2 grid couples rows 33000 apart, beyond 16 bits: the products
+    # keep the 32-bit indices, still identical to the plain workspace
+    A = gen.poisson2d(33000, 2)
+    rng = np.random.default_rng(24)
+    b = rng.uniform(-1, 1, A.n)
+    r1, r2 = _solve_pair(A, gen.uniform_blocks(A.n, 32), b, 200)
+    assert r1.status == mb.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.relres_hist, r2.relres_hist)
+    assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
