@@ -74,6 +74,8 @@ struct BSpmvArgs {
   double *part;          // [nch][8]
   const int32_t *n_active;
   const int32_t *sched;   // [9] chunk run of each XCD
+  const int16_t *o16;     // col - row of every entry (16-bit copy), read while *rel16
+  const int32_t *rel16;
 };
 
 // floor(e / m) for 0 <= e < 4096 and 1 <= m <= 8 (multiply by ceil(2^16/m);
@@ -119,7 +121,8 @@ struct VecT<2> {
 
 // H: elements per lane in flight; VW: consecutive columns per element (2
 // needs an even M: one 16-byte access per vector and neighbour).
-template <int H, int VW>
+// REL: the staged column indices are the 16-bit row-relative copy.
+template <int H, int VW, bool REL>
 __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, SpmvLds &L) {
   constexpr int CAP = kSpmvNnzCap;
   constexpr int NL = CAP / 64;
@@ -151,7 +154,8 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
       for (int k = 0; k < NL; ++k) {
         const int i = min(lane + 64 * k, cnt - 1);
         vv[k] = __builtin_nontemporal_load(a.v + e0 + i);     // read once per product:
-        cc[k] = __builtin_nontemporal_load(a.ci + e0 + i);    // do not displace the vectors
+        if constexpr (REL) cc[k] = (int)__builtin_nontemporal_load(a.o16 + e0 + i);   // do not
+        else cc[k] = __builtin_nontemporal_load(a.ci + e0 + i);                      // displace the vectors
       }
 #pragma unroll
       for (int k = 0; k < NL; ++k) {
@@ -198,7 +202,7 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
           for (int k = 0; k < U; ++k) {
             const int idx = min(sidx[h] + min(k0 + k, max(len[h] - 1, 0)), cnt - 1);
             const bool ok = k0 + k < len[h];
-            cs[h][k] = staged ? L.c[idx] : a.ci[e0 + idx];
+            cs[h][k] = staged ? L.c[idx] + (REL ? r0 + row[h] : 0) : a.ci[e0 + idx];
             const double vv = staged ? L.v[idx] : a.v[e0 + idx];
             vs[h][k] = ok ? vv : 0.0;
           }
@@ -273,6 +277,7 @@ template <int H>
 __global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
   __shared__ SpmvLds lds[4];
   if (*a.n_active == 0) return;
+  const bool rel = a.o16 && *a.rel16;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int x = blockIdx.x & 7;
   const int j = (blockIdx.x >> 3) * 4 + wv;
@@ -280,10 +285,13 @@ __global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
   const int ce = a.sched[x + 1];
   for (int ch = a.sched[x] + j; ch < ce; ch += Wx) {
     const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ch_sys[ch]]);
-    if (m & 1)
-      bspmv_chunk<H, 1>(a, ch, m, lds[wv]);
-    else
-      bspmv_chunk<H, 2>(a, ch, m, lds[wv]);
+    if (rel) {
+      if (m & 1) bspmv_chunk<H, 1, true>(a, ch, m, lds[wv]);
+      else bspmv_chunk<H, 2, true>(a, ch, m, lds[wv]);
+    } else {
+      if (m & 1) bspmv_chunk<H, 1, false>(a, ch, m, lds[wv]);
+      else bspmv_chunk<H, 2, false>(a, ch, m, lds[wv]);
+    }
   }
 }
 
@@ -820,6 +828,7 @@ constexpr int kBMaxWaves = kBMaxGrid * 4;
 
 struct BPlan {
   int32_t S = 0, ncols = 0;
+  int64_t nnz = 0;
   int64_t veclen = 0;
   std::vector<int32_t> sys_row, sys_m, sys_col, sys_ch, sys_ach, ch_row0, ch_sys, ach_blk, ach_sys;
   std::vector<int64_t> sys_vec, sys_xvec;
@@ -834,6 +843,7 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
   if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
   if (apply_rows < kBWaveRows || apply_rows > (1 << 20)) return BJAC_EINVAL;
   pl.S = S;
+  pl.nnz = A ? A->nnz : 0;
   pl.sys_row.assign(sys_row, sys_row + S + 1);
   pl.sys_m.assign(sys_m, sys_m + S);
   pl.sys_col.resize(S + 1);
@@ -951,6 +961,8 @@ struct BWs {
   int32_t *iter, *status, *n_active;
   int32_t *tabs;   // every int32 table, then both wave schedules
   int64_t *sys_vec, *sys_xvec;
+  int16_t *o16;    // [nnz] 16-bit row-relative column indices
+  int32_t *rel16;  // 1 while every entry fits 16 bits
   size_t bytes;
 };
 
@@ -980,6 +992,8 @@ static BWs carve_b(void *ws, const BPlan &p) {
   w.tabs = c.take<int32_t>(tabs_len(p));
   w.sys_vec = c.take<int64_t>(p.sys_vec.size());
   w.sys_xvec = c.take<int64_t>(p.sys_xvec.size());
+  w.rel16 = c.take<int32_t>(1);
+  w.o16 = p.nnz > 0 ? c.take<int16_t>(p.nnz) : nullptr;
   w.bytes = c.used;
   return w;
 }
@@ -1043,8 +1057,16 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
                          hipMemcpyHostToDevice, s));
   MPB_HIP(hipMemcpyAsync(c.w.sys_xvec, pl.sys_xvec.data(), pl.sys_xvec.size() * sizeof(int64_t),
                          hipMemcpyHostToDevice, s));
+  const int32_t one = 1;
+  MPB_HIP(hipMemcpyAsync(c.w.rel16, &one, sizeof(int32_t), hipMemcpyHostToDevice, s));
   // the host vectors above go out of scope at return: wait for the copies
   MPB_HIP(hipStreamSynchronize(s));
+  // the 16-bit copy of the column structure the matrix-vector products read
+  if (c.w.o16 && A->n < ((int64_t)1 << 31)) {
+    if ((rc = launch_off16((int)A->n, A->row_ptr, A->col_idx, c.w.o16, c.w.rel16, s))) return rc;
+  } else if (c.w.o16) {
+    c.w.o16 = nullptr;
+  }
   BTables &t = c.t;
   t.S = pl.S;
   t.nch = (int32_t)pl.ch_sys.size();
@@ -1085,6 +1107,8 @@ static void benq_spmv_k(const BCtx &c, const double *pold, double *pnew, hipStre
   a.part = c.w.part1;
   a.n_active = c.w.n_active;
   a.sched = c.sched1;
+  a.o16 = c.w.o16;
+  a.rel16 = c.w.rel16;
   if (c.ilp == 1)
     hipLaunchKernelGGL(bspmv_kernel<1>, dim3(c.G1), dim3(256), 0, s, a);
   else

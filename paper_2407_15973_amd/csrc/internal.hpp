@@ -136,5 +136,8 @@ struct Carver {
 
 // launchers implemented in solve.hip, used by setup and api
 int launch_round(const double *in, void *out, int64_t count, int prec, double scale, hipStream_t s);
+// writes col - row of every entry of the CSR as int16 into o; clears *flag
+// when some entry lies more than 32767 rows from its row
+int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_t *flag, hipStream_t s);
 
 }  // namespace mpb

@@ -174,11 +174,11 @@ __device__ __forceinline__ double sum_partials(double *p, int n, int stride, dou
 static_assert(offsetof(PcgState, rel16) == offsetof(PcgState, status) + 4 && offsetof(PcgState, status) % 8 == 0,
               "status and rel16 are read as one 8-byte word");
 
-// The 16-bit row-relative copy of A's column indices (col - row) used by the
-// PCG SpMV; any entry farther than 32767 rows from its row clears st->rel16,
-// and the products keep the 32-bit indices.
+// The 16-bit row-relative copy of A's column indices (col - row) read by the
+// PCG SpMVs; any entry farther than 32767 rows from its row clears *flag, and
+// the products keep the 32-bit indices.
 __global__ __launch_bounds__(256) void off16_kernel(int n, const int32_t *rp, const int32_t *ci, int16_t *o,
-                                                    PcgState *st) {
+                                                    int32_t *flag) {
   bool ok = true;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     for (int k = rp[i]; k < rp[i + 1]; ++k) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void off16_kernel(int n, const int32_t *rp, co
       o[k] = (int16_t)d;
     }
   }
-  if (!ok) __hip_atomic_store(&st->rel16, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!ok) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
@@ -1422,6 +1422,12 @@ static void enqueue_poly_map(const bjac_handle *M, int high, PcgState *st, const
 }
 
 // ---------------------------------------------------------------- launchers
+int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_t *flag, hipStream_t s) {
+  hipLaunchKernelGGL(off16_kernel, dim3(poly_grid(n)), dim3(256), 0, s, n, rp, ci, o, flag);
+  MPB_HIP(hipGetLastError());
+  return BJAC_OK;
+}
+
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
                         PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr) {
   SpmvArgs a{};
@@ -1762,9 +1768,7 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   MPB_HIP(hipEventRecord(e0, s));
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
                      M->policy.temporal, opts->relres_hist, opts->high_hist);
-  if (w.o16)
-    hipLaunchKernelGGL(off16_kernel, dim3(poly_grid(A->n)), dim3(256), 0, s, (int)A->n, A->row_ptr, A->col_idx, w.o16,
-                       w.st);
+  if (w.o16) launch_off16((int)A->n, A->row_ptr, A->col_idx, w.o16, &w.st->rel16, s);
   hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q);
   hipLaunchKernelGGL(fill_empty_kernel, dim3(24), dim3(256), 0, s, w.part1, 3 * kMaxGrid);
   // first application z_0 = M^-1 r_0 (alpha = 0 leaves x = 0, r = b)

@@ -308,3 +308,21 @@ def test_batched_tiny_and_ragged_systems():
             if bsys.A.n <= 64:
                 assert res.col_iters[col] == 1
             col += 1
+
+
+def test_batched_far_couplings_keep_32_bit_indices():
+    # a 33000 x 2 grid couples rows 33000 apart, beyond the 16-bit row-relative
+    # column copy: the products fall back to the 32-bit indices
+    A = gen.poisson2d(33000, 2)
+    rng = np.random.default_rng(31)
+    B = rng.uniform(-1, 1, (A.n, 2))
+    bp = gen.uniform_blocks(A.n, 32)
+    st = gen.stack_batch([gen.BatchSystem(A, bp, B)])
+    M, bs, res = _run(st, mb.Policy(mode=mb.FIXED, low=mb.FP32), maxit=200)
+    assert res.status == mb.OK
+    ref = _oracle_cols(st, M.tags(), 1e-10, 200)
+    x = res.x.cpu().numpy().reshape(A.n, 2)
+    for c, (it, status, xo, sub, bcol) in enumerate(ref):
+        assert status == OP.CONVERGED
+        assert abs(int(res.col_iters[c]) - it) <= max(2, int(0.05 * it))
+        assert OP.true_relres(A, x[:, c], B[:, c]) <= 2e-10
