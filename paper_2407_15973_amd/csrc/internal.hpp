@@ -13,10 +13,11 @@ namespace mpb {
 
 constexpr int kWaveRows = 64;       // padded rows of one apply wave tile
 constexpr int kSpmvRows = 64;       // rows of one SpMV wave tile
-constexpr int kSpmvNnzCap = 448;    // CSR entries staged in LDS per SpMV wave tile
+constexpr int kSpmvNnzCap = 448;    // CSR entries staged in LDS per batched SpMV wave tile
+constexpr int kSpmvSlot = 512;      // LDS entries per wave of the PCG SpMV (16-byte chunks)
 constexpr int kMaxGrid = 2048;      // persistent workgroups (multiple of 8)
-constexpr int kGridPerCu = 3;       // persistent workgroups per compute unit (measured: more
-                                    // resident streams lower the HBM rate of these kernels)
+constexpr int kGridPerCu = 2;       // persistent workgroups per compute unit (measured at 128^3:
+                                    // 2 beats 3 by 3 us per FP16 apply, 1 loses 5 us per SpMV)
 
 // Device-resident PCG scalars. Written only by the last workgroup of each
 // kernel (ticket pattern) and by the init kernel.

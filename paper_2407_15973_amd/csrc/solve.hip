@@ -207,19 +207,23 @@ struct SpmvArgs {
   PcgState *st;
   double *part;
   const int16_t *o16;   // PCG: col - row of every entry, valid while st->rel16
+  int32_t nnz8;         // nnz rounded down to a multiple of 8: whole 16-byte chunks of every array
+  int32_t vec;          // values and indices 16-byte aligned: tiles may be staged in 16-byte chunks
 };
 
 // Dot product of one CSR row with p_new = z + beta p_old (the p update of PCG
-// folded into the product; PLAIN mode reads p = z). Eight entries at a time
+// folded into the product; PLAIN mode reads p = z). Seven entries at a time
+// (a 7-point row in one group: measured 52.6 -> 50.7 us per product at 128^3
+// against groups of eight, whose clamped eighth gather is pure overhead there)
 // with every load in flight before the first multiply: indices past the row
 // end are clamped to its last entry and their values replaced by zero, so
 // there is no branch inside a group. Also returns p_new of the row itself
 // when the row stores its diagonal.
-template <bool PCG, bool STAGED>
+template <bool PCG, class IT>
 __device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
-                                          const int *__restrict__ cidx, const double *__restrict__ vals, double beta,
+                                          const IT *__restrict__ cidx, const double *__restrict__ vals, double beta,
                                           int base, int len, int row, double &prow, bool &found, int roff) {
-  constexpr int U = 8;
+  constexpr int U = 7;
   double acc = 0.0;
   for (int k0 = 0; k0 < len; k0 += U) {
     int cs[U];
@@ -227,7 +231,7 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int idx = base + min(k0 + k, len - 1);
-      cs[k] = cidx[idx] + roff;   // roff = row when the indices are row-relative
+      cs[k] = (int)cidx[idx] + roff;   // roff = row when the indices are row-relative
       const double v = vals[idx];
       vs[k] = (k0 + k < len) ? v : 0.0;
     }
@@ -245,87 +249,129 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
   return acc;
 }
 
+// s_waitcnt operand that waits for every vector memory operation and leaves the
+// other counters free (gfx9 encoding: vmcnt 0, expcnt 7, lgkmcnt 15)
+constexpr int kVmcntZero = 0x0F70;
+
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+
 // The tiles of one wave; returns the wave's partial (p_new, q). REL: the
-// staged column indices are the 16-bit row-relative copy (one loop per
-// choice, decided once per launch).
+// column indices are the 16-bit row-relative copy (one loop per choice,
+// decided once per launch).
+//
+// A tile's CSR entries are staged into the wave's LDS slice in whole 16-byte
+// chunks from the 8-entry boundary at or below its first entry: 4 loads of
+// values and 1 (16-bit) or 2 (32-bit) of indices per lane instead of one load
+// per entry and array. Tiles whose window would pass the last whole 8-entry
+// group of the arrays, or that hold more than a slice, read their rows from
+// memory unstaged. The matrix is read once per product: non-temporal loads keep
+// it from displacing the vectors, which the next kernel then finds in the
+// last-level cache.
+//
+// Software-pipelined by one tile: tile t+1's chunk loads are issued before
+// tile t's gathers of z and p_old, so the two round trips overlap (the row
+// pointers run two tiles ahead), and the q / p_new stores of tile t are held
+// back until after tile t+1's loads are issued.
 template <bool PCG, bool REL>
 __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc) {
-  constexpr int CAP = kSpmvNnzCap;
-  constexpr int NL = CAP / 64;
+  constexpr int SLOT = kSpmvSlot;
+  constexpr int NV = SLOT * 8 / 16 / 64;                  // value chunks per lane
+  constexpr int NC = SLOT * (REL ? 2 : 4) / 16 / 64;      // index chunks per lane
+  constexpr int EV = 2, EC = REL ? 8 : 4;                 // entries per chunk
+  using IT = typename std::conditional<REL, int16_t, int32_t>::type;
   const int32_t *__restrict__ rp = a.rp;
-  const int32_t *__restrict__ ci = a.ci;
-  const int16_t *__restrict__ o16 = a.o16;
+  const IT *__restrict__ cix = REL ? (const IT *)a.o16 : (const IT *)a.ci;
   const double *__restrict__ vv_g = a.v;
   const double *__restrict__ z = a.z;
   const double *__restrict__ pold = a.pold;
+  const IT *sci = (const IT *)sc;
   const int lane = threadIdx.x & 63;
   double dot = 0.0;
-  bool s_has = false;   // q and p_new of the previous tile, stored after this tile's loads
+  bool s_has = false;   // q and p_new of the previous tile, stored after the next loads
   int s_row = 0;
   double s_q = 0.0, s_p = 0.0;
-  // row pointers of a lane's row in tile t (tile clamped into range, row into
-  // the tile), fetched one tile ahead
-  auto fetch_rp = [&](int t, int &s_out, int &e_out) {
-    const int tc = min(t, a.ntiles - 1);
-    const int rc = min(tc * 64 + lane, min(a.n, tc * 64 + 64) - 1);
-    s_out = rp[rc];
-    e_out = rp[rc + 1];
-  };
   WaveIter it(a.ntiles);
-  int s_nx, e_nx;
-  fetch_rp(it.t, s_nx, e_nx);
-  for (; it.t < it.end; it.t += it.step) {
-    const int r0 = it.t * 64;
-    const int r1 = min(a.n, r0 + 64);
-    const int row = r0 + lane;
-    const bool has = row < r1;
-    const int s = s_nx, e = e_nx;
-    fetch_rp(it.t + it.step, s_nx, e_nx);
-    // rp[r0] is lane 0's start, rp[r1] the end of the tile's last row
-    const int e0 = __builtin_amdgcn_readlane(s, 0);
-    const int cnt = __builtin_amdgcn_readlane(e, r1 - 1 - r0) - e0;
-    const int len = has ? e - s : 0;
-    double acc = 0.0, prow = 0.0;
-    bool found = false;
-    if (cnt > 0 && cnt <= CAP) {
-      // coalesced staging of the tile's CSR entries into this wave's LDS. The
-      // matrix is read once per product: non-temporal loads keep it from
-      // displacing the vectors, which the next kernel then finds in the
-      // last-level cache (measured: SpMV unchanged, fused apply 51 -> 46 us at
-      // 128^3; the same hint on the stored inverses made the apply slower).
-      // With the 16-bit row-relative copy of the indices the staged values
-      // are col - row, 2 bytes per entry instead of 4.
-      double vv[NL];
-      int cc[NL];
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const int i = min(lane + 64 * k, cnt - 1);
-        vv[k] = __builtin_nontemporal_load(vv_g + e0 + i);
-        if constexpr (REL) cc[k] = (int)__builtin_nontemporal_load(o16 + e0 + i);
-        else cc[k] = __builtin_nontemporal_load(ci + e0 + i);
-      }
-      if (s_has) {
-        a.q[s_row] = s_q;
-        if (PCG) a.pnew[s_row] = s_p;
-        s_has = false;
-      }
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const int i = lane + 64 * k;
-        if (i < cnt) {
-          sv[i] = vv[k];
-          sc[i] = cc[k];
-        }
-      }
-      wave_lds_sync();
-      acc = row_dot<PCG, true>(z, pold, sc, sv, beta, s - e0, len, row, prow, found, REL ? row : 0);
-      wave_lds_sync();
-    } else {
-      acc = row_dot<PCG, false>(z, pold, ci, vv_g, beta, s, len, row, prow, found, 0);
+  // row pointers of a lane's row in tile t (row clamped into the tile); tiles
+  // at or past the wave's end are not read
+  auto fetch_rp = [&](int t, int &s_out, int &e_out) {
+    s_out = e_out = 0;
+    if (t < it.end) {
+      const int rc = min(t * 64 + lane, min(a.n, t * 64 + 64) - 1);
+      s_out = rp[rc];
+      e_out = rp[rc + 1];
     }
+  };
+  // staging window of tile t: chunk-aligned base and entries from there to
+  // the tile's end (0: the tile is read unstaged)
+  auto window = [&](int t, int s, int e, int &base, int &need) {
+    const int e0 = __builtin_amdgcn_readlane(s, 0);
+    const int last = min(a.n, t * 64 + 64) - 1 - t * 64;
+    const int cnt = t < it.end ? __builtin_amdgcn_readlane(e, last) - e0 : 0;
+    base = e0 & ~7;
+    need = e0 - base + cnt;
+    // every chunk read starts below base + need and lies below base + need
+    // rounded up to 8 entries, which must not pass the last whole group
+    if (!a.vec || cnt <= 0 || need > SLOT || base + ((need + 7) & ~7) > a.nnz8) need = 0;
+  };
+  auto stage = [&](int base, int need, u32x4 (&gv)[NV], u32x4 (&gc)[NC]) {
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    const u32x4 *vp = (const u32x4 *)(vv_g + base);
+    const u32x4 *cp = (const u32x4 *)(cix + base);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int c = lane + 64 * q;
+      gv[q] = c * EV < need ? __builtin_nontemporal_load(vp + c) : zero;
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = lane + 64 * q;
+      gc[q] = c * EC < need ? __builtin_nontemporal_load(cp + c) : zero;
+    }
+  };
+  int s_c, e_c, s_n, e_n, base_c, need_c;
+  u32x4 gv[NV], gc[NC];
+  fetch_rp(it.t, s_c, e_c);
+  fetch_rp(it.t + it.step, s_n, e_n);
+  window(it.t, s_c, e_c, base_c, need_c);
+  stage(base_c, need_c, gv, gc);
+  // the first tile's chunks in registers before the loop: inside it the
+  // compiler then needs no wait on the loads of the tile after
+  __builtin_amdgcn_s_waitcnt(kVmcntZero);
+  for (; it.t < it.end; it.t += it.step) {
+    const int tn = it.t + it.step;
+    int s_nn, e_nn, base_n, need_n;
+    fetch_rp(tn + it.step, s_nn, e_nn);
+    window(tn, s_n, e_n, base_n, need_n);
+    u32x4 hv[NV], hc[NC];
+    stage(base_n, need_n, hv, hc);
     if (s_has) {
       a.q[s_row] = s_q;
       if (PCG) a.pnew[s_row] = s_p;
+      s_has = false;
+    }
+    const int row = it.t * 64 + lane;
+    const bool has = row < a.n;
+    const int len = has ? e_c - s_c : 0;
+    double acc = 0.0, prow = 0.0;
+    bool found = false;
+    if (need_c > 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EV < need_c) ((u32x4 *)sv)[c] = gv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EC < need_c) ((u32x4 *)sc)[c] = gc[q];
+      }
+      wave_lds_sync();
+      acc = row_dot<PCG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, REL ? row : 0);
+      wave_lds_sync();
+    } else if (REL) {
+      acc = row_dot<PCG>(z, pold, a.o16, vv_g, beta, s_c, len, row, prow, found, row);
+    } else {
+      acc = row_dot<PCG>(z, pold, a.ci, vv_g, beta, s_c, len, row, prow, found, 0);
     }
     s_has = has;
     s_row = row;
@@ -335,6 +381,16 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
       s_p = pr;
       dot = fma(pr, acc, dot);
     }
+    s_c = s_n;
+    e_c = e_n;
+    s_n = s_nn;
+    e_n = e_nn;
+    base_c = base_n;
+    need_c = need_n;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) gv[q] = hv[q];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) gc[q] = hc[q];
   }
   if (s_has) {
     a.q[s_row] = s_q;
@@ -345,9 +401,9 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
 
 template <bool PCG>
 __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
-  constexpr int CAP = kSpmvNnzCap;
-  __shared__ double svs[4][CAP];
-  __shared__ int scs[4][CAP];
+  constexpr int SLOT = kSpmvSlot;
+  __shared__ __align__(16) double svs[4][SLOT];
+  __shared__ __align__(16) int scs[4][SLOT];
   __shared__ double sh[4];
   __shared__ int flag, ok;
   // status and rel16 are adjacent: one load before the early exit
@@ -1443,6 +1499,9 @@ static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, 
   a.q = q;
   a.st = st;
   a.part = part;
+  a.nnz8 = (int32_t)(A->nnz & ~(int64_t)7);
+  const uintptr_t al = (uintptr_t)A->val | (uintptr_t)A->col_idx | (uintptr_t)o16;
+  a.vec = (al & 15) == 0;
   if (mode == SPMV_PCG) {
     const void *k = (const void *)spmv_kernel<true>;
     hipLaunchKernelGGL(spmv_kernel<true>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);

@@ -305,6 +305,38 @@ def test_compact_column_index_gives_identical_iterates():
     assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
 
 
+def test_unaligned_matrix_arrays_read_unstaged_with_identical_iterates():
+    # values and indices not 16-byte aligned: the SpMV reads every tile's rows
+    # straight from memory instead of staging 16-byte chunks; the same products
+    # in the same order, identical iterates
+    import copy
+    import torch
+    rng = np.random.default_rng(29)
+    A = gen.diffusion3d(gen.kappa_loguniform((13, 11, 9), rng))
+    b = rng.uniform(-1, 1, A.n)
+    bp = gen.uniform_blocks(A.n, 32)
+    Ad = mb.DeviceCSR(A, dev())
+    Au = copy.copy(Ad)
+    vbuf = torch.zeros(A.nnz + 1, dtype=torch.float64, device=dev())
+    cbuf = torch.zeros(A.nnz + 1, dtype=torch.int32, device=dev())
+    vbuf[1:] = Ad.val
+    cbuf[1:] = Ad.col_idx
+    Au.val, Au.col_idx = vbuf[1:], cbuf[1:]
+    assert Au.val.data_ptr() % 16 == 8 and Au.col_idx.data_ptr() % 16 == 4
+    Au.c = mb.bjac_csr(Au.n, Au.nnz, Au.row_ptr.data_ptr(), Au.col_idx.data_ptr(), Au.val.data_ptr())
+    out = []
+    for AA in (Ad, Au):
+        M = mb.BlockJacobi(AA, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+        for compact in (True, False):
+            S = mb.Solver(A.n, dev(), compact_index=compact)
+            out.append(S.solve(AA, M, tensor(b), tol=1e-10, maxit=2000, history=True, raise_on_error=False))
+    assert out[0].status == mb.OK
+    for r in out[1:]:
+        assert r.status == mb.OK and r.iters == out[0].iters
+        assert np.array_equal(r.relres_hist, out[0].relres_hist)
+        assert np.array_equal(r.x.cpu().numpy(), out[0].x.cpu().numpy())
+
+
 def test_compact_column_index_falls_back_for_far_couplings():
     # a 33000 x 2 grid couples rows 33000 apart, beyond 16 bits: the products
     # keep the 32-bit indices, still identical to the plain workspace
