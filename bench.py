@@ -8,7 +8,8 @@ One step = block-Jacobi setup (extract, FP64 invert, features, round + pack)
 plus the PCG solve to 1e-10, with A and b already resident in HBM.
 
 The headline value is the time to solution with the block inverses stored in
-FP16 (fMP); the same steps with FP64 storage are timed beside it. A profile
+FP16 (fMP), each block as its H00, H01 and H11 quarters (the inverse is
+symmetric); the same steps with FP64 storage are timed beside it. A profile
 pass times each kernel with HIP events on the stream it runs on and reports
 the dominant kernel against the 8 TB/s HBM roofline. The CPU oracle is timed
 on a bounded sample on the host.
@@ -29,7 +30,8 @@ Other workloads (each prints its own line of the same form):
   --workload band      128^3 log-uniform diffusion, blocks of 32: full vs
                        band-truncated storage of the inverses (diagonals
                        kept down to the format's unit roundoff), FP64 /
-                       FP32 / FP16
+                       FP32 / FP16, and symmetric storage (three of the
+                       four 16 x 16 quarters), FP64 / FP16
   --workload paper     the paper's own setting (Sec. 4.2, Table 4.2): 128^3
                        Diff3D-Const / Dis(1000) / Ani(s), f = 1, 32 slabs,
                        BJAC(k=2, t=2) uniform FP64 vs fMP FP32 vs aMP(hl/lh)
@@ -115,8 +117,8 @@ VERIFY = 3
 # profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
 # for the kernel sources they were measured on: reported when the digest of
 # those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "1b9d0ed161611cf7a75197ef4ae4a627866e907278767d8bf88a827892cb361e",
-           "spmv": 267551310, "apply": 252362895}
+TRAFFIC = {"sources_sha256": "d0c74349c7cd9003e0c1afa5178184226b45fa181701b6cc6e543f7e579e3cd9",
+           "spmv": 237234639, "apply": 252355088}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
@@ -169,8 +171,9 @@ def bench_diff3d(args):
     b = torch.as_tensor(p.b, device=dev)
     solver = mb.Solver(n, dev)
     tol, maxit = p.tol, p.maxit
-    pol16 = mb.Policy(mode=mb.FIXED, low=mb.FP16)
-    pol64 = mb.Policy(mode=mb.UNIFORM)
+    # both maps store each block's H00, H01 and H11 (the inverse is symmetric)
+    pol16 = mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM)
+    pol64 = mb.Policy(mode=mb.UNIFORM, storage=mb.STORE_SYM)
 
     def step(policy, profile=False):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -252,7 +255,8 @@ def bench_diff3d(args):
         "ms_per_step": ms16, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "apply_arith": "fp16-stored block inverses, f32 accumulation", "data": "synthetic",
         "config": {"workload": f"diff3d_loguniform_{args.N}^3_b32", "n": n, "nnz": nnz, "blocks": nb,
-                   "block_rows": 32, "precision_map": "fp16 fixed (fMP)", "tol": tol, "seed": 0},
+                   "block_rows": 32, "precision_map": "fp16 fixed (fMP)",
+                   "storage": "symmetric (H00, H01, H11 of each block)", "tol": tol, "seed": 0},
         "iters": r16.iters, "iters_fp64": r64.iters, "delay_iters": r16.iters - r64.iters,
         "restarts": r16.restarts, "restarts_fp64": r64.restarts, "true_relres_device": r16.true_relres,
         "setup_ms": setup16, "solve_ms": solve16, "fp64_ms_per_step": ms64, "fp64_setup_ms": setup64,
@@ -268,10 +272,10 @@ def bench_diff3d(args):
 
 
 # ------------------------------------------------------------- batched solves
-def batched_spmv_bytes(n, nnz, veclen):
-    """One batched SpMV launch: CSR once, and per (row, column) z and p_old
-    read, p_new and q written."""
-    return 12 * nnz + 4 * (n + 1) + 32 * veclen
+def batched_spmv_bytes(n, nnz, veclen, ib=4):
+    """One batched SpMV launch: CSR once (ib bytes per column index), and per
+    (row, column) z and p_old read, p_new and q written."""
+    return (8 + ib) * nnz + 4 * (n + 1) + 32 * veclen
 
 
 def batched_apply_bytes(nb, stored_bytes, veclen):
@@ -400,7 +404,7 @@ def bench_batched(args):
     log("profile pass")
     _, rp16, _ = step(pol16, profile=True)
     info16 = M16.info()
-    kb = {"spmv": batched_spmv_bytes(n, nnz, veclen), "apply": batched_apply_bytes(nb, info16["low_bytes"], veclen)}
+    kb = {"spmv": batched_spmv_bytes(n, nnz, veclen, index_bytes(st.A)), "apply": batched_apply_bytes(nb, info16["low_bytes"], veclen)}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp16.kernel_ms[name]
@@ -568,7 +572,9 @@ def bench_band(args):
     band = dict(storage=mb.STORE_BAND)
     pols = {"fp64_full": mb.Policy(mode=mb.UNIFORM), "fp16_full": mb.Policy(mode=mb.FIXED, low=mb.FP16),
             "fp64_band": mb.Policy(mode=mb.UNIFORM, **band), "fp32_band": mb.Policy(mode=mb.FIXED, low=mb.FP32, **band),
-            "fp16_band": mb.Policy(mode=mb.FIXED, low=mb.FP16, **band)}
+            "fp16_band": mb.Policy(mode=mb.FIXED, low=mb.FP16, **band),
+            "fp64_sym": mb.Policy(mode=mb.UNIFORM, storage=mb.STORE_SYM),
+            "fp16_sym": mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM)}
     head = "fp16_band"
 
     def step(policy, profile=False):

@@ -87,10 +87,22 @@ typedef enum {
  * reads (w_k + 1) / bpad_k of FULL's bytes. Band handles serve every entry
  * point that takes a handle (bjac_apply, bjac_apply_multi, pcg_solve,
  * pcg_solve_batched); the multi-column products then run on the vector units
- * instead of the matrix cores. */
+ * instead of the matrix cores.
+ * SYM: the same inverses as FULL in three quarters of its bytes for blocks of
+ * padded size 32 (not in the paper). The inverse H of an SPD block is
+ * symmetric, so of its 16 x 16 quarters H00, H01, H10, H11 only H00, H01 and
+ * H11 are stored, with FULL's scale and rounding, and the application uses the
+ * transpose of H01 for H10. The computed FP64 inverse is symmetric up to its
+ * own rounding (about one unit in the last place of FP64, far below every
+ * storage format's rounding), so the application matches FULL's to within the
+ * accumulation's rounding. Blocks of other padded sizes are stored as FULL.
+ * SYM handles serve bjac_apply, bjac_get_block (which returns the mirrored
+ * block) and pcg_solve; bjac_apply_multi and pcg_solve_batched return
+ * BJAC_EINVAL for them. */
 typedef enum {
   BJAC_STORE_FULL = 0,
-  BJAC_STORE_BAND = 1
+  BJAC_STORE_BAND = 1,
+  BJAC_STORE_SYM = 2
 } bjac_storage;
 
 /* Square CSR matrix, all arrays device memory, caller-owned, read-only.

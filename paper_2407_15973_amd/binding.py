@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmpbjac.so")
 FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 UNIFORM, FIXED, RULE, LEARNED, EXPLICIT = 0, 1, 2, 3, 4
 TEMPORAL_NONE, TEMPORAL_HL, TEMPORAL_LH = 0, 1, 2
-STORE_FULL, STORE_BAND = 0, 1
+STORE_FULL, STORE_BAND, STORE_SYM = 0, 1, 2
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 MLP_NPARAM = 5443
 MLP_NBLOB = MLP_NPARAM + 32
@@ -197,7 +197,7 @@ class Policy:
     d16: float = 1.0
     mlp_blob: object = None          # device float tensor [MLP_NBLOB]
     explicit_tags: object = None     # numpy uint8 [nb]
-    storage: int = STORE_FULL        # STORE_BAND: band-truncated inverses
+    storage: int = STORE_FULL        # STORE_BAND: band-truncated inverses; STORE_SYM: symmetric blocks of 32
     band_rtol: float = 0.0           # <= 0: each block's unit roundoff
 
     def c(self):

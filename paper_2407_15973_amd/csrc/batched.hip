@@ -840,6 +840,7 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
                       const int32_t *sys_m, int chunk_rows, int apply_rows, BPlan &pl) {
   if (!M || S < 1 || !sys_row || !sys_m || sys_row[0] != 0 || sys_row[S] != M->n) return BJAC_EINVAL;
   if (M->kind != 0) return BJAC_EINVAL;  // stored block inverses only
+  if (M->storage == BJAC_STORE_SYM) return BJAC_EINVAL;  // full or band storage only
   if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
   if (apply_rows < kBWaveRows || apply_rows > (1 << 20)) return BJAC_EINVAL;
   pl.S = S;
@@ -1407,7 +1408,7 @@ extern "C" int pcg_batched_tune(const bjac_csr *A, const bjac_handle *M, int32_t
 
 extern "C" int bjac_apply_multi(const bjac_handle *M, const double *R, double *Z, int32_t m, void *stream) {
   if (!M || !R || !Z || R == Z || m < 1 || m > kBCols) return BJAC_EINVAL;
-  if (M->kind != 0) return BJAC_EINVAL;
+  if (M->kind != 0 || M->storage == BJAC_STORE_SYM) return BJAC_EINVAL;
   BApplyArgs a{};
   a.blk_row = M->blk_row;
   a.bpad = M->bpad;

@@ -55,7 +55,13 @@ struct DevMap {
   const double *scale;
   const uint8_t *tag;
   const uint8_t *w = nullptr;   // band storage: diagonals 0..w[k] kept; null: full blocks
+  int32_t sym = 0;              // symmetric storage of the blocks of padded size 32
 };
+
+// Symmetric storage of a block of padded size 32: its first 16-row tile in
+// the full layout (H00 and H01), then H11 as the 16-row tile of a 16-column
+// block. Entries per block (elements of the block's format).
+constexpr int kSym32Elems = 64 * 8 + 64 * 4;
 
 }  // namespace mpb
 

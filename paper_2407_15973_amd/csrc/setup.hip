@@ -41,6 +41,7 @@ struct SetupArgs {
   double band_rtol;       // <= 0: the format's unit roundoff
   const uint8_t *w_lo;    // packing: band store of the low map when non-null
   const uint8_t *w_hi;    // packing: band store of the all-FP64 map when non-null
+  int32_t sym;            // packing: symmetric storage of the blocks of padded size 32
 };
 
 constexpr double kDomCap = 1e8;
@@ -91,6 +92,46 @@ __device__ __forceinline__ void store_rows(uint8_t *dst, const double (&row)[B],
       }
     }
   }
+}
+
+// Symmetric storage of a block of padded size 32: rows 0..15 (H00, H01) as
+// the first 16-row tile of the full layout, the columns 16..31 of rows 16..31
+// (H11) as the 16-row tile of a 16-column block after it; rows 16..31 store
+// nothing of columns 0..15, the transpose of H01.
+template <int P>
+__device__ __forceinline__ void store_rows_sym32(uint8_t *dst, const double (&row)[32], int lane, double inv_s) {
+  if (lane < 16) {
+    store_rows<32, P>(dst, row, lane, inv_s);
+  } else {
+    double h[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) h[j] = row[16 + j];
+    store_rows<16, P>(dst + 64 * 8 * prec_bytes(P), h, lane - 16, inv_s);
+  }
+}
+
+__device__ __forceinline__ void store_block_sym32(uint8_t *dst, int prec, const double (&row)[32], int lane,
+                                                  double inv_s) {
+  switch (prec) {
+    case P64: store_rows_sym32<P64>(dst, row, lane, 1.0); break;
+    case P32: store_rows_sym32<P32>(dst, row, lane, inv_s); break;
+    case PBF16: store_rows_sym32<PBF16>(dst, row, lane, inv_s); break;
+    default: store_rows_sym32<P16>(dst, row, lane, inv_s); break;
+  }
+}
+
+// Stores block rows in the symmetric layout when it applies (blocks of 32);
+// false: the caller stores them otherwise.
+template <int B>
+__device__ __forceinline__ bool store_sym(uint8_t *dst, int prec, const double (&row)[B], int lane, double inv_s,
+                                          int sym) {
+  if constexpr (B == 32) {
+    if (sym) {
+      if (lane < 32) store_block_sym32(dst, prec, row, lane, inv_s);
+      return true;
+    }
+  }
+  return false;
 }
 
 template <int B>
@@ -342,7 +383,8 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   }
   if (a.off_hi) {
     if (a.w_hi) store_band<B>(a.base + a.off_hi[k], P64, row, lane, 1.0, a.w_hi[k]);
-    else store_block<B>(a.base + a.off_hi[k], P64, row, lane, 1.0);
+    else if (!store_sym<B>(a.base + a.off_hi[k], P64, row, lane, 1.0, a.sym))
+      store_block<B>(a.base + a.off_hi[k], P64, row, lane, 1.0);
     if (lane == 0) a.scale_hi[k] = 1.0;
   }
   if (a.off_lo) {
@@ -350,7 +392,8 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
     if (tag == P16 || tag == PBF16) sc = ldexp(1.0, ceil_log2(hmax) - kScaleTopExp);
     if (!(a.off_hi && tag == P64)) {
       if (a.w_lo) store_band<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc, a.w_lo[k]);
-      else store_block<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc);
+      else if (!store_sym<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc, a.sym))
+        store_block<B>(a.base + a.off_lo[k], tag, row, lane, 1.0 / sc);
     }
     if (lane == 0) a.scale_lo[k] = sc;
   }
@@ -401,7 +444,7 @@ static int make_plan(const bjac_csr *A, const int32_t *bp, int32_t nb, const bja
   if (pol->mode == BJAC_FIXED && (pol->low < BJAC_FP64 || pol->low > BJAC_FP16)) return BJAC_EINVAL;
   if (pol->mode == BJAC_EXPLICIT && !pol->explicit_tags) return BJAC_EINVAL;
   if (pol->mode == BJAC_LEARNED && !pol->mlp_blob) return BJAC_EINVAL;
-  if (pol->storage != BJAC_STORE_FULL && pol->storage != BJAC_STORE_BAND) return BJAC_EINVAL;
+  if (pol->storage < BJAC_STORE_FULL || pol->storage > BJAC_STORE_SYM) return BJAC_EINVAL;
   if (!(pol->band_rtol < 1.0)) return BJAC_EINVAL;  // NaN or >= 1
   pl.n = A->n;
   pl.nb = nb;
@@ -576,6 +619,7 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
 
   // precision map (and, for band storage, the widths) on the host
   const bool band = policy->storage == BJAC_STORE_BAND;
+  const bool sym = policy->storage == BJAC_STORE_SYM;
   a.band_rtol = policy->band_rtol;
   std::vector<uint8_t> tags(nb, 0), wb;
   const int mode = policy->mode;
@@ -600,11 +644,13 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   } else if (mode == BJAC_EXPLICIT) {
     std::memcpy(tags.data(), policy->explicit_tags, nb);
   }
-  // stored bytes of block k in format p: B^2 entries, or w + 1 diagonals of B
+  // stored bytes of block k in format p: B^2 entries, w + 1 diagonals of B,
+  // or the three stored quarters of a symmetric block of 32
   auto width = [&](int32_t k, int p) -> int { return band ? wb[(size_t)k * 4 + p] : 0; };
+  auto blk_elems = [&](int B) -> int64_t { return sym && B == 32 ? (int64_t)kSym32Elems : (int64_t)B * B; };
   auto blk_bytes = [&](int32_t k, int p) -> int64_t {
     const int64_t B = pl.bpad[k];
-    return (band ? B * (width(k, p) + 1) : B * B) * prec_bytes(p);
+    return (band ? B * (width(k, p) + 1) : blk_elems((int)B)) * prec_bytes(p);
   };
   // offsets: the FP64 map first (temporal), then the low map; in temporal
   // handles FP64 blocks of the low map alias the FP64 map
@@ -652,6 +698,7 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
     h->w_lo = L.w_lo;
     h->w_hi = pl.temporal ? L.w_hi : nullptr;
   }
+  if (sym) h->storage = BJAC_STORE_SYM;
   if (pl.temporal) {
     std::vector<uint8_t> t64(nb, 0);
     if (hipMemcpyAsync(L.off_hi, off_hi.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice, st) ||
@@ -669,6 +716,7 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   p2.scale_hi = L.scale_hi;
   p2.w_lo = band ? L.w_lo : nullptr;
   p2.w_hi = (band && pl.temporal) ? L.w_hi : nullptr;
+  p2.sym = sym ? 1 : 0;
   if ((rc = launch_setup(p2, cls, L.blist, st))) return fail(rc);
   int32_t bad = 0;
   if (hipMemcpyAsync(&bad, L.any_bad, sizeof(int32_t), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
@@ -682,14 +730,14 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   for (int32_t k = 0; k + 1 < nb && rows_uniform; ++k) rows_uniform = pl.sizes[k] == pl.uniform_b;
   h->rows_uniform = rows_uniform;
   if (rows_uniform && h->uprec_lo >= 0 && !band) {
-    const int64_t stride = (int64_t)pl.uniform_b * pl.uniform_b * prec_bytes(h->uprec_lo);
+    const int64_t stride = blk_elems(pl.uniform_b) * prec_bytes(h->uprec_lo);
     bool contig = true;
     for (int32_t k = 0; k < nb && contig; ++k) contig = off_lo[k] == off_lo[0] + k * stride;
     h->fast_lo = contig;
     h->lo_off0 = off_lo[0];
   }
   if (rows_uniform && pl.temporal && !band) {
-    const int64_t stride = (int64_t)pl.uniform_b * pl.uniform_b * 8;
+    const int64_t stride = blk_elems(pl.uniform_b) * 8;
     bool contig = true;
     for (int32_t k = 0; k < nb && contig; ++k) contig = off_hi[k] == off_hi[0] + k * stride;
     h->fast_hi = contig;
@@ -762,8 +810,9 @@ extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block
   const int64_t off = which == 1 ? h->h_off_hi[block] : h->h_off_lo[block];
   const int BY = prec_bytes(prec), V = 16 / BY;
   const bool band = h->storage == BJAC_STORE_BAND;
+  const bool sym = h->storage == BJAC_STORE_SYM && B == 32;
   const int w = band ? (which == 1 ? h->h_w_hi[block] : h->h_w_lo[block]) : 0;
-  std::vector<uint8_t> raw((size_t)B * (band ? w + 1 : B) * BY);
+  std::vector<uint8_t> raw((size_t)(sym ? kSym32Elems : B * (band ? w + 1 : B)) * BY);
   double sc = 1.0;
   MPB_HIP(hipMemcpyAsync(raw.data(), h->ws + off, raw.size(), hipMemcpyDeviceToHost, h->stream));
   MPB_HIP(hipMemcpyAsync(&sc, (which == 1 ? h->scale_hi : h->scale_lo) + block, sizeof(double),
@@ -771,7 +820,13 @@ extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block
   MPB_HIP(hipStreamSynchronize(h->stream));
   for (int i = 0; i < b; ++i) {
     for (int j = 0; j < b; ++j) {
-      if (!band) {
+      if (sym) {
+        // rows 0..15 in the full layout; H11 as a 16-column block after them;
+        // the lower-left quarter mirrored from the upper-right one
+        const int ii = (i >= 16 && j < 16) ? j : i, jj = (i >= 16 && j < 16) ? i : j;
+        const int64_t e = ii < 16 ? layout_elem(32, V, ii, jj) : 64 * 8 + layout_elem(16, V, ii - 16, jj - 16);
+        out[(size_t)i * b + j] = decode(raw.data() + e * BY, prec);
+      } else if (!band) {
         out[(size_t)i * b + j] = decode(raw.data() + layout_elem(B, V, i, j) * BY, prec);
       } else {
         const int d = std::abs(i - j);

@@ -521,7 +521,77 @@ struct Frag {
       return (double)acc;
     }
   }
+
+  // this lane's entry of k-step KS (column 4 KS + lane / 16 of its row), in
+  // the accumulation type: double for FP64, float for the others
+  template <int KS>
+  __device__ __forceinline__ auto value() const {
+    constexpr int g = KS / V, e = KS % V;
+    if constexpr (P == P64) {
+      if constexpr (e == 0) return __hiloint2double((int)h[g].y, (int)h[g].x);
+      else return __hiloint2double((int)h[g].w, (int)h[g].z);
+    } else {
+      constexpr int c = P == P32 ? e : e >> 1;
+      const uint32_t w = c == 0 ? h[g].x : c == 1 ? h[g].y : c == 2 ? h[g].z : h[g].w;
+      if constexpr (P == P32) return __uint_as_float(w);
+      else if constexpr (P == PBF16) return (e & 1) ? bf16_hi(w) : bf16_lo(w);
+      else return (e & 1) ? f16_hi(w) : f16_lo(w);
+    }
+  }
 };
+
+// A block of padded size 32 in symmetric storage (H00 and H01 as the first
+// 16-row tile of the full layout, H11 as a 16-column block after it): the
+// lane's fragments of both, and z = H r with the transpose of H01 standing
+// for H10.
+template <int P>
+struct Sym32 {
+  Frag<32, P> f0;
+  Frag<16, P> f1;
+
+  __device__ __forceinline__ void load(const uint8_t *blk, int lane) {
+    f0.load(blk, 0, lane);
+    f1.load(blk + 64 * 8 * prec_bytes(P), 0, lane);
+  }
+
+  // r32 / r64: the block's residual in LDS; writes sc * (H r) to zt[0..31];
+  // tt: 16 LDS slots of scratch
+  __device__ __forceinline__ void apply(const float *r32, const double *r64, double sc, double *zt, double *tt,
+                                        int lane) const {
+    using CT = std::conditional_t<P == P64, double, float>;
+    const int i = lane & 15, kq = lane >> 4;
+    const double z0 = f0.dot(r32, r64, lane);             // rows 0..15: H00 r0 + H01 r1
+    const double z1 = f1.dot(r32 + 16, r64 + 16, lane);   // rows 16..31: H11 r1
+    // (H01^T r0)[4 s + kq] = sum over i of H01[i][4 s + kq] r0[i]: lane (i, kq)
+    // holds H01[i][4 s + kq] as k-step 4 + s of its first-tile fragment
+    CT ri;
+    if constexpr (P == P64) ri = r64[i];
+    else ri = r32[i];
+    CT t0 = f0.template value<4>() * ri, t1 = f0.template value<5>() * ri;
+    CT t2 = f0.template value<6>() * ri, t3 = f0.template value<7>() * ri;
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1) {
+      t0 += __shfl_xor(t0, m, kWave);
+      t1 += __shfl_xor(t1, m, kWave);
+      t2 += __shfl_xor(t2, m, kWave);
+      t3 += __shfl_xor(t3, m, kWave);
+    }
+    if (i < 4) tt[4 * i + kq] = (double)(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3);
+    wave_lds_sync();
+    if (lane < 16) {
+      zt[lane] = z0 * sc;
+      zt[16 + lane] = (z1 + tt[lane]) * sc;
+    }
+  }
+};
+
+template <int P>
+__device__ __forceinline__ void sym32_apply(const uint8_t *blk, const float *r32, const double *r64, double sc,
+                                            double *zt, double *tt, int lane) {
+  Sym32<P> f;
+  f.load(blk, lane);
+  f.apply(r32, r64, sc, zt, tt, lane);
+}
 
 __device__ __forceinline__ void record_high(PcgState *st, int idx, int hi) {
   if (st->high_hist && idx >= 0 && idx <= st->maxit) st->high_hist[idx] = (uint8_t)hi;
@@ -668,19 +738,22 @@ __device__ __forceinline__ bool apply_skip(const ApplyArgs &a) {
 // in P, block k at a fixed stride. Rows, block addresses and the tile shape are
 // arithmetic, so the stored fragments, the per-block scales and the vectors of
 // a tile are all requested before the first wait.
-template <int B, int P, int MODE>
+// SYM: blocks of 32 in symmetric storage (H10 taken as the transpose of H01).
+template <int B, int P, int MODE, bool SYM = false>
 __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
+  static_assert(!SYM || B == 32, "symmetric storage holds blocks of 32");
   using T = ModeTraits<MODE>;
   constexpr int NB = 64 / B;        // blocks per wave tile
   constexpr int R = NB * B;         // padded rows per wave tile
   constexpr int MT = R / 16;        // 16-row tiles per wave tile
   constexpr int MPB = B / 16;       // 16-row tiles per block
   using F = Frag<B, P>;
-  constexpr int64_t BLK = (int64_t)B * B * prec_bytes(P);
-  constexpr bool PRE = MT * F::G <= 8;
+  constexpr int64_t BLK = (SYM ? (int64_t)kSym32Elems : (int64_t)B * B) * prec_bytes(P);
+  constexpr bool PRE = SYM || MT * F::G <= 8;
   __shared__ float r32s[4][64];
   __shared__ double r64s[4][64];
   __shared__ double zts[4][64];
+  __shared__ double tts[4][SYM ? 64 : 1];
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
@@ -702,11 +775,15 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
     const int kb = k0 + j;
     const int grow = kb * B + li;
     const bool real = lane < R && kb < a.nb && grow < a.n;
-    F fr[PRE ? MT : 1];
+    F fr[PRE && !SYM ? MT : 1];
+    Sym32<P> fs[SYM ? NB : 1];
     double scl = 1.0;
     if constexpr (T::APP) {
       if constexpr (P != P64) scl = scale[min(k0 + lane % NB, a.nb - 1)];
-      if constexpr (PRE) {
+      if constexpr (SYM) {
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) fs[jb].load(base + (int64_t)min(k0 + jb, a.nb - 1) * BLK, lane);
+      } else if constexpr (PRE) {
 #pragma unroll
         for (int u = 0; u < MT; ++u) fr[u].load(base + (int64_t)min(k0 + u / MPB, a.nb - 1) * BLK, u % MPB, lane);
       }
@@ -725,8 +802,18 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
         r32[lane] = __double2float_rn(rv);
       }
       wave_lds_sync();
+      if constexpr (SYM) {
 #pragma unroll
-      for (int u = 0; u < MT; ++u) {
+        for (int jb = 0; jb < NB; ++jb) {
+          if (k0 + jb < a.nb) {
+            const int cb = jb * B;
+            const double sc = (P == P64) ? 1.0 : bcast(scl, jb);
+            fs[jb].apply(r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < (SYM ? 0 : MT); ++u) {
         const int jb = u / MPB;
         if (k0 + jb < a.nb) {
           const int cb = jb * B;
@@ -786,6 +873,7 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
   __shared__ float r32s[4][64];
   __shared__ double r64s[4][64];
   __shared__ double zts[4][64];
+  __shared__ double tts[4][64];
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
@@ -844,6 +932,16 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
         const int prec = readlane_i(mtag, i);
         const uint8_t *blk = a.map.base + readlane_l(moff, i);
         const double sc = bcast(msc, i);
+        if (B == 32 && a.map.sym) {
+          switch (prec) {
+            case P64: sym32_apply<P64>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            case P32: sym32_apply<P32>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            case PBF16: sym32_apply<PBF16>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            default: sym32_apply<P16>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+          }
+          cb += B;
+          continue;
+        }
         for (int mt = 0; mt < B / 16; ++mt) {
           double zv;
           switch (B) {
@@ -1519,11 +1617,13 @@ struct MapSel {
 };
 
 static MapSel sel_lo(const bjac_handle *h) {
-  return MapSel{DevMap{h->ws, h->off_lo, h->scale_lo, h->tag_lo, h->w_lo}, h->uprec_lo, h->fast_lo, h->lo_off0};
+  return MapSel{DevMap{h->ws, h->off_lo, h->scale_lo, h->tag_lo, h->w_lo, h->storage == BJAC_STORE_SYM},
+                h->uprec_lo, h->fast_lo, h->lo_off0};
 }
 static MapSel sel_hi(const bjac_handle *h) {
   if (!h->off_hi) return sel_lo(h);
-  return MapSel{DevMap{h->ws, h->off_hi, h->scale_hi, h->tag_hi, h->w_hi}, (int)P64, h->fast_hi, h->hi_off0};
+  return MapSel{DevMap{h->ws, h->off_hi, h->scale_hi, h->tag_hi, h->w_hi, h->storage == BJAC_STORE_SYM}, (int)P64,
+                h->fast_hi, h->hi_off0};
 }
 
 template <class K>
@@ -1533,6 +1633,17 @@ static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a) {
 
 template <int B, int MODE>
 static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
+  if constexpr (B == 32 && MODE != M_UPD) {
+    if (a.map.sym) {
+      switch (prec) {
+        case P64: launch_persistent(apply_fast_kernel<32, P64, MODE, true>, s, a); break;
+        case P32: launch_persistent(apply_fast_kernel<32, P32, MODE, true>, s, a); break;
+        case PBF16: launch_persistent(apply_fast_kernel<32, PBF16, MODE, true>, s, a); break;
+        default: launch_persistent(apply_fast_kernel<32, P16, MODE, true>, s, a); break;
+      }
+      return;
+    }
+  }
   switch (prec) {
     case P64: launch_persistent(apply_fast_kernel<B, P64, MODE>, s, a); break;
     case P32: launch_persistent(apply_fast_kernel<B, P32, MODE>, s, a); break;

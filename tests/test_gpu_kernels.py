@@ -250,3 +250,83 @@ def test_temporal_handle_stores_both_maps():
     assert np.all(np.abs(z_lo - ref_lo) <= (gamma(48, 2.0 ** -24) + 2.0 ** -10) * OB.apply_abs(store, bp, r))
     info = M.info()
     assert info["high_bytes"] == (len(bp) - 1) * 48 * 48 * 8 and info["low_bytes"] == (len(bp) - 1) * 48 * 48 * 2
+
+
+# ------------------------------------------------ symmetric storage (blocks of 32)
+@pytest.mark.parametrize("prec", [OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16])
+def test_sym_storage_exact_family(prec):
+    # integer inverses are exactly symmetric: the three stored quarters read
+    # back as the oracle's full rounded block, and the application stays within
+    # the FP32 (FP64) accumulation bound of the oracle's full product
+    rng = np.random.default_rng(11)
+    A = gen.spd_exact_inverse_blocks(40, 32, rng)
+    bp = gen.uniform_blocks(A.n, 32)
+    nb = len(bp) - 1
+    tags = np.full(nb, prec, np.uint8)
+    H, store = oracle_setup(A, bp, tags)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=prec, storage=mb.STORE_SYM))
+    full = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=prec))
+    assert M.info()["low_bytes"] * 4 == full.info()["low_bytes"] * 3
+    for k in range(nb):
+        got, s = M.block(k)
+        Hh, s_ref, _ = store[k]
+        assert s == s_ref
+        np.testing.assert_array_equal(got, Hh)
+    u = 2.0 ** -53 if prec == OPr.FP64 else 2.0 ** -24
+    for trial in range(3):
+        r = rng.uniform(-1, 1, A.n) * np.exp(rng.uniform(-30, 0, A.n))
+        z = M.apply(tensor(r)).cpu().numpy()
+        ref = OB.apply(store, bp, r)
+        bound = gamma(32, u) * OB.apply_abs(store, bp, r)
+        assert np.all(np.abs(z - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("sizes", [None, (16, 32, 48, 64), (7, 33, 64, 32)])
+def test_sym_storage_general_mixed_map(sizes):
+    # blocks of padded size 32 stored symmetric, the others full; mixed formats
+    # run the generic kernel. H10 of the oracle's inverse and the transpose of
+    # its H01 differ by the FP64 inversion's rounding, bounded like the stored
+    # one-ulp differences of the full-storage test
+    A, bp, rng = _diffusion_case(seed=6, shape=(16, 12, 10), sizes=sizes, b=32)
+    nb = len(bp) - 1
+    tags = rng.choice([OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16], size=nb).astype(np.uint8)
+    if sizes is None:
+        tags[:] = OPr.FP16      # one format: the arithmetic tile path
+    Ad = mb.DeviceCSR(A, dev())
+    pol = mb.Policy(mode=mb.EXPLICIT, explicit_tags=tags, storage=mb.STORE_SYM)
+    M = mb.BlockJacobi(Ad, bp, pol)
+    H, store = oracle_setup(A, bp, tags)
+    bmax = int(np.max(np.diff(bp)))
+    kap = max(np.linalg.cond(h, 1) for h in H)
+    ulp_rel = np.array([{0: 2.0 ** -52, 1: 2.0 ** -23, 2: 2.0 ** -7, 3: 2.0 ** -10}[t] for t in tags])
+    per_row = np.repeat(ulp_rel, np.diff(bp))
+    for trial in range(2):
+        r = rng.uniform(-1, 1, A.n)
+        z = M.apply(tensor(r)).cpu().numpy()
+        ref = OB.apply(store, bp, r)
+        zb = OB.apply_abs(store, bp, r)
+        bound = (gamma(bmax, 2.0 ** -24) + per_row + 8 * bmax * kap * 2.0 ** -53) * zb
+        assert np.all(np.abs(z - ref) <= bound + 1e-300)
+    # a read-back block of padded size 32 mirrors its upper-right quarter
+    nsym = 0
+    for k in range(nb):
+        got, _ = M.block(k)
+        b = got.shape[0]
+        if 16 < b <= 32:
+            np.testing.assert_array_equal(got[16:, :16], got[:16, 16:].T)
+            nsym += 1
+    assert nsym > 0
+
+
+def test_sym_storage_rejected_by_multi_column_entry_points():
+    A, bp, rng = _diffusion_case(seed=8, shape=(8, 8, 8), b=32)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM))
+    with pytest.raises(mb.MpbjacError) as e:
+        M.apply_multi(tensor(rng.uniform(-1, 1, (A.n, 2))))
+    assert e.value.code == mb.EINVAL
+    with pytest.raises(mb.MpbjacError) as e:
+        mb.BatchSolver(Ad, M, np.array([0, A.n], np.int32), np.array([1], np.int32)).solve(
+            tensor(rng.uniform(-1, 1, A.n)))
+    assert e.value.code == mb.EINVAL

@@ -347,3 +347,46 @@ def test_compact_column_index_falls_back_for_far_couplings():
     assert r1.status == mb.OK and r1.iters == r2.iters
     assert np.array_equal(r1.relres_hist, r2.relres_hist)
     assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
+
+
+@pytest.mark.parametrize("prec,slack", [(OPr.FP64, 1), (OPr.FP32, 2), (OPr.FP16, 2)])
+def test_sym_storage_pcg_matches_oracle(prec, slack):
+    # symmetric storage of blocks of 32 holds FULL's values (H10 read as the
+    # transpose of H01): the oracle's full-storage PCG is the reference
+    rng = np.random.default_rng(41)
+    A = gen.diffusion3d(gen.kappa_loguniform((24, 20, 16), rng))
+    bp = gen.uniform_blocks(A.n, 32)
+    nb = len(bp) - 1
+    b = rng.uniform(-1, 1, A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    pol = (mb.Policy(mode=mb.UNIFORM, storage=mb.STORE_SYM) if prec == OPr.FP64
+           else mb.Policy(mode=mb.FIXED, low=prec, storage=mb.STORE_SYM))
+    M = mb.BlockJacobi(Ad, bp, pol)
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(b), tol=1e-10, maxit=3000)
+    ref = OP.solve_bjac(A, bp, b, np.full(nb, prec, np.uint8), tol=1e-10, maxit=3000)
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= slack, (res.iters, ref.iters)
+    assert OP.true_relres(A, res.x.cpu().numpy(), b) <= 2e-10
+
+
+def test_sym_storage_temporal_and_rule_maps():
+    # both maps of a temporal handle and a per-block rule map (generic kernel)
+    rng = np.random.default_rng(42)
+    A = gen.diffusion3d(gen.kappa_loguniform((20, 16, 12), rng))
+    bp = gen.uniform_blocks(A.n, 32)
+    nb = len(bp) - 1
+    b = rng.uniform(-1, 1, A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=mb.TEMPORAL_HL, adp_tol=1e-4,
+                                         storage=mb.STORE_SYM))
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(b), tol=1e-10, maxit=3000)
+    ref = OP.solve_bjac(A, bp, b, np.full(nb, OPr.FP16, np.uint8), tol=1e-10, maxit=3000,
+                        temporal=OP.TEMPORAL_HL, adp_tol=1e-4)
+    assert res.status == mb.OK and abs(res.iters - ref.iters) <= 2, (res.iters, ref.iters)
+    Mr = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.RULE, storage=mb.STORE_SYM))
+    Mf = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.RULE))
+    assert np.array_equal(Mr.tags(), Mf.tags())
+    rr = mb.Solver(A.n, dev()).solve(Ad, Mr, tensor(b), tol=1e-10, maxit=3000)
+    rf = mb.Solver(A.n, dev()).solve(Ad, Mf, tensor(b), tol=1e-10, maxit=3000)
+    assert rr.status == mb.OK and abs(rr.iters - rf.iters) <= 2
+    assert OP.true_relres(A, rr.x.cpu().numpy(), b) <= 2e-10
