@@ -18,6 +18,9 @@ constexpr int kSpmvSlot = 512;      // LDS entries per wave of the PCG SpMV (16-
 constexpr int kMaxGrid = 2048;      // persistent workgroups (multiple of 8)
 constexpr int kGridPerCu = 2;       // persistent workgroups per compute unit (measured at 128^3:
                                     // 2 beats 3 by 3 us per FP16 apply, 1 loses 5 us per SpMV)
+constexpr int kGridPerCuGeneric = 3;  // the same for the per-block dispatch applications (generic and
+                                      // generic band) and the paper-mode CSR sweeps (measured: 2 per CU
+                                      // costs the generic apply 8 %, the sweeps 20 %)
 
 // Device-resident PCG scalars. Written only by the last workgroup of each
 // kernel (ticket pattern) and by the init kernel.

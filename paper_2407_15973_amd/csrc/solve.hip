@@ -50,7 +50,7 @@ struct WaveIter {
 // compute unit, at least two tiles per wave (fewer, longer-lived workgroups
 // cost less ramp-up and a shorter end-of-kernel reduction), a multiple of 8
 // when possible.
-static int grid_for_waves(int T, const void *kernel) {
+static int grid_for_waves(int T, const void *kernel, int per_cu_max = kGridPerCu) {
   static std::unordered_map<const void *, int> cap;
   auto it = cap.find(kernel);
   if (it == cap.end()) {
@@ -62,7 +62,7 @@ static int grid_for_waves(int T, const void *kernel) {
       per_cu = 1;
       cus = 256;
     }
-    it = cap.emplace(kernel, (per_cu < kGridPerCu ? per_cu : kGridPerCu) * cus).first;
+    it = cap.emplace(kernel, (per_cu < per_cu_max ? per_cu : per_cu_max) * cus).first;
   }
   int G = (T + 7) / 8;
   if (G > it->second) G = it->second;
@@ -1515,8 +1515,8 @@ static void enqueue_poly_app(const bjac_handle *M, PolyArgs a, const double *r, 
   const int64_t n = M->n;
   const int G = poly_grid(n);
   const int ntiles = (int)((n + 63) / 64);
-  const int GC = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_SWEEP>);
-  const int GR = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_RESID>);
+  const int GC = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_SWEEP>, kGridPerCuGeneric);
+  const int GR = grid_for_waves(ntiles, (const void *)poly_csr_kernel<T, PO_RESID>, kGridPerCuGeneric);
   a.val = sizeof(T) == 4 ? (const void *)M->val32 : (const void *)M->pval;
   a.dinv = sizeof(T) == 4 ? (const void *)M->dinv32 : (const void *)M->dinv64;
   T *v = (T *)M->pbuf, *w = (T *)(M->pbuf + n), *ya = (T *)(M->pbuf + 2 * n), *yb = (T *)(M->pbuf + 3 * n);
@@ -1627,8 +1627,8 @@ static MapSel sel_hi(const bjac_handle *h) {
 }
 
 template <class K>
-static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a) {
-  hipLaunchKernelGGL(kernel, dim3(grid_for_waves(a.ntiles, (const void *)kernel)), dim3(256), 0, s, a);
+static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a, int per_cu_max = kGridPerCu) {
+  hipLaunchKernelGGL(kernel, dim3(grid_for_waves(a.ntiles, (const void *)kernel, per_cu_max)), dim3(256), 0, s, a);
 }
 
 template <int B, int MODE>
@@ -1676,12 +1676,13 @@ static void launch_band(const bjac_handle *h, int prec, hipStream_t s, const App
     }
     return;
   }
+  constexpr int G = kGridPerCuGeneric;
   switch (prec) {
-    case P64: launch_persistent(apply_band_kernel<MODE, P64>, s, a); break;
-    case P32: launch_persistent(apply_band_kernel<MODE, P32>, s, a); break;
-    case PBF16: launch_persistent(apply_band_kernel<MODE, PBF16>, s, a); break;
-    case P16: launch_persistent(apply_band_kernel<MODE, P16>, s, a); break;
-    default: launch_persistent(apply_band_kernel<MODE, -1>, s, a); break;
+    case P64: launch_persistent(apply_band_kernel<MODE, P64>, s, a, G); break;
+    case P32: launch_persistent(apply_band_kernel<MODE, P32>, s, a, G); break;
+    case PBF16: launch_persistent(apply_band_kernel<MODE, PBF16>, s, a, G); break;
+    case P16: launch_persistent(apply_band_kernel<MODE, P16>, s, a, G); break;
+    default: launch_persistent(apply_band_kernel<MODE, -1>, s, a, G); break;
   }
 }
 
@@ -1704,7 +1705,7 @@ static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, co
       default: launch_fast_bm<64, MODE>(prec, s, a); break;
     }
   } else {
-    launch_persistent(apply_generic_kernel<MODE>, s, a);
+    launch_persistent(apply_generic_kernel<MODE>, s, a, kGridPerCuGeneric);
   }
 }
 
