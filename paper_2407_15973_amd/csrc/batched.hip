@@ -126,7 +126,9 @@ template <int H, int VW, bool REL>
 __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, SpmvLds &L) {
   constexpr int CAP = kSpmvNnzCap;
   constexpr int NL = CAP / 64;
-  constexpr int U = 8 / VW;   // CSR entries per row with loads in flight together
+  // CSR entries per row with loads in flight together: a 7-point row in one
+  // group of single columns (an eighth, clamped gather would be overhead)
+  constexpr int U = VW == 1 ? 7 : 4;
   const int lane = threadIdx.x & 63;
   const int s = __builtin_amdgcn_readfirstlane(a.t.ch_sys[ch]);
   const int rs = a.t.sys_row[s];
