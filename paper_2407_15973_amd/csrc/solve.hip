@@ -540,6 +540,32 @@ struct Frag {
   }
 };
 
+// Sum over the 16 lanes of a DPP row, left in every lane of the row: pairs
+// within quads, then quads (quad permutations), then half-rows (half-row
+// mirror), then the two halves (row mirror). Each step adds the same two
+// partial sums in every lane of a pair, so all 16 lanes hold the same value.
+__device__ __forceinline__ int dpp_row_step(int v, int step) {
+  switch (step) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+  }
+}
+__device__ __forceinline__ float row16_sum(float v) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) v += __int_as_float(dpp_row_step(__float_as_int(v), st));
+  return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int lo = dpp_row_step(__double2loint(v), st), hi = dpp_row_step(__double2hiint(v), st);
+    v += __hiloint2double(hi, lo);
+  }
+  return v;
+}
+
 // A block of padded size 32 in symmetric storage (H00 and H01 as the first
 // 16-row tile of the full layout, H11 as a 16-column block after it): the
 // lane's fragments of both, and z = H r with the transpose of H01 standing
@@ -563,19 +589,17 @@ struct Sym32 {
     const double z0 = f0.dot(r32, r64, lane);             // rows 0..15: H00 r0 + H01 r1
     const double z1 = f1.dot(r32 + 16, r64 + 16, lane);   // rows 16..31: H11 r1
     // (H01^T r0)[4 s + kq] = sum over i of H01[i][4 s + kq] r0[i]: lane (i, kq)
-    // holds H01[i][4 s + kq] as k-step 4 + s of its first-tile fragment
+    // holds H01[i][4 s + kq] as k-step 4 + s of its first-tile fragment, and
+    // the 16 lanes of column class kq form one DPP row
     CT ri;
     if constexpr (P == P64) ri = r64[i];
     else ri = r32[i];
     CT t0 = f0.template value<4>() * ri, t1 = f0.template value<5>() * ri;
     CT t2 = f0.template value<6>() * ri, t3 = f0.template value<7>() * ri;
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1) {
-      t0 += __shfl_xor(t0, m, kWave);
-      t1 += __shfl_xor(t1, m, kWave);
-      t2 += __shfl_xor(t2, m, kWave);
-      t3 += __shfl_xor(t3, m, kWave);
-    }
+    t0 = row16_sum(t0);
+    t1 = row16_sum(t1);
+    t2 = row16_sum(t2);
+    t3 = row16_sum(t3);
     if (i < 4) tt[4 * i + kq] = (double)(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3);
     wave_lds_sync();
     if (lane < 16) {
