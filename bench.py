@@ -117,8 +117,8 @@ VERIFY = 3
 # profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
 # for the kernel sources they were measured on: reported when the digest of
 # those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "c12ea455a49ff405ec3bf560dffd58cb9340cdb59ea6355227ea5c0ac9018260",
-           "spmv": 228037080, "apply": 218782592}
+TRAFFIC = {"sources_sha256": "3e1c4737f01a854db289d5b692198efb2dbc88fa6d84f5af3fe7e87e2ac09663",
+           "spmv": 228009847, "apply": 218779252}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
