@@ -854,8 +854,8 @@ def main():
                     help="also run one 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload == "diff3d":
         args.N = args.N or 128
