@@ -257,7 +257,8 @@ int bjac_apply(const bjac_handle *h, int32_t which, const double *r, double *z, 
  * distinct, 1 <= m <= 8. Applies the low map only. Each block product runs on
  * the 16x16x4 matrix-core instructions: FP32 for FP32/BF16/FP16 blocks (the
  * FP32 copy of R, FP32 accumulation, then times the block scale in FP64),
- * FP64 for FP64 blocks. */
+ * FP64 for FP64 blocks. Returns BJAC_EINVAL for a handle with symmetric
+ * storage (BJAC_STORE_SYM). */
 int bjac_apply_multi(const bjac_handle *h, const double *R, double *Z, int32_t m, void *stream);
 
 /* ---- q = A p, the FP64 CSR product used by PCG ------------------------- */
@@ -322,7 +323,9 @@ int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t
                                 const bjac_batch_cfg *cfg, size_t *workspace_bytes);
 /* Returns BJAC_OK when every column converged, else BJAC_EBREAKDOWN if any
  * column broke down, else BJAC_NOT_CONVERGED. stats: iters = the largest
- * column count, relres = the largest column relres. Synchronises the stream. */
+ * column count, relres = the largest column relres. Synchronises the stream.
+ * Both calls return BJAC_EINVAL for a handle with symmetric storage
+ * (BJAC_STORE_SYM). */
 int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
                       const int32_t *sys_m, const double *b, double *x, const bjac_solve_opts *opts,
                       const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes,
