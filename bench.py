@@ -117,8 +117,8 @@ VERIFY = 3
 # profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
 # for the kernel sources they were measured on: reported when the digest of
 # those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "3e1c4737f01a854db289d5b692198efb2dbc88fa6d84f5af3fe7e87e2ac09663",
-           "spmv": 228009847, "apply": 218779252}
+TRAFFIC = {"sources_sha256": "9a901b9d12bda19f0a14b2342ad39b5fd41686db74bd984803b480846986e402",
+           "spmv": 228006256, "apply": 218779413}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 

@@ -1228,8 +1228,9 @@ static int bcollect(const BCtx &c, hipStream_t s, int32_t *col_iters, int32_t *c
 static int bprofile_run(const BCtx &c, int maxit, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int32_t *col_iters,
                         int32_t *col_status, double *col_relres, bjac_stats *stats) {
   hipEvent_t ev[5];
+  // timing-only events: no system-scope cache writeback and invalidation at each record
   for (auto &e : ev)
-    if (hipEventCreate(&e) != hipSuccess) return BJAC_EHIP;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return BJAC_EHIP;
   int32_t *active = nullptr;
   if (hipHostMalloc((void **)&active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return BJAC_EHIP;
   double t_spmv = 0.0, t_apply = 0.0, t_red = 0.0;

@@ -1858,8 +1858,11 @@ static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, cons
                         int chunk, int max_launches, hipStream_t s, PcgState &hs, int &launches, Prof &prof) {
   constexpr int EV = 4;  // events per iteration: spmv start, update/apply start, split point, end
   std::vector<hipEvent_t> ev((size_t)EV * chunk);
+  // timing-only events: no system-scope cache writeback and invalidation at
+  // each record, which would lengthen the bracketed kernel and cool the cache
+  // for the next one (the captured iterations have no events between kernels)
   for (auto &e : ev)
-    if (hipEventCreate(&e) != hipSuccess) return BJAC_EHIP;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return BJAC_EHIP;
   int rc = BJAC_OK;
   while (hs.status == ST_RUNNING && launches < max_launches) {
     const int it0 = hs.iter;
