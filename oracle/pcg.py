@@ -7,7 +7,7 @@ The paper takes PCG (Hestenes-Stiefel, cited in Sec. 3.2) without printing it;
 this is the textbook recurrence, x0 = 0 (Sec. 4.2). Readings:
   * stopping test ||r_j||_2 / ||r_0||_2 <= tol on the recursive residual,
     checked right after the r update; the iteration count is the number of x
-    updates (Sec. 4.2, "reduction tolerance of relative residual L2-norm");
+    updates (Sec. 4.2: the relative residual 2-norm stopping test);
   * the adaptive switch of Algorithms 3.2 / 3.3 is evaluated every time the
     preconditioner is applied, with the current recursive relres; the first
     application (to r_0) sees relres = +inf (so hl starts high and lh starts

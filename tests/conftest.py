@@ -10,13 +10,3 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long CPU replication runs, enabled with MPBJAC_SLOW=1")
-
-
-def pytest_collection_modifyitems(config, items):
-    if os.environ.get("MPBJAC_SLOW") == "1":
-        return
-    skip = pytest.mark.skip(reason="long replication run; set MPBJAC_SLOW=1")
-    for it in items:
-        if "slow" in it.keywords:
-            it.add_marker(skip)

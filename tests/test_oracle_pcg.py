@@ -206,10 +206,10 @@ def test_poly_bjac_polynomial_definition():
     np.testing.assert_allclose(OP.PolyBJAC(A, bp, k=2, exact=True)(r), Mk @ r, rtol=0, atol=1e-12)
 
 
-@pytest.mark.slow
 def test_paper_mode_const_replication():
     # Table 4.2 / Sec. 4.4.1: Diff3D-Const, 32 blocks, k = t = 2, tol 1e-10:
     # 148 (fp64) -> 165 (fp32 fMP). Partition, ordering and f are unstated, so soft (+-5%).
+    # About a minute on one core: the full-size pin of the FP32 paper mode.
     N = 128
     A = gen.diffusion3d(gen.kappa_const(N))
     bp = gen.uniform_blocks(A.n, A.n // 32)
@@ -234,3 +234,102 @@ def test_band_storage_at_unit_roundoff_keeps_iterations():
         band = OP.solve_bjac(A, bp, b, M=OP.BJAC(A, bp, tags, H=H, band=True), tol=1e-10)
         assert full.status == OP.CONVERGED and band.status == OP.CONVERGED
         assert abs(full.iters - band.iters) <= 1
+
+
+# ------------------------------------------- FP32 paper mode (low=True) pins
+# Sec. 3.2: in fMP every floating-point operation of M^-1(p_l) runs in p_l
+# (fp32): r is rounded to fp32 on entry (Algorithm 3.1), A's values and the
+# inverted diagonal are fp32 copies (the inversion 1/a_ii itself is set-up
+# work, done in fp64 and then rounded), and z is widened on exit.
+
+def test_poly_bjac_low_k_t_one_is_rounded_diagonal_scaling():
+    # k = t = 1: z = fp64(fp32(1/a_ii) * fp32(r)), one fp32 multiply per entry
+    rng = np.random.default_rng(21)
+    A = gen.diffusion3d(gen.kappa_loguniform((6, 6, 6), rng))
+    bp = gen.uniform_blocks(A.n, A.n // 4)
+    r = rng.uniform(-1, 1, A.n)
+    d = A.to_scipy().diagonal()
+    ref = (np.float32(1.0) * (1.0 / d).astype(np.float32) * r.astype(np.float32)).astype(np.float64)
+    got = OP.PolyBJAC(A, bp, k=1, t=1, low=True)(r)
+    assert got.dtype == np.float64
+    np.testing.assert_array_equal(got, ref)
+    # and it is not the fp64 scaling (the fp32 rounding is visible)
+    assert np.any(got != r / d)
+
+
+def _tiny_chain():
+    """1D tridiagonal SPD matrix of 6 rows in two blocks of 3, with entries and
+    a right-hand side that fp32 cannot represent exactly."""
+    n = 6
+    diag = np.array([3.1, 2.7, 3.3, 2.9, 3.7, 3.05])
+    off = np.array([-1.3, -0.7, -1.1, -0.9, -1.45])
+    i = np.arange(n)
+    A = gen._csr_from_coo(n, np.concatenate([i, i[1:], i[:-1]]), np.concatenate([i, i[:-1], i[1:]]),
+                          np.concatenate([diag, off, off]))
+    r = np.random.default_rng(23).uniform(-1, 1, n)
+    return A, np.array([0, 3, 6]), r
+
+
+def _scalar_chain(A, bp, r, k, t, residual_fp64=False, round_entry=True):
+    """Eq. 3-1 (k outer steps) with eq. 3-3's block solve (t point-Jacobi
+    sweeps from zero), one scalar operation at a time on numpy float32
+    scalars (each + - * correctly rounded to fp32), row sums in column order.
+    The flags produce the two plausible mistakes the test must tell apart."""
+    f32 = np.float32
+    n = A.n
+    rp, ci, va = A.row_ptr, A.col_idx, A.val
+    blk = np.searchsorted(bp, np.arange(n), side="right") - 1
+    dinv = [f32(1.0 / va[[k for k in range(rp[i], rp[i + 1]) if ci[k] == i][0]]) for i in range(n)]
+    v = [f32(x) if round_entry else np.float64(x) for x in r]
+
+    def rowsum(i, y, same_block):
+        acc = f32(0.0)
+        for kk in range(rp[i], rp[i + 1]):
+            j = ci[kk]
+            if same_block and blk[j] != blk[i]:
+                continue
+            acc = acc + f32(va[kk]) * y[j]
+        return acc
+
+    def dhat(w):
+        y = [dinv[i] * w[i] for i in range(n)]
+        for _ in range(t - 1):
+            y = [y[i] + dinv[i] * (w[i] - rowsum(i, y, True)) for i in range(n)]
+        return y
+
+    z = dhat(v)
+    for _ in range(k - 1):
+        if residual_fp64:
+            res = [f32(float(v[i]) - sum(float(va[kk]) * float(z[ci[kk]]) for kk in range(rp[i], rp[i + 1])))
+                   for i in range(n)]
+        else:
+            res = [v[i] - rowsum(i, z, False) for i in range(n)]
+        d = dhat(res)
+        z = [z[i] + d[i] for i in range(n)]
+    return np.array([float(x) for x in z])
+
+
+def test_poly_bjac_low_matches_scalar_fp32_chain():
+    A, bp, r = _tiny_chain()
+    for k, t in ((1, 2), (2, 1), (2, 2), (3, 3)):
+        got = OP.PolyBJAC(A, bp, k=k, t=t, low=True)(r)
+        np.testing.assert_array_equal(got, _scalar_chain(A, bp, r, k, t))
+    # the inputs separate the plausible mistakes: an fp64 residual r - A z,
+    # an unrounded r, or the fp64 evaluation all give other values
+    got = OP.PolyBJAC(A, bp, k=2, t=2, low=True)(r)
+    assert np.any(got != _scalar_chain(A, bp, r, 2, 2, residual_fp64=True))
+    assert np.any(got != _scalar_chain(A, bp, r, 2, 2, round_entry=False))
+    assert np.any(got != OP.PolyBJAC(A, bp, k=2, t=2, low=False)(r))
+
+
+def test_poly_bjac_low_exact_on_representable_values():
+    # 5-point Laplacian (diagonal 4: 1/4 exact, off-diagonals -1) and a dyadic
+    # right-hand side: every fp32 operation is exact, so the low mode equals
+    # the fp64 evaluation bit for bit
+    A = gen.poisson2d(8, 8)
+    bp = gen.uniform_blocks(A.n, 8)
+    r = np.random.default_rng(23).integers(-8, 9, A.n) / 8.0
+    for k, t in ((1, 2), (2, 2), (3, 2)):
+        lo = OP.PolyBJAC(A, bp, k=k, t=t, low=True)(r)
+        hi = OP.PolyBJAC(A, bp, k=k, t=t, low=False)(r)
+        np.testing.assert_array_equal(lo, hi)
