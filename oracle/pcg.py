@@ -99,6 +99,70 @@ def pcg(matvec, b, precond, tol, maxit, temporal=TEMPORAL_NONE, adp_tol=math.inf
     return res
 
 
+def pcg_single_reduction(matvec, b, precond, tol, maxit) -> Result:
+    """PCG with one reduction phase per iteration: the Chronopoulos-Gear
+    recurrence (Chronopoulos and Gear, J. Comput. Appl. Math. 25, 1989), which
+    in exact arithmetic produces the iterates of the textbook PCG above. Each
+    iteration forms u = M^-1 r and w = A u first, then takes the three inner
+    products (r, r), (r, u) and (w, u) together; the direction p and its image
+    s = A p are updated by the same recurrence, so A p is never formed:
+        gamma = (r, u), delta = (w, u), beta = gamma / gamma_old,
+        alpha = gamma / (delta - beta * gamma / alpha_old),
+        p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s
+    (beta = 0 and alpha = gamma / delta in the first iteration). The stopping
+    test and the iteration count are those of ``pcg`` (Sec. 4.2, x0 = 0)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    r0 = float(np.sqrt(r @ r))
+    res = Result(x, 0, CONVERGED, 0.0)
+    if r0 == 0.0:
+        return res
+    p = np.zeros_like(b)
+    s = np.zeros_like(b)
+    gamma_old = alpha_old = 0.0
+    for j in range(0, maxit + 1):
+        if j > 0:
+            relres = float(np.sqrt(r @ r)) / r0
+            res.history.append(relres)
+            res.iters, res.relres = j, relres
+            if relres <= tol:
+                res.status = CONVERGED
+                return res
+            if j == maxit:
+                break
+        u = precond(r)
+        w = matvec(u)
+        gamma = float(r @ u)
+        delta = float(w @ u)
+        if not (gamma > 0):
+            res.status = BREAKDOWN
+            return res
+        if j == 0:
+            beta, denom = 0.0, delta
+        else:
+            beta = gamma / gamma_old
+            denom = delta - beta * gamma / alpha_old
+        if not (denom > 0):
+            res.status = BREAKDOWN
+            return res
+        alpha = gamma / denom
+        p = u + beta * p
+        s = w + beta * s
+        x += alpha * p
+        r -= alpha * s
+        gamma_old, alpha_old = gamma, alpha
+    res.status = MAXIT
+    return res
+
+
+def solve_bjac_single_reduction(A, block_ptr, b, tags=None, tol=1e-10, maxit=5000, M=None) -> Result:
+    """Block-Jacobi PCG in the single-reduction (Chronopoulos-Gear) form."""
+    M = BJAC(A, block_ptr, tags) if M is None else M
+    S = A.to_scipy()
+    return pcg_single_reduction(lambda v: S @ v, b, M.low, tol, maxit)
+
+
 def true_relres(A, x, b) -> float:
     """||b - A x||_2 / ||b||_2 recomputed in FP64 (Sec. 4.5.1, true RelResNorm)."""
     S = A.to_scipy()
