@@ -1,29 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of mixed-precision block-Jacobi PCG on one MI355X.
 
-Workload: 3D 7-point variable-coefficient diffusion on a 128^3 grid
-(n = 2,097,152, nnz = 14,581,760), point coefficients 10**U(-2,2), contiguous
-row blocks of 32, RHS U[-1,1] (seed 0), x0 = 0, stop at ||r||/||b|| <= 1e-10.
-One step = block-Jacobi setup (extract, FP64 invert, features, round + pack)
-plus the PCG solve to 1e-10, with A and b already resident in HBM.
+Default workload (the largest single system): 3D anisotropic diffusion on a
+192^3 grid (n = 7,077,888, nnz = 49,324,032), K = diag(1e3, 1, 1) times a
+coefficient of 1e4 on 16 random subcubes and 1 elsewhere, contiguous row
+blocks of 48, RHS U[-1,1] (held-out seed 100), x0 = 0, stop at
+||r||/||b|| <= 1e-10 with an FP64 check of the true residual. One step =
+block-Jacobi setup (extract, FP64 invert, features, precision map, round +
+pack) plus the PCG solve, with A and b already resident in HBM.
 
-The headline value is the time to solution with the block inverses stored in
-FP16 (fMP), each block as its H00, H01 and H11 quarters (the inverse is
-symmetric); the same steps with FP64 storage are timed beside it. A profile
-pass times each kernel with HIP events on the stream it runs on and reports
-the dominant kernel against the 8 TB/s HBM roofline. The CPU oracle is timed
-on a bounded sample on the host.
+The headline value is the time to solution with the precision map the
+learned selector picks (the network is trained first, untimed, on labels the
+solver generates on the 2D Poisson and 3D log-uniform diffusion families);
+the per-block rule, fixed FP16 and FP64 maps are timed beside it over fewer
+steps. Every map stores each block's upper 16 x 16 quarters (the inverse is
+symmetric). Iteration counts are reported against the oracle's, stored by
+tests/golden/make_oracle_iters.py. A profile pass times each kernel with HIP
+events on the stream it runs on and reports the dominant kernel against the
+8 TB/s HBM roofline. The CPU oracle is timed on the host's cores. The 128^3
+log-uniform workload (blocks of 32) is timed as extra keys.
 
 Other workloads (each prints its own line of the same form):
+  --workload diff3d    128^3 log-uniform diffusion (10^U(-2,2)), blocks of
+                       32: FP16 vs FP64 maps, symmetric storage
   --workload batched   256 independent 7-point systems, edges U{32..96},
                        1-8 right-hand sides each, blocks from {16,32,48,64};
                        FP16 block storage vs FP64 (and FP16 band storage),
                        autotuned launch shape
   --workload aniso     160^3 anisotropic (1e3) diffusion with 1e4 jumps on
                        16 random subcubes, blocks of 48: per-block rule vs
-                       FP16 and FP64 storage
-  --workload selector  192^3 held-out anisotropic jump problem: learned
-                       selector (trained first, untimed) vs rule vs FP64
+                       FP16 and FP64 storage; --axis yz puts the strong axes
+                       across the row blocks (the paper's Ani(s) orientation)
   --workload rhd       synthetic radiation-diffusion-like systems at 128^3:
                        coupled 3T (eq. 4-3, 6.3M rows) and 1T, stored
                        inverses and paper mode, and a P_diag sweep (Sec. 4.5.2)
@@ -112,23 +119,26 @@ METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP6
 # restarts from the true residual (at most this many times) when it is above
 VERIFY = 3
 
-# HBM bytes per launch of the two per-iteration kernels of the default
-# workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
-# profiles/hbm_traffic_diff3d_128_b32.md (scaled by a 1 GiB copy). Valid only
-# for the kernel sources they were measured on: reported when the digest of
-# those sources matches, null otherwise.
-TRAFFIC = {"sources_sha256": "9a901b9d12bda19f0a14b2342ad39b5fd41686db74bd984803b480846986e402",
-           "spmv": 228006256, "apply": 218779413}
+# HBM bytes per launch of the per-iteration kernels, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs (profiles/, scaled by a 1 GiB copy), keyed by
+# workload and kernel. Valid only for the kernel sources they were measured
+# on: reported when the digest of those sources matches, null otherwise.
+TRAFFIC = {}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
-def measured_traffic(kernel):
+def sources_digest():
     import hashlib
     h = hashlib.sha256()
     for name in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2407_15973_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    return TRAFFIC.get(kernel) if h.hexdigest() == TRAFFIC["sources_sha256"] else None
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    e = TRAFFIC.get(key)
+    return e[1] if e is not None and e[0] == sources_digest() else None
 
 
 def stream_ceilings(dev, gib=1):
@@ -237,7 +247,7 @@ def bench_diff3d(args):
     iter_us16 = solve16 * 1e3 / max(1, r16.iters)
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["gbs"] / HBM_PEAK_GBS,
-                "traffic": measured_traffic(dom) if args.N == 128 else None, "kernel": f"{dom}_kernel",
+                "traffic": measured_traffic(f"diff3d_128:{dom}") if args.N == 128 else None, "kernel": f"{dom}_kernel",
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     pair_gbs = iter_bytes / ((kern["spmv"]["avg_us"] + kern["apply"]["avg_us"]) * 1e-6) / 1e9
 
@@ -464,7 +474,93 @@ def train_selector(dev):
     return sel.train(np.concatenate(F), np.concatenate(Y), steps=400, lr=3e-3)
 
 
+def oracle_golden(workload, pmap):
+    """The oracle's iteration count and sampled solution at a benchmark size,
+    as stored by tests/golden/make_oracle_iters.py (which calls only oracle/);
+    None when not stored."""
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_iters_{workload}_{pmap}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def x_err_vs_oracle(g, x):
+    """||x - x_oracle|| / ||x_oracle|| on the stored oracle run's sample rows
+    (None when no run is stored)."""
+    import numpy as np
+    if g is None:
+        return None
+    rows = np.asarray(g["sample_rows"], dtype=np.int64)
+    xo = np.asarray(g["x_sample"])
+    return float(np.linalg.norm(x[rows] - xo) / np.linalg.norm(xo))
+
+
+def host_cores():
+    """Physical cores of the host (lscpu: cores per socket x sockets), else
+    the logical CPU count."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            kv[k.strip()] = v.strip()
+        return int(kv["Core(s) per socket"]) * int(kv["Socket(s)"]), kv.get("Model name", "")
+    except Exception:
+        return os.cpu_count() or 1, ""
+
+
+def cpu_baseline_full(p, iters_total, reps=3, iters_sample=3):
+    """The oracle as it stands, on the host with its thread pools set to the
+    host's core count: the FP64 setup of every block with FP16 storage, timed
+    once, then `reps` runs of `iters_sample` PCG iterations of the same
+    problem; the solve is the median time per iteration times the full
+    solve's iteration count. `cores` is the CPU time the oracle used over its
+    wall time (its NumPy/SciPy work is mostly single-threaded)."""
+    import resource
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pcg as OP
+    from oracle import precision as OPr
+    ncores, model = host_cores()
+
+    def cpu_s():
+        r = resource.getrusage(resource.RUSAGE_SELF)
+        return r.ru_utime + r.ru_stime
+
+    with threadpool_limits(limits=ncores):
+        c0, t0 = cpu_s(), time.perf_counter()
+        nb = len(p.block_ptr) - 1
+        M = OP.BJAC(p.A, p.block_ptr, np.full(nb, OPr.FP16, np.uint8))
+        S = p.A.to_scipy()
+        t1 = time.perf_counter()
+        per = []
+        for _ in range(reps):
+            ta = time.perf_counter()
+            res = OP.pcg(lambda v: S @ v, p.b, M.low, 0.0, iters_sample)
+            per.append((time.perf_counter() - ta) / max(1, res.iters))
+        c1, t2 = cpu_s(), time.perf_counter()
+    setup_s, iter_s = t1 - t0, float(np.median(per))
+    used = (c1 - c0) / max(1e-9, t2 - t0)
+    return {"value": 1e3 * (setup_s + iter_s * iters_total), "unit": "ms", "cores": max(1, round(used)),
+            "kind": "oracle", "host_cores": ncores, "host_cpu": model, "threads_allowed": ncores,
+            "setup_ms": 1e3 * setup_s, "solve_ms": 1e3 * iter_s * iters_total, "ms_per_iter": 1e3 * iter_s,
+            "sample": f"oracle setup of all {nb} blocks (Cholesky inverse, FP16 storage) timed once "
+                      f"({setup_s:.1f} s); PCG iterations timed in {reps} runs of {iters_sample} "
+                      f"(median {1e3 * iter_s:.0f} ms per iteration) and multiplied by the full solve's "
+                      f"{iters_total} iterations; CPU time / wall time {used:.2f}"}
+
+
 def bench_policies(args):
+    """Precision maps on one large anisotropic jump-coefficient problem, every
+    map with symmetric storage of the block inverses. ``selector`` (the
+    default workload): the held-out 192^3 problem, the learned selector
+    (trained first, untimed, on labels from the solver's own runs) timed over
+    the requested steps, the per-block rule, fixed FP16 and FP64 beside it over
+    fewer steps; ``aniso``: the 160^3 problem, the rule as the headline."""
     import numpy as np
     import torch
 
@@ -473,20 +569,31 @@ def bench_policies(args):
 
     dev = "cuda:0"
     selector_mode = args.workload == "selector"
+    gkey = "heldout_192" if selector_mode else "aniso_160"
     log("building the workload")
-    p = gen.config5_eval(seed=100, N=args.N) if selector_mode else gen.config3(seed=0, N=args.N)
+    p = (gen.config5_eval(seed=100, N=args.N) if selector_mode else
+         gen.aniso_jump_problem(seed=0, N=args.N, name="diff3d_aniso1e3yz_jump1e4", ratio=1e3, strong="yz")
+         if args.axis == "yz" else gen.config3(seed=0, N=args.N))
+    if args.axis == "yz":
+        gkey = None
     n, nnz, nb = p.A.n, p.A.nnz, len(p.block_ptr) - 1
     A = mb.DeviceCSR(p.A, dev)
     b = torch.as_tensor(p.b, device=dev)
     solver = mb.Solver(n, dev)
-    pols = {"fp64": mb.Policy(mode=mb.UNIFORM), "fp16": mb.Policy(mode=mb.FIXED, low=mb.FP16),
-            "rule": mb.Policy(mode=mb.RULE)}
+    sym = dict(storage=mb.STORE_SYM)
+    pols = {"fp64": mb.Policy(mode=mb.UNIFORM, **sym), "fp16": mb.Policy(mode=mb.FIXED, low=mb.FP16, **sym),
+            "rule": mb.Policy(mode=mb.RULE, **sym)}
     head = "rule"
     if selector_mode:
         log("training the selector (untimed)")
-        s = train_selector(dev)
-        pols = {"fp64": pols["fp64"], "rule": pols["rule"], "learned": mb.Policy(mode=mb.LEARNED, mlp_blob=s.blob)}
+        t0 = time.perf_counter()
+        sel = train_selector(dev)
+        log(f"trained in {time.perf_counter() - t0:.1f} s")
+        pols = {"learned": mb.Policy(mode=mb.LEARNED, mlp_blob=sel.blob, **sym), **pols}
         head = "learned"
+    else:
+        pols = {"rule": pols["rule"], "fp16": pols["fp16"], "fp64": pols["fp64"]}
+    cmp_steps = min(args.steps, args.cmp_steps)
 
     def step(policy, profile=False):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -497,33 +604,42 @@ def bench_policies(args):
         e2.record()
         return M, res, (e0, e1, e2)
 
-    rows = {}
-    for name, pol in pols.items():
-        for _ in range(args.warmup):
-            step(pol)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        runs = [step(pol) for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        M, res, ev = runs[-1]
-        info = M.info()
-        rows[name] = {"ms_per_step": ms, "iters": res.iters, "status": res.status, "restarts": res.restarts,
-                      "true_relres_device": res.true_relres,
-                      "setup_ms": float(np.median([r[2][0].elapsed_time(r[2][1]) for r in runs])),
-                      "solve_ms": float(np.median([r[2][1].elapsed_time(r[2][2]) for r in runs])),
-                      "blocks_per_prec": info["blocks_per_prec"], "low_bytes": info["low_bytes"],
-                      "x": res.x}
-        log(f"{name}: {ms:.1f} ms/step, {res.iters} iterations, map {info['blocks_per_prec']}")
     S = p.A.to_scipy()
     bn = float(np.linalg.norm(p.b))
-    for r in rows.values():
-        r["true_relres"] = float(np.linalg.norm(p.b - S @ r.pop("x").cpu().numpy()) / bn)
+    g64 = oracle_golden(gkey, "fp64") if gkey else None
+    rows = {}
+    for name, pol in pols.items():
+        k = args.steps if name == head else cmp_steps
+        for _ in range(args.warmup if name == head else 1):
+            step(pol)
+        log(f"timing {k} steps, {name}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runs = [step(pol) for _ in range(k)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / k
+        M, res, ev = runs[-1]
+        info = M.info()
+        x = res.x.cpu().numpy()
+        g = oracle_golden(gkey, name) if (gkey and name != "learned") else None
+        rows[name] = {"ms_per_step": ms, "steps": k, "iters": res.iters, "status": res.status,
+                      "restarts": res.restarts, "true_relres_device": res.true_relres,
+                      "true_relres": float(np.linalg.norm(p.b - S @ x) / bn),
+                      "setup_ms": float(np.median([r[2][0].elapsed_time(r[2][1]) for r in runs])),
+                      "solve_ms": float(np.median([r[2][1].elapsed_time(r[2][2]) for r in runs])),
+                      "blocks_per_prec": info["blocks_per_prec"], "stored_bytes": info["low_bytes"],
+                      "iters_oracle_same_map": g["iters"] if g else None,
+                      "delay_vs_oracle_fp64": res.iters - g64["iters"] if g64 else None,
+                      "x_rel_err_vs_oracle_fp64": x_err_vs_oracle(g64, x)}
+        log(f"{name}: {ms:.1f} ms/step, {res.iters} iterations (oracle FP64 "
+            f"{g64['iters'] if g64 else '-'}), map {info['blocks_per_prec']}")
+        del runs, M
 
     log("profile pass")
     M, rp, _ = step(pols[head], profile=True)
     info = M.info()
-    kb = {"spmv": spmv_bytes(n, nnz, index_bytes(p.A)), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
+    ib = index_bytes(p.A)
+    kb = {"spmv": spmv_bytes(n, nnz, ib), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp.kernel_ms[name]
@@ -532,25 +648,82 @@ def bench_policies(args):
                       "gbs": kb[name] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None}
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     dk = kern[dom]
+    iter_bytes = kb["spmv"] + kb["apply"]
+    pair_gbs = iter_bytes / ((kern["spmv"]["avg_us"] + kern["apply"]["avg_us"]) * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": f"{dom}_kernel",
-                "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(f"{gkey}:{dom}") if gkey else None,
+                "kernel": f"{dom}_kernel", "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(p, rows[head]["iters"])
+        log("cpu baseline (oracle on the host cores)")
+        cpu = cpu_baseline_full(p, rows[head]["iters"])
     hv = rows[head]
+    del M, A, b, solver
+    torch.cuda.empty_cache()
+    extra = bench_config2_keys(args) if (selector_mode and not args.no_config2) else None
+    ceil = stream_ceilings(dev)
     return {
         "metric": METRIC, "value": hv["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "apply_arith": "per-block FP64/FP32/FP16 storage, f32 accumulation for reduced blocks",
-        "config": {"workload": f"{p.name}", "n": n, "nnz": nnz, "blocks": nb, "block_rows": 48,
-                   "precision_map": head, "tol": p.tol, "seed": 100 if selector_mode else 0},
-        "policies": rows, "speedup_vs_fp64": rows["fp64"]["ms_per_step"] / hv["ms_per_step"],
-        "delay_iters": hv["iters"] - rows["fp64"]["iters"],
-        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu,
+        "apply_arith": "per-block FP64/FP32/FP16-stored block inverses (symmetric storage), "
+                       "f32 accumulation for reduced blocks",
+        "config": {"workload": p.name, "n": n, "nnz": nnz, "blocks": nb, "block_rows": 48,
+                   "precision_map": head, "storage": "symmetric (upper 16x16 quarters of each block)",
+                   "tol": p.tol, "seed": 100 if selector_mode else 0},
+        "iters": hv["iters"], "iters_oracle_fp64": g64["iters"] if g64 else None,
+        "delay_vs_oracle_fp64": hv["delay_vs_oracle_fp64"],
+        "true_relres": hv["true_relres"], "setup_ms": hv["setup_ms"], "solve_ms": hv["solve_ms"],
+        "speedup_vs_fp64": rows["fp64"]["ms_per_step"] / hv["ms_per_step"],
+        "speedup_vs_rule": rows["rule"]["ms_per_step"] / hv["ms_per_step"],
+        "speedup_vs_fp16": rows["fp16"]["ms_per_step"] / hv["ms_per_step"],
+        "policies": rows, "comparison_steps": cmp_steps,
+        "us_per_iter": hv["solve_ms"] * 1e3 / max(1, hv["iters"]), "bytes_per_iter": iter_bytes,
+        "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
+        "kernels": kern, "roofline": roofline, "cpu_baseline": cpu, "stream_ceilings_gbs": ceil,
+        "diff3d_128": extra,
     }
+
+
+def bench_config2_keys(args):
+    """The 128^3 log-uniform workload (blocks of 32) as extra keys of the
+    default line: FP16 and FP64 maps in symmetric storage, a few steps each,
+    iterations against the oracle's."""
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    log("128^3 log-uniform workload (extra keys)")
+    p = gen.config2(seed=0, N=128, b=32)
+    A = mb.DeviceCSR(p.A, dev)
+    b = torch.as_tensor(p.b, device=dev)
+    solver = mb.Solver(p.A.n, dev)
+    out = {"workload": p.name, "n": p.A.n, "nnz": p.A.nnz, "blocks": len(p.block_ptr) - 1}
+    S = p.A.to_scipy()
+    for name, pol in (("fp16", mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM)),
+                      ("fp64", mb.Policy(mode=mb.UNIFORM, storage=mb.STORE_SYM))):
+        def one():
+            M = mb.BlockJacobi(A, p.block_ptr, pol)
+            return solver.solve(A, M, b, tol=p.tol, maxit=p.maxit, verify=VERIFY)
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            res = one()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / 5
+        x = res.x.cpu().numpy()
+        g = oracle_golden("diff3d_128", name)
+        out[name] = {"ms_per_step": ms, "steps": 5, "iters": res.iters,
+                     "true_relres": float(np.linalg.norm(p.b - S @ x) / np.linalg.norm(p.b)),
+                     "iters_oracle_same_map": g["iters"] if g else None,
+                     "x_rel_err_vs_oracle_same_map": x_err_vs_oracle(g, x)}
+        log(f"128^3 {name}: {ms:.1f} ms/step, {res.iters} iterations")
+    out["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp16"]["ms_per_step"]
+    return out
 
 
 # ------------------------------------------------ band-truncated storage
@@ -629,7 +802,7 @@ def bench_band(args):
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     dk = kern[dom]
     # the SpMV is the same kernel as in the default workload: its measured traffic applies
-    traffic = measured_traffic(dom) if (N == 128 and dom == "spmv") else None
+    traffic = measured_traffic("diff3d_128:spmv") if (N == 128 and dom == "spmv") else None
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": f"{dom}_kernel",
                 "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
@@ -846,8 +1019,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--N", type=int, default=None, help="grid edge (diff3d 128, aniso 160, selector 192)")
-    ap.add_argument("--workload", default="diff3d",
+    ap.add_argument("--workload", default="selector",
                     choices=("diff3d", "batched", "aniso", "selector", "paper", "rhd", "band"))
+    ap.add_argument("--axis", default="x", choices=("x", "yz"),
+                    help="aniso: strong axis along x (inside the row blocks) or y and z (the paper's Ani(s))")
+    ap.add_argument("--cmp-steps", type=int, default=3,
+                    help="selector / aniso: timed steps of each comparison map (the headline map takes --steps)")
+    ap.add_argument("--no-config2", action="store_true", help="selector: skip the 128^3 extra keys")
     ap.add_argument("--nsys", type=int, default=256, help="batched: number of systems")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate", action="store_true",

@@ -8,8 +8,12 @@
  * point allocates device memory: the caller passes workspaces whose sizes the
  * *_query calls report. Work is enqueued on the caller's HIP stream (passed
  * as void*, NULL = the default stream); calls return after it is enqueued
- * unless stated otherwise. No C++ exception crosses this boundary. Handles
- * are not thread-safe; distinct handles may be used from distinct threads.
+ * unless stated otherwise. No C++ exception crosses this boundary.
+ * Threads: one handle must not be used by two threads at once (a solve
+ * caches its captured iteration graph and capture stream in the handle);
+ * distinct handles, each with its own workspaces, may be used from distinct
+ * threads at the same time. The library's only shared state is a cache of
+ * per-(kernel, device) occupancy figures, filled under a lock.
  *
  * Method (arXiv 2407.15973, "Mixed Precision Block-Jacobi Preconditioner"):
  *   Sec. 3.1, eq. 3-1 with one outer step: M^-1 = D_b^-1, the inverse of the
@@ -35,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MPBJAC_ABI_VERSION 1
+#define MPBJAC_ABI_VERSION 2
 #define BJAC_MAX_BLOCK 64        /* largest diagonal block (rows) */
 #define BJAC_NFEAT 16            /* block features per block */
 #define BJAC_MLP_NPARAM 5443     /* W1[64,16] b1[64] W2[64,64] b2[64] W3[3,64] b3[3] */
@@ -88,14 +92,15 @@ typedef enum {
  * point that takes a handle (bjac_apply, bjac_apply_multi, pcg_solve,
  * pcg_solve_batched); the multi-column products then run on the vector units
  * instead of the matrix cores.
- * SYM: the same inverses as FULL in three quarters of its bytes for blocks of
- * padded size 32 (not in the paper). The inverse H of an SPD block is
- * symmetric, so of its 16 x 16 quarters H00, H01, H10, H11 only H00, H01 and
- * H11 are stored, with FULL's scale and rounding, and the application uses the
- * transpose of H01 for H10. The computed FP64 inverse is symmetric up to its
- * own rounding (about one unit in the last place of FP64, far below every
- * storage format's rounding), so the application matches FULL's to within the
- * accumulation's rounding. Blocks of other padded sizes are stored as FULL.
+ * SYM: the same inverses as FULL in fewer bytes (not in the paper). The
+ * inverse H of an SPD block is symmetric, so of its 16 x 16 quarters H_IJ
+ * only those with I <= J are stored, with FULL's scale and rounding, and the
+ * application uses the transpose of H_JI for H_IJ below the diagonal. A block
+ * of padded size 32, 48, 64 keeps 3/4, 2/3, 5/8 of FULL's bytes; blocks of 16
+ * are stored as FULL. The computed FP64 inverse is symmetric up to its own
+ * rounding (about one unit in the last place of FP64, far below every storage
+ * format's rounding), so the application matches FULL's to within the
+ * accumulation's rounding.
  * SYM handles serve bjac_apply, bjac_get_block (which returns the mirrored
  * block) and pcg_solve; bjac_apply_multi and pcg_solve_batched return
  * BJAC_EINVAL for them. */
@@ -161,7 +166,25 @@ typedef struct {
                                     exceeds tol, replace r by b - A x and
                                     restart CG (p = z), at most `verify` times
                                     (then BJAC_NOT_CONVERGED). Graph mode only. */
+  int32_t variant;               /* bjac_pcg_variant                           */
+  int32_t reserved;              /* 0                                          */
 } bjac_solve_opts;
+
+/* PCG recurrences (both produce the same iterates in exact arithmetic):
+ * TEXTBOOK: Hestenes-Stiefel as the paper uses it (Sec. 3.2): per iteration
+ *   q = A p with (p, q), then x, r updated, z = M^-1 r with (r, r), (r, z):
+ *   two reduction phases.
+ * SINGLE_REDUCTION: the Chronopoulos-Gear recurrence (not in the paper):
+ *   x, r, p and s = A p updated from the last dots, u = M^-1 r, then w = A u
+ *   with (r, r), (r, u), (w, u) taken together: one reduction phase, and the
+ *   product gathers only u at the neighbouring rows. The convergence test
+ *   and the iteration count are the textbook ones. Serves stored-inverse
+ *   handles without the adaptive switch (temporal or paper-mode handles:
+ *   BJAC_EINVAL). */
+typedef enum {
+  BJAC_PCG_TEXTBOOK = 0,
+  BJAC_PCG_SINGLE_REDUCTION = 1
+} bjac_pcg_variant;
 
 typedef struct {
   int32_t iters;                 /* x updates performed                        */
@@ -305,7 +328,7 @@ int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *
  * then column. opts: tol, maxit, chunk (iterations per captured graph) are
  * used, and profile (eager launches, kernel times in stats->spmv_ms,
  * apply_ms and update_ms = the per-system reductions); relres_hist and
- * high_hist are ignored. */
+ * high_hist are ignored; variant must be BJAC_PCG_TEXTBOOK. */
 typedef struct {
   int32_t chunk_rows;   /* rows per matrix-vector chunk (>= 64; 0 = 128)      */
   int32_t wg_per_cu;    /* workgroups of 256 threads per compute unit in the

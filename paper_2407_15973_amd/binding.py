@@ -21,6 +21,7 @@ FP64, FP32, BF16, FP16 = 0, 1, 2, 3
 UNIFORM, FIXED, RULE, LEARNED, EXPLICIT = 0, 1, 2, 3, 4
 TEMPORAL_NONE, TEMPORAL_HL, TEMPORAL_LH = 0, 1, 2
 STORE_FULL, STORE_BAND, STORE_SYM = 0, 1, 2
+PCG_TEXTBOOK, PCG_SINGLE_REDUCTION = 0, 1
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 MLP_NPARAM = 5443
 MLP_NBLOB = MLP_NPARAM + 32
@@ -57,7 +58,7 @@ class bjac_info(C.Structure):
 class bjac_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("relres_hist", C.c_void_p), ("high_hist", C.c_void_p), ("profile", C.c_int32),
-                ("verify", C.c_int32)]
+                ("verify", C.c_int32), ("variant", C.c_int32), ("reserved", C.c_int32)]
 
 
 class bjac_stats(C.Structure):
@@ -197,7 +198,7 @@ class Policy:
     d16: float = 1.0
     mlp_blob: object = None          # device float tensor [MLP_NBLOB]
     explicit_tags: object = None     # numpy uint8 [nb]
-    storage: int = STORE_FULL        # STORE_BAND: band-truncated inverses; STORE_SYM: symmetric blocks of 32
+    storage: int = STORE_FULL        # STORE_BAND: band-truncated inverses; STORE_SYM: upper quarters of blocks of 32-64
     band_rtol: float = 0.0           # <= 0: each block's unit roundoff
 
     def c(self):
@@ -331,7 +332,7 @@ class Solver:
         self.compact_index = compact_index
 
     def solve(self, A: DeviceCSR, M: BlockJacobi, b, tol=1e-10, maxit=5000, chunk=16, history=False, x=None,
-              raise_on_error=True, profile=False, verify=0) -> SolveResult:
+              raise_on_error=True, profile=False, verify=0, variant=PCG_TEXTBOOK) -> SolveResult:
         torch = _torch()
         if self.compact_index:
             nbytes = C.c_size_t()
@@ -342,7 +343,8 @@ class Solver:
         rh = torch.empty(maxit, dtype=torch.float64, device=b.device) if history else None
         hh = torch.zeros(maxit + 1, dtype=torch.uint8, device=b.device) if history else None
         opts = bjac_solve_opts(tol, maxit, chunk, rh.data_ptr() if rh is not None else None,
-                               hh.data_ptr() if hh is not None else None, 1 if profile else 0, int(verify))
+                               hh.data_ptr() if hh is not None else None, 1 if profile else 0, int(verify),
+                               int(variant), 0)
         st = bjac_stats()
         rc = load().pcg_solve(C.byref(A.c), M.h, _ptr(b), _ptr(x), C.byref(opts), _ptr(self.ws),
                               self.ws.numel(), C.byref(st), _stream())

@@ -16,6 +16,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -925,15 +927,23 @@ static void split_cost(const std::vector<double> &cost, int W, std::vector<int32
   }
 }
 
+// compute units of the current device and resident workgroups of the batched
+// SpMV, queried once per device under a lock (handles may be used from
+// several threads)
+static std::mutex g_occ_mu;
+
 static int cu_count() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                               hipSuccess || cus < 1)
-      cus = 256;
+  static std::map<int, int> cus_of;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  auto it = cus_of.find(dev);
+  if (it == cus_of.end()) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    it = cus_of.emplace(dev, cus).first;
   }
-  return cus;
+  return it->second;
 }
 
 // workgroups for `units` chunks: a multiple of 8 (XCD-ordered wave slots), at
@@ -949,13 +959,19 @@ static int bgrid(int units, int wg_per_cu) {
 // workgroups of the SpMV that fit on one compute unit at once: its grid is
 // one resident round, so every wave of an XCD sweeps the same window
 static int spmv_resident(int ilp) {
-  static int occ[3] = {0, 0, 0};
-  int &o = occ[ilp == 1 ? 1 : 2];
-  if (!o) {
-    const void *k = ilp == 1 ? (const void *)bspmv_kernel<1> : (const void *)bspmv_kernel<2>;
+  static std::map<std::pair<int, int>, int> occ;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 2;
+  const int key = ilp == 1 ? 1 : 2;
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  auto it = occ.find({dev, key});
+  if (it == occ.end()) {
+    int o = 0;
+    const void *k = key == 1 ? (const void *)bspmv_kernel<1> : (const void *)bspmv_kernel<2>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, 256, 0) != hipSuccess || o < 1) o = 2;
+    it = occ.emplace(std::make_pair(dev, key), o).first;
   }
-  return o;
+  return it->second;
 }
 
 struct BWs {
@@ -1231,11 +1247,10 @@ static int bprofile_run(const BCtx &c, int maxit, hipStream_t s, hipEvent_t e0, 
   // timing-only events: no system-scope cache writeback and invalidation at each record
   for (auto &e : ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return BJAC_EHIP;
-  int32_t *active = nullptr;
-  if (hipHostMalloc((void **)&active, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return BJAC_EHIP;
+  int32_t active_h = 1;  // running columns, read back after every iteration
+  int32_t *active = &active_h;
   double t_spmv = 0.0, t_apply = 0.0, t_red = 0.0;
   int n_it = 0, rc = BJAC_OK;
-  *active = 1;
   if (hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     rc = BJAC_EHIP;
@@ -1265,7 +1280,6 @@ static int bprofile_run(const BCtx &c, int maxit, hipStream_t s, hipEvent_t e0, 
     t_red += b + f;
     ++n_it;
   }
-  (void)hipHostFree(active);
   for (auto &e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
   MPB_HIP(hipEventRecord(e1, s));
@@ -1306,7 +1320,7 @@ extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_
                                  const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes,
                                  int32_t *col_iters, int32_t *col_status, double *col_relres, bjac_stats *stats,
                                  void *stream) {
-  if (!opts) return BJAC_EINVAL;
+  if (!opts || opts->variant != BJAC_PCG_TEXTBOOK) return BJAC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   BCtx c;
   int rc = bctx_make(A, M, nsys, sys_row, sys_m, b, x, opts->tol, opts->maxit, cfg, workspace, workspace_bytes, s, c);
@@ -1340,8 +1354,8 @@ extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_
   (void)hipStreamDestroy(cs);
   if (ce != hipSuccess) return BJAC_EHIP;
 
-  int32_t *active = nullptr;
-  MPB_HIP(hipHostMalloc((void **)&active, sizeof(int32_t), hipHostMallocDefault));
+  int32_t active_h = 0;  // running columns, read back after every replay
+  int32_t *active = &active_h;
   int launches = 0;
   const int max_launches = opts->maxit / chunk + 2;
   hipError_t le = hipMemcpyAsync(active, c.w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s);
@@ -1353,7 +1367,6 @@ extern "C" int pcg_solve_batched(const bjac_csr *A, const bjac_handle *M, int32_
     if (le == hipSuccess) le = hipStreamSynchronize(s);
   }
   (void)hipGraphExecDestroy(ge);
-  (void)hipHostFree(active);
   if (le != hipSuccess) return BJAC_EHIP;
   MPB_HIP(hipEventRecord(e1, s));
   MPB_HIP(hipEventSynchronize(e1));

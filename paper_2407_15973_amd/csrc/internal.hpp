@@ -58,13 +58,20 @@ struct DevMap {
   const double *scale;
   const uint8_t *tag;
   const uint8_t *w = nullptr;   // band storage: diagonals 0..w[k] kept; null: full blocks
-  int32_t sym = 0;              // symmetric storage of the blocks of padded size 32
+  int32_t sym = 0;              // symmetric storage of the blocks of padded size 32..64
 };
 
-// Symmetric storage of a block of padded size 32: its first 16-row tile in
-// the full layout (H00 and H01), then H11 as the 16-row tile of a 16-column
-// block. Entries per block (elements of the block's format).
-constexpr int kSym32Elems = 64 * 8 + 64 * 4;
+// Symmetric storage of a block of padded size B = 16 m (the inverse of an SPD
+// block is symmetric): row tile I keeps only its columns 16 I .. B-1, stored
+// as the single 16-row tile of a block of padded size B - 16 I in the full
+// layout, strips back to back (I = 0 first). The quarters below the diagonal
+// are the transposes of stored ones. Entries per block, and where strip I
+// starts (elements of the block's format); for B = 16 this is full storage.
+__host__ __device__ constexpr int sym_elems(int B) { return 128 * (B / 16) * (B / 16 + 1); }
+__host__ __device__ constexpr int sym_strip_off(int B, int I) { return 256 * (I * (B / 16) - I * (I - 1) / 2); }
+static_assert(sym_elems(32) == 768 && sym_strip_off(32, 1) == 512 && sym_elems(48) == 1536 &&
+                  sym_elems(64) == 2560 && sym_strip_off(64, 3) == 256 * 9 && sym_elems(16) == 256,
+              "symmetric layout sizes");
 
 }  // namespace mpb
 
@@ -105,9 +112,10 @@ struct bjac_handle {
   std::vector<double> h_scale_lo;
   int32_t hist[4] = {0, 0, 0, 0};
   int64_t low_bytes = 0, high_bytes = 0;
-  // cached PCG graph
+  // cached PCG graph and the stream it is captured on
   hipGraphExec_t gexec = nullptr;
   std::vector<uintptr_t> gkey;
+  hipStream_t cap_stream = nullptr;
   // paper-mode BJAC(k, t) (kind 1): no stored inverses; k outer steps with t
   // point-Jacobi sweeps inside each block, in FP32 (low) or FP64
   int32_t kind = 0;

@@ -41,7 +41,7 @@ struct SetupArgs {
   double band_rtol;       // <= 0: the format's unit roundoff
   const uint8_t *w_lo;    // packing: band store of the low map when non-null
   const uint8_t *w_hi;    // packing: band store of the all-FP64 map when non-null
-  int32_t sym;            // packing: symmetric storage of the blocks of padded size 32
+  int32_t sym;            // packing: symmetric storage of the blocks of padded size 32..64
 };
 
 constexpr double kDomCap = 1e8;
@@ -94,40 +94,49 @@ __device__ __forceinline__ void store_rows(uint8_t *dst, const double (&row)[B],
   }
 }
 
-// Symmetric storage of a block of padded size 32: rows 0..15 (H00, H01) as
-// the first 16-row tile of the full layout, the columns 16..31 of rows 16..31
-// (H11) as the 16-row tile of a 16-column block after it; rows 16..31 store
-// nothing of columns 0..15, the transpose of H01.
-template <int P>
-__device__ __forceinline__ void store_rows_sym32(uint8_t *dst, const double (&row)[32], int lane, double inv_s) {
-  if (lane < 16) {
-    store_rows<32, P>(dst, row, lane, inv_s);
-  } else {
-    double h[16];
+// Symmetric storage of a block of padded size B (32, 48 or 64): the lane of
+// row i (row tile I = i / 16) stores the columns 16 I .. B-1 of its row as row
+// i % 16 of the single row tile of a block of padded size B - 16 I, at strip
+// I's offset; the columns left of 16 I are the transposes of entries stored by
+// the rows above.
+template <int B, int P, int I>
+__device__ __forceinline__ void store_sym_strip(uint8_t *dst, const double (&row)[B], int lane, double inv_s) {
+  constexpr int W = B - 16 * I;
+  double h[W];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) h[j] = row[16 + j];
-    store_rows<16, P>(dst + 64 * 8 * prec_bytes(P), h, lane - 16, inv_s);
+  for (int j = 0; j < W; ++j) h[j] = row[16 * I + j];
+  store_rows<W, P>(dst + (int64_t)sym_strip_off(B, I) * prec_bytes(P), h, lane - 16 * I, inv_s);
+}
+
+template <int B, int P>
+__device__ __forceinline__ void store_rows_sym(uint8_t *dst, const double (&row)[B], int lane, double inv_s) {
+  switch (lane >> 4) {
+    case 0: store_sym_strip<B, P, 0>(dst, row, lane, inv_s); break;
+    case 1: store_sym_strip<B, P, 1>(dst, row, lane, inv_s); break;
+    case 2:
+      if constexpr (B >= 48) store_sym_strip<B, P, 2>(dst, row, lane, inv_s);
+      break;
+    default:
+      if constexpr (B >= 64) store_sym_strip<B, P, 3>(dst, row, lane, inv_s);
+      break;
   }
 }
 
-__device__ __forceinline__ void store_block_sym32(uint8_t *dst, int prec, const double (&row)[32], int lane,
-                                                  double inv_s) {
-  switch (prec) {
-    case P64: store_rows_sym32<P64>(dst, row, lane, 1.0); break;
-    case P32: store_rows_sym32<P32>(dst, row, lane, inv_s); break;
-    case PBF16: store_rows_sym32<PBF16>(dst, row, lane, inv_s); break;
-    default: store_rows_sym32<P16>(dst, row, lane, inv_s); break;
-  }
-}
-
-// Stores block rows in the symmetric layout when it applies (blocks of 32);
-// false: the caller stores them otherwise.
+// Stores block rows in the symmetric layout when it applies (blocks of 32 to
+// 64 rows); false: the caller stores them otherwise.
 template <int B>
 __device__ __forceinline__ bool store_sym(uint8_t *dst, int prec, const double (&row)[B], int lane, double inv_s,
                                           int sym) {
-  if constexpr (B == 32) {
+  if constexpr (B >= 32) {
     if (sym) {
-      if (lane < 32) store_block_sym32(dst, prec, row, lane, inv_s);
+      if (lane < B) {
+        switch (prec) {
+          case P64: store_rows_sym<B, P64>(dst, row, lane, 1.0); break;
+          case P32: store_rows_sym<B, P32>(dst, row, lane, inv_s); break;
+          case PBF16: store_rows_sym<B, PBF16>(dst, row, lane, inv_s); break;
+          default: store_rows_sym<B, P16>(dst, row, lane, inv_s); break;
+        }
+      }
       return true;
     }
   }
@@ -645,9 +654,9 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
     std::memcpy(tags.data(), policy->explicit_tags, nb);
   }
   // stored bytes of block k in format p: B^2 entries, w + 1 diagonals of B,
-  // or the three stored quarters of a symmetric block of 32
+  // or the upper strips of a symmetric block (B (B + 16) / 2 entries)
   auto width = [&](int32_t k, int p) -> int { return band ? wb[(size_t)k * 4 + p] : 0; };
-  auto blk_elems = [&](int B) -> int64_t { return sym && B == 32 ? (int64_t)kSym32Elems : (int64_t)B * B; };
+  auto blk_elems = [&](int B) -> int64_t { return sym ? (int64_t)sym_elems(B) : (int64_t)B * B; };
   auto blk_bytes = [&](int32_t k, int p) -> int64_t {
     const int64_t B = pl.bpad[k];
     return (band ? B * (width(k, p) + 1) : blk_elems((int)B)) * prec_bytes(p);
@@ -752,6 +761,7 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
 extern "C" void bjac_destroy(bjac_handle *h) {
   if (!h) return;
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 
@@ -810,9 +820,9 @@ extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block
   const int64_t off = which == 1 ? h->h_off_hi[block] : h->h_off_lo[block];
   const int BY = prec_bytes(prec), V = 16 / BY;
   const bool band = h->storage == BJAC_STORE_BAND;
-  const bool sym = h->storage == BJAC_STORE_SYM && B == 32;
+  const bool sym = h->storage == BJAC_STORE_SYM;
   const int w = band ? (which == 1 ? h->h_w_hi[block] : h->h_w_lo[block]) : 0;
-  std::vector<uint8_t> raw((size_t)(sym ? kSym32Elems : B * (band ? w + 1 : B)) * BY);
+  std::vector<uint8_t> raw((size_t)(sym ? sym_elems(B) : B * (band ? w + 1 : B)) * BY);
   double sc = 1.0;
   MPB_HIP(hipMemcpyAsync(raw.data(), h->ws + off, raw.size(), hipMemcpyDeviceToHost, h->stream));
   MPB_HIP(hipMemcpyAsync(&sc, (which == 1 ? h->scale_hi : h->scale_lo) + block, sizeof(double),
@@ -821,10 +831,12 @@ extern "C" int bjac_get_block(const bjac_handle *h, int32_t which, int32_t block
   for (int i = 0; i < b; ++i) {
     for (int j = 0; j < b; ++j) {
       if (sym) {
-        // rows 0..15 in the full layout; H11 as a 16-column block after them;
-        // the lower-left quarter mirrored from the upper-right one
-        const int ii = (i >= 16 && j < 16) ? j : i, jj = (i >= 16 && j < 16) ? i : j;
-        const int64_t e = ii < 16 ? layout_elem(32, V, ii, jj) : 64 * 8 + layout_elem(16, V, ii - 16, jj - 16);
+        // row tile I keeps columns 16 I .. B-1 as strip I; an entry left of
+        // its row tile's strip is the mirror of a stored one
+        const bool lower = (j / 16) < (i / 16);
+        const int ri = lower ? j : i, rj = lower ? i : j;
+        const int I = ri / 16;
+        const int64_t e = sym_strip_off(B, I) + layout_elem(B - 16 * I, V, ri % 16, rj - 16 * I);
         out[(size_t)i * b + j] = decode(raw.data() + e * BY, prec);
       } else if (!band) {
         out[(size_t)i * b + j] = decode(raw.data() + layout_elem(B, V, i, j) * BY, prec);

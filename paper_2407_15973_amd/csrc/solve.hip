@@ -18,7 +18,8 @@
 #include <cstddef>
 #include <type_traits>
 #include <cstring>
-#include <unordered_map>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "device_util.hpp"
@@ -51,21 +52,31 @@ struct WaveIter {
 // cost less ramp-up and a shorter end-of-kernel reduction), a multiple of 8
 // when possible.
 static int grid_for_waves(int T, const void *kernel, int per_cu_max = kGridPerCu) {
-  static std::unordered_map<const void *, int> cap;
-  auto it = cap.find(kernel);
-  if (it == cap.end()) {
-    int per_cu = 0, cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1 ||
-        cus < 1) {
-      per_cu = 1;
-      cus = 256;
+  // occupancy and compute units per (kernel, device), queried once under a
+  // lock, so handles used from several threads (or devices) share the cache
+  static std::mutex mu;
+  static std::map<std::pair<const void *, int>, std::pair<int, int>> cap;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::pair<int, int> pc;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cap.find({kernel, dev});
+    if (it == cap.end()) {
+      int per_cu = 0, cus = 0;
+      if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1 ||
+          cus < 1) {
+        per_cu = 1;
+        cus = 256;
+      }
+      it = cap.emplace(std::make_pair(kernel, dev), std::make_pair(per_cu, cus)).first;
     }
-    it = cap.emplace(kernel, (per_cu < per_cu_max ? per_cu : per_cu_max) * cus).first;
+    pc = it->second;
   }
+  const int resident = std::min(pc.first, per_cu_max) * pc.second;
   int G = (T + 7) / 8;
-  if (G > it->second) G = it->second;
+  if (G > resident) G = resident;
   if (G > kMaxGrid) G = kMaxGrid;
   if (G >= 8) G &= ~7;
   return G < 1 ? 1 : G;
@@ -195,13 +206,16 @@ __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
 }
 
 // ------------------------------------------------------------------- SpMV
-enum SpmvMode { SPMV_PLAIN = 0, SPMV_PCG = 1 };
+// SPMV_CG: the single-reduction iteration's product w = A u (u gathered at
+// the neighbours, no p update) with the three dots (r, r), (r, u), (w, u).
+enum SpmvMode { SPMV_PLAIN = 0, SPMV_PCG = 1, SPMV_CG = 2 };
 
 struct SpmvArgs {
   int32_t n, ntiles;
   const int32_t *rp, *ci;
   const double *v;
-  const double *z;      // PCG: preconditioned residual; PLAIN: the vector p
+  const double *z;      // PCG: preconditioned residual; PLAIN: the vector p; CG: u = M^-1 r
+  const double *rv;     // CG: the residual r (read at the row only)
   const double *pold;
   double *pnew, *q;
   PcgState *st;
@@ -219,7 +233,7 @@ struct SpmvArgs {
 // end are clamped to its last entry and their values replaced by zero, so
 // there is no branch inside a group. Also returns p_new of the row itself
 // when the row stores its diagonal.
-template <bool PCG, class IT>
+template <bool PCG, class IT, bool FIND = PCG>
 __device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
                                           const IT *__restrict__ cidx, const double *__restrict__ vals, double beta,
                                           int base, int len, int row, double &prow, bool &found, int roff) {
@@ -240,7 +254,7 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       acc = fma(vs[k], g[k], acc);
-      if (PCG && cs[k] == row) {
+      if (FIND && cs[k] == row) {
         prow = g[k];
         found = true;
       }
@@ -272,8 +286,14 @@ using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 // tile t's gathers of z and p_old, so the two round trips overlap (the row
 // pointers run two tiles ahead), and the q / p_new stores of tile t are held
 // back until after tile t+1's loads are issued.
-template <bool PCG, bool REL>
-__device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc) {
+struct Dots3 {
+  double a = 0.0, b = 0.0, c = 0.0;
+};
+
+template <int SM, bool REL>
+__device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc) {
+  constexpr bool PCG = SM == SPMV_PCG;   // p = z + beta p_old gathered, (p, q)
+  constexpr bool CG = SM == SPMV_CG;     // u gathered, (r, r), (r, u), (w, u)
   constexpr int SLOT = kSpmvSlot;
   constexpr int NV = SLOT * 8 / 16 / 64;                  // value chunks per lane
   constexpr int NC = SLOT * (REL ? 2 : 4) / 16 / 64;      // index chunks per lane
@@ -286,7 +306,7 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
   const double *__restrict__ pold = a.pold;
   const IT *sci = (const IT *)sc;
   const int lane = threadIdx.x & 63;
-  double dot = 0.0;
+  Dots3 dot;
   bool s_has = false;   // q and p_new of the previous tile, stored after the next loads
   int s_row = 0;
   double s_q = 0.0, s_p = 0.0;
@@ -354,6 +374,7 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
     const int len = has ? e_c - s_c : 0;
     double acc = 0.0, prow = 0.0;
     bool found = false;
+    const double rrow = CG ? a.rv[min(row, a.n - 1)] : 0.0;   // in flight with the gathers
     if (need_c > 0) {
 #pragma unroll
       for (int q = 0; q < NV; ++q) {
@@ -366,12 +387,12 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
         if (c * EC < need_c) ((u32x4 *)sc)[c] = gc[q];
       }
       wave_lds_sync();
-      acc = row_dot<PCG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, REL ? row : 0);
+      acc = row_dot<PCG, IT, PCG || CG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, REL ? row : 0);
       wave_lds_sync();
     } else if (REL) {
-      acc = row_dot<PCG>(z, pold, a.o16, vv_g, beta, s_c, len, row, prow, found, row);
+      acc = row_dot<PCG, int16_t, PCG || CG>(z, pold, a.o16, vv_g, beta, s_c, len, row, prow, found, row);
     } else {
-      acc = row_dot<PCG>(z, pold, a.ci, vv_g, beta, s_c, len, row, prow, found, 0);
+      acc = row_dot<PCG, int32_t, PCG || CG>(z, pold, a.ci, vv_g, beta, s_c, len, row, prow, found, 0);
     }
     s_has = has;
     s_row = row;
@@ -379,7 +400,13 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
     if (has && PCG) {
       const double pr = found ? prow : fma(beta, pold[row], z[row]);
       s_p = pr;
-      dot = fma(pr, acc, dot);
+      dot.a = fma(pr, acc, dot.a);
+    }
+    if (has && CG) {
+      const double ur = found ? prow : z[row];
+      dot.a = fma(rrow, rrow, dot.a);
+      dot.b = fma(rrow, ur, dot.b);
+      dot.c = fma(acc, ur, dot.c);
     }
     s_c = s_n;
     e_c = e_n;
@@ -399,8 +426,59 @@ __device__ __forceinline__ double spmv_tiles(const SpmvArgs &a, double beta, dou
   return dot;
 }
 
-template <bool PCG>
+// State transition of the single-reduction iteration, after w = A u and the
+// dots (r, r), (r, u), (w, u) of the residual r the last update left (the
+// Chronopoulos-Gear recurrence): convergence test on r (the iteration count
+// is the number of x updates, as in the textbook form), then
+// beta = gamma / gamma_old and alpha = gamma / (delta - beta gamma / alpha_old)
+// (beta = 0, alpha = gamma / delta for the first direction or after a
+// restart) for the next update.
+__device__ __forceinline__ void cg_after_spmv(PcgState *st, double rr, double gamma, double delta) {
+  st->rr = rr;
+  if (st->restart) {
+    st->relres = sqrt(rr) / st->rnorm0;
+  } else if (st->iter < 0) {
+    st->rnorm0 = sqrt(rr);
+    st->iter = 0;
+    st->relres = INFINITY;
+    if (st->rnorm0 == 0.0) {
+      st->relres = 0.0;
+      st->status = ST_CONVERGED;
+      return;
+    }
+  } else {
+    st->iter += 1;
+    st->relres = sqrt(rr) / st->rnorm0;
+    if (st->relres_hist) st->relres_hist[st->iter - 1] = st->relres;
+    if (st->relres <= st->tol) {
+      st->status = ST_CONVERGED;
+      return;
+    }
+  }
+  st->rz = gamma;
+  if (!(gamma > 0.0)) {
+    st->status = ST_BREAKDOWN;
+    return;
+  }
+  const bool first = st->iter == 0 || st->restart;
+  const double beta = first ? 0.0 : gamma / st->rho;
+  const double denom = first ? delta : delta - beta * gamma / st->alpha;
+  st->pq = denom;   // (p, A p) of the new direction in exact arithmetic
+  if (!(denom > 0.0)) {
+    st->status = ST_BREAKDOWN;
+    return;
+  }
+  st->beta = beta;
+  st->alpha = gamma / denom;
+  st->rho = gamma;
+  st->restart = 0;
+  if (st->iter >= st->maxit) st->status = ST_MAXIT;
+}
+
+template <int SM>
 __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
+  constexpr bool PCG = SM == SPMV_PCG;
+  constexpr bool CG = SM == SPMV_CG;
   constexpr int SLOT = kSpmvSlot;
   __shared__ __align__(16) double svs[4][SLOT];
   __shared__ __align__(16) int scs[4][SLOT];
@@ -408,36 +486,57 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   __shared__ int flag, ok;
   // status and rel16 are adjacent: one load before the early exit
   int2 sr = make_int2(ST_RUNNING, 0);
-  if (PCG) sr = *(const int2 *)&a.st->status;
-  if (PCG && sr.x != ST_RUNNING) return;
+  if (PCG || CG) sr = *(const int2 *)&a.st->status;
+  if ((PCG || CG) && sr.x != ST_RUNNING) return;
   const double beta = PCG ? a.st->beta : 0.0;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double dot;
-  if constexpr (PCG) {
-    if (a.o16 && sr.y) dot = spmv_tiles<true, true>(a, beta, svs[wv], scs[wv]);
-    else dot = spmv_tiles<true, false>(a, beta, svs[wv], scs[wv]);
+  Dots3 dot;
+  if constexpr (PCG || CG) {
+    if (a.o16 && sr.y) dot = spmv_tiles<SM, true>(a, beta, svs[wv], scs[wv]);
+    else dot = spmv_tiles<SM, false>(a, beta, svs[wv], scs[wv]);
   } else {
-    dot = spmv_tiles<false, false>(a, beta, svs[wv], scs[wv]);
+    dot = spmv_tiles<SPMV_PLAIN, false>(a, beta, svs[wv], scs[wv]);
   }
-  if (!PCG) return;
-  const double bs = block_sum(dot, sh);
-  if (threadIdx.x == 0) {
-    publish(a.part + blockIdx.x, bs);
-    ok = 1;
-  }
-  if (last_workgroup(&a.st->ticket_a, &flag)) {
-    const double pq = sum_partials(a.part, gridDim.x, 1, sh, &ok);
+  if constexpr (PCG) {
+    const double bs = block_sum(dot.a, sh);
     if (threadIdx.x == 0) {
-      PcgState *st = a.st;
-      st->pq = pq;
-      if (!ok) {
-        st->status = ST_SYNC_FAIL;
-      } else if (!(pq > 0.0)) {
-        st->status = ST_BREAKDOWN;
-      } else {
-        st->alpha = st->rho / pq;
+      publish(a.part + blockIdx.x, bs);
+      ok = 1;
+    }
+    if (last_workgroup(&a.st->ticket_a, &flag)) {
+      const double pq = sum_partials(a.part, gridDim.x, 1, sh, &ok);
+      if (threadIdx.x == 0) {
+        PcgState *st = a.st;
+        st->pq = pq;
+        if (!ok) {
+          st->status = ST_SYNC_FAIL;
+        } else if (!(pq > 0.0)) {
+          st->status = ST_BREAKDOWN;
+        } else {
+          st->alpha = st->rho / pq;
+        }
+        __hip_atomic_store(&st->ticket_a, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      __hip_atomic_store(&st->ticket_a, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if constexpr (CG) {
+    const double b0 = block_sum(dot.a, sh);
+    const double b1 = block_sum(dot.b, sh);
+    const double b2 = block_sum(dot.c, sh);
+    if (threadIdx.x == 0) {
+      publish(a.part + 3 * blockIdx.x, b0);
+      publish(a.part + 3 * blockIdx.x + 1, b1);
+      publish(a.part + 3 * blockIdx.x + 2, b2);
+      ok = 1;
+    }
+    if (last_workgroup(&a.st->ticket_a, &flag)) {
+      double t[3];
+      sum_partials_n<3>(a.part, gridDim.x, 3, sh, &ok, t);
+      if (threadIdx.x == 0) {
+        PcgState *st = a.st;
+        if (!ok) st->status = ST_SYNC_FAIL;
+        else cg_after_spmv(st, t[0], t[1], t[2]);
+        __hip_atomic_store(&st->ticket_a, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
@@ -446,7 +545,10 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
 // Launch modes: x/r update fused with the application (PCG), update only
 // (adaptive switch, first half), application of the map the device-side
 // switch chose (second half), standalone application z = M^-1 rin.
-enum ApplyMode { M_FUSED = 0, M_UPD = 1, M_APPDEV = 2, M_APP = 3 };
+// M_CG: the single-reduction (Chronopoulos-Gear) iteration: p = u + beta p,
+// s = w + beta s, x += alpha p, r -= alpha s, then u = M^-1 r, with no
+// reduction (the dots are taken by the following SpMV).
+enum ApplyMode { M_FUSED = 0, M_UPD = 1, M_APPDEV = 2, M_APP = 3, M_CG = 4 };
 
 struct ApplyArgs {
   int32_t ntiles, nb, n, want_high;
@@ -458,6 +560,7 @@ struct ApplyArgs {
   const double *p, *q, *rin;
   PcgState *st;
   double *part;
+  double *pw, *sw;   // M_CG: p and s = A p, read and written in place (z holds u, q holds w = A u)
 };
 
 // The fragment one lane holds of one 16-row tile of a stored block, and its
@@ -566,55 +669,94 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// A block of padded size 32 in symmetric storage (H00 and H01 as the first
-// 16-row tile of the full layout, H11 as a 16-column block after it): the
-// lane's fragments of both, and z = H r with the transpose of H01 standing
-// for H10.
-template <int P>
-struct Sym32 {
-  Frag<32, P> f0;
-  Frag<16, P> f1;
+// A block of padded size B = 16 m (m = 2..4) in symmetric storage: strip I
+// holds row tile I's columns 16 I .. B-1 (the quarters H_IJ, J >= I) as the
+// single 16-row tile of a block of padded size B - 16 I. The lane holds its
+// fragment of every strip; z_I = sum_{J >= I} H_IJ r_J + sum_{J < I} H_JI^T r_J.
+template <int B, int P>
+struct SymB {
+  static constexpr int M = B / 16;
+  static_assert(M >= 2 && M <= 4, "symmetric storage holds blocks of 32 to 64");
+  static constexpr int W1 = M >= 2 ? B - 16 : 16, W2 = M >= 3 ? B - 32 : 16, W3 = M >= 4 ? B - 48 : 16;
+  Frag<B, P> f0;
+  Frag<W1, P> f1;
+  Frag<W2, P> f2;
+  Frag<W3, P> f3;
+  using CT = std::conditional_t<P == P64, double, float>;
 
   __device__ __forceinline__ void load(const uint8_t *blk, int lane) {
+    constexpr int BY = prec_bytes(P);
     f0.load(blk, 0, lane);
-    f1.load(blk + 64 * 8 * prec_bytes(P), 0, lane);
+    f1.load(blk + (int64_t)sym_strip_off(B, 1) * BY, 0, lane);
+    if constexpr (M >= 3) f2.load(blk + (int64_t)sym_strip_off(B, 2) * BY, 0, lane);
+    if constexpr (M >= 4) f3.load(blk + (int64_t)sym_strip_off(B, 3) * BY, 0, lane);
   }
 
-  // r32 / r64: the block's residual in LDS; writes sc * (H r) to zt[0..31];
-  // tt: 16 LDS slots of scratch
+  // lane (i, kq)'s share of (H_JI^T r_J)[4 s + kq] for every J < I: its entry
+  // H_JI[i][4 s + kq] is k-step 4 (I - J) + s of strip J's fragment
+  template <int I, int S>
+  __device__ __forceinline__ CT trans_term(const CT (&ri)[4]) const {
+    CT t = f0.template value<4 * I + S>() * ri[0];
+    if constexpr (I >= 2) t += f1.template value<4 * (I - 1) + S>() * ri[1];
+    if constexpr (I >= 3) t += f2.template value<4 * (I - 2) + S>() * ri[2];
+    return t;
+  }
+
+  // the transposed contributions to row tile I, summed over the 16 lanes of
+  // each column class (one DPP row) and left in tt[16 I + 4 s + kq]
+  template <int I>
+  __device__ __forceinline__ void trans(const CT (&ri)[4], double *tt, int lane) const {
+    const int i = lane & 15, kq = lane >> 4;
+    CT t0 = row16_sum(trans_term<I, 0>(ri)), t1 = row16_sum(trans_term<I, 1>(ri));
+    CT t2 = row16_sum(trans_term<I, 2>(ri)), t3 = row16_sum(trans_term<I, 3>(ri));
+    if (i < 4) tt[16 * I + 4 * i + kq] = (double)(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3);
+  }
+
+  // r32 / r64: the block's residual in LDS; writes sc * (H r) to zt[0..B-1];
+  // tt: B LDS slots of scratch
   __device__ __forceinline__ void apply(const float *r32, const double *r64, double sc, double *zt, double *tt,
                                         int lane) const {
-    using CT = std::conditional_t<P == P64, double, float>;
-    const int i = lane & 15, kq = lane >> 4;
-    const double z0 = f0.dot(r32, r64, lane);             // rows 0..15: H00 r0 + H01 r1
-    const double z1 = f1.dot(r32 + 16, r64 + 16, lane);   // rows 16..31: H11 r1
-    // (H01^T r0)[4 s + kq] = sum over i of H01[i][4 s + kq] r0[i]: lane (i, kq)
-    // holds H01[i][4 s + kq] as k-step 4 + s of its first-tile fragment, and
-    // the 16 lanes of column class kq form one DPP row
-    CT ri;
-    if constexpr (P == P64) ri = r64[i];
-    else ri = r32[i];
-    CT t0 = f0.template value<4>() * ri, t1 = f0.template value<5>() * ri;
-    CT t2 = f0.template value<6>() * ri, t3 = f0.template value<7>() * ri;
-    t0 = row16_sum(t0);
-    t1 = row16_sum(t1);
-    t2 = row16_sum(t2);
-    t3 = row16_sum(t3);
-    if (i < 4) tt[4 * i + kq] = (double)(i == 0 ? t0 : i == 1 ? t1 : i == 2 ? t2 : t3);
+    const int i = lane & 15;
+    double zd[4];
+    zd[0] = f0.dot(r32, r64, lane);
+    zd[1] = f1.dot(r32 + 16, r64 + 16, lane);
+    if constexpr (M >= 3) zd[2] = f2.dot(r32 + 32, r64 + 32, lane);
+    if constexpr (M >= 4) zd[3] = f3.dot(r32 + 48, r64 + 48, lane);
+    CT ri[4];
+#pragma unroll
+    for (int J = 0; J < M - 1; ++J) {
+      if constexpr (P == P64) ri[J] = r64[16 * J + i];
+      else ri[J] = r32[16 * J + i];
+    }
+    trans<1>(ri, tt, lane);
+    if constexpr (M >= 3) trans<2>(ri, tt, lane);
+    if constexpr (M >= 4) trans<3>(ri, tt, lane);
     wave_lds_sync();
     if (lane < 16) {
-      zt[lane] = z0 * sc;
-      zt[16 + lane] = (z1 + tt[lane]) * sc;
+      zt[lane] = zd[0] * sc;
+#pragma unroll
+      for (int I = 1; I < M; ++I) zt[16 * I + lane] = (zd[I] + tt[16 * I + lane]) * sc;
     }
   }
 };
 
-template <int P>
-__device__ __forceinline__ void sym32_apply(const uint8_t *blk, const float *r32, const double *r64, double sc,
-                                            double *zt, double *tt, int lane) {
-  Sym32<P> f;
+template <int B, int P>
+__device__ __forceinline__ void sym_apply(const uint8_t *blk, const float *r32, const double *r64, double sc,
+                                          double *zt, double *tt, int lane) {
+  SymB<B, P> f;
   f.load(blk, lane);
   f.apply(r32, r64, sc, zt, tt, lane);
+}
+
+template <int B>
+__device__ __forceinline__ void sym_apply_p(int prec, const uint8_t *blk, const float *r32, const double *r64,
+                                            double sc, double *zt, double *tt, int lane) {
+  switch (prec) {
+    case P64: sym_apply<B, P64>(blk, r32, r64, sc, zt, tt, lane); break;
+    case P32: sym_apply<B, P32>(blk, r32, r64, sc, zt, tt, lane); break;
+    case PBF16: sym_apply<B, PBF16>(blk, r32, r64, sc, zt, tt, lane); break;
+    default: sym_apply<B, P16>(blk, r32, r64, sc, zt, tt, lane); break;
+  }
 }
 
 __device__ __forceinline__ void record_high(PcgState *st, int idx, int hi) {
@@ -670,53 +812,104 @@ __device__ __forceinline__ void after_apply(PcgState *st, double rz, int used_hi
 template <int MODE>
 struct ModeTraits {
   static constexpr bool UPD = MODE == M_FUSED || MODE == M_UPD;
+  static constexpr bool CG = MODE == M_CG;
   static constexpr bool APP = MODE != M_UPD;
   static constexpr bool PCG = MODE != M_APP;
 };
 
-// Row phase of one lane (x += alpha p, r -= alpha q in the update modes, else
-// read r), split into loads and stores: the kernels hold a tile's stores back
-// until the next tile's loads are out, because a wait for loads also waits for
-// every store issued before them (one counter), so storing at the end of a
-// tile would add a store round trip to every tile. Loads read a row clamped
-// into [0, n) and are zeroed for lanes without a row, so no branch separates
-// them.
+// Row phase of one lane (x += alpha p, r -= alpha q in the update modes; the
+// p / s recurrences first in the single-reduction mode; else read r), split
+// into loads and stores: the kernels hold a tile's stores back until the next
+// tile's loads are out, because a wait for loads also waits for every store
+// issued before them (one counter), so storing at the end of a tile would add
+// a store round trip to every tile. Loads read a row clamped into [0, n) and
+// are zeroed for lanes without a row, so no branch separates them.
 struct RowIn {
-  double x, p, q, r;
+  double x, p, q, r, u, w;
 };
+
+// Results of one tile, stored after the next tile's loads are issued.
+struct RowHold {
+  bool real = false;
+  int grow = 0;
+  double x = 0.0, r = 0.0, z = 0.0, p = 0.0, s = 0.0;
+};
+
+struct UpdCoef {
+  double alpha, beta;
+};
+
+template <int MODE>
+__device__ __forceinline__ UpdCoef upd_coef(const ApplyArgs &a) {
+  UpdCoef c{0.0, 0.0};
+  if constexpr (ModeTraits<MODE>::UPD || ModeTraits<MODE>::CG) c.alpha = a.st->alpha;
+  if constexpr (ModeTraits<MODE>::CG) c.beta = a.st->beta;
+  return c;
+}
 
 template <int MODE>
 __device__ __forceinline__ RowIn row_load(const ApplyArgs &a, bool real, int grow) {
   const int gc = min(max(grow, 0), a.n - 1);
-  RowIn v{0.0, 0.0, 0.0, 0.0};
+  RowIn v{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if constexpr (ModeTraits<MODE>::UPD) {
     v.x = a.x[gc];
     v.p = a.p[gc];
     v.q = a.q[gc];
     v.r = a.r[gc];
+  } else if constexpr (ModeTraits<MODE>::CG) {
+    v.x = a.x[gc];
+    v.p = a.pw[gc];
+    v.q = a.sw[gc];
+    v.r = a.r[gc];
+    v.u = a.z[gc];
+    v.w = a.q[gc];
   } else if constexpr (MODE == M_APP) {
     v.r = a.rin[gc];
   } else {
     v.r = a.r[gc];
   }
-  if (!real) v = RowIn{0.0, 0.0, 0.0, 0.0};
+  if (!real) v = RowIn{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   return v;
 }
 
+// The update of one row; returns the residual the application reads and
+// leaves the row's new x (and p, s) in h.
 template <int MODE>
-__device__ __forceinline__ void row_store(const ApplyArgs &a, bool real, int grow, double xn, double rn, double zn) {
-  if (!real) return;
+__device__ __forceinline__ double row_update(const RowIn &v, const UpdCoef &c, double &rr, RowHold &h) {
   if constexpr (ModeTraits<MODE>::UPD) {
-    a.x[grow] = xn;
-    a.r[grow] = rn;
+    h.x = fma(c.alpha, v.p, v.x);
+    const double rv = fma(-c.alpha, v.q, v.r);
+    rr = fma(rv, rv, rr);
+    return rv;
+  } else if constexpr (ModeTraits<MODE>::CG) {
+    h.p = fma(c.beta, v.p, v.u);
+    h.s = fma(c.beta, v.q, v.w);
+    h.x = fma(c.alpha, h.p, v.x);
+    return fma(-c.alpha, h.s, v.r);
+  } else {
+    return v.r;
   }
-  if constexpr (ModeTraits<MODE>::APP) a.z[grow] = zn;
+}
+
+template <int MODE>
+__device__ __forceinline__ void row_store(const ApplyArgs &a, const RowHold &h) {
+  if (!h.real) return;
+  if constexpr (ModeTraits<MODE>::UPD || ModeTraits<MODE>::CG) {
+    a.x[h.grow] = h.x;
+    a.r[h.grow] = h.r;
+  }
+  if constexpr (ModeTraits<MODE>::CG) {
+    a.pw[h.grow] = h.p;
+    a.sw[h.grow] = h.s;
+  }
+  if constexpr (ModeTraits<MODE>::APP) a.z[h.grow] = h.z;
 }
 
 // Reductions and the state machine at the end of a PCG launch.
 template <int MODE>
 __device__ __forceinline__ void apply_epilogue(const ApplyArgs &a, double rr, double rz, double *sh, int *flag) {
   using T = ModeTraits<MODE>;
+  if constexpr (T::CG) return;   // the single-reduction SpMV takes the dots
   const double brr = T::UPD ? block_sum(rr, sh) : 0.0;
   const double brz = T::APP ? block_sum(rz, sh) : 0.0;
   if (threadIdx.x == 0) {
@@ -762,17 +955,18 @@ __device__ __forceinline__ bool apply_skip(const ApplyArgs &a) {
 // in P, block k at a fixed stride. Rows, block addresses and the tile shape are
 // arithmetic, so the stored fragments, the per-block scales and the vectors of
 // a tile are all requested before the first wait.
-// SYM: blocks of 32 in symmetric storage (H10 taken as the transpose of H01).
+// SYM: blocks of 32 to 64 in symmetric storage (the quarters below the
+// diagonal taken as transposes of stored ones).
 template <int B, int P, int MODE, bool SYM = false>
 __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
-  static_assert(!SYM || B == 32, "symmetric storage holds blocks of 32");
+  static_assert(!SYM || B >= 32, "symmetric storage holds blocks of 32 to 64");
   using T = ModeTraits<MODE>;
   constexpr int NB = 64 / B;        // blocks per wave tile
   constexpr int R = NB * B;         // padded rows per wave tile
   constexpr int MT = R / 16;        // 16-row tiles per wave tile
   constexpr int MPB = B / 16;       // 16-row tiles per block
   using F = Frag<B, P>;
-  constexpr int64_t BLK = (SYM ? (int64_t)kSym32Elems : (int64_t)B * B) * prec_bytes(P);
+  constexpr int64_t BLK = (SYM ? (int64_t)sym_elems(B) : (int64_t)B * B) * prec_bytes(P);
   constexpr bool PRE = SYM || MT * F::G <= 8;
   __shared__ float r32s[4][64];
   __shared__ double r64s[4][64];
@@ -781,7 +975,7 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
-  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const UpdCoef cf = upd_coef<MODE>(a);
   const uint8_t *__restrict__ base = a.map.base + a.off0;
   const double *__restrict__ scale = a.map.scale;
   const int lane = threadIdx.x & 63;
@@ -791,16 +985,14 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
   double *zt = zts[wv];
   const int j = lane / B, li = lane - j * B;
   double rr = 0.0, rz = 0.0;
-  bool s_real = false;   // results of the previous tile, stored after this tile's loads
-  int s_grow = 0;
-  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
+  RowHold hold;   // results of the previous tile, stored after this tile's loads
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = it.t * NB;
     const int kb = k0 + j;
     const int grow = kb * B + li;
     const bool real = lane < R && kb < a.nb && grow < a.n;
     F fr[PRE && !SYM ? MT : 1];
-    Sym32<P> fs[SYM ? NB : 1];
+    SymB<SYM ? B : 32, P> fs[SYM ? NB : 1];
     double scl = 1.0;
     if constexpr (T::APP) {
       if constexpr (P != P64) scl = scale[min(k0 + lane % NB, a.nb - 1)];
@@ -813,13 +1005,10 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
       }
     }
     const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
-    double rv = v.r, xn = 0.0, zv_out = 0.0;
-    if constexpr (T::UPD) {
-      xn = fma(alpha, v.p, v.x);
-      rv = fma(-alpha, v.q, v.r);
-      rr = fma(rv, rv, rr);
-    }
+    row_store<MODE>(a, hold);
+    RowHold nh;
+    const double rv = row_update<MODE>(v, cf, rr, nh);
+    double zv_out = 0.0;
     if constexpr (T::APP) {
       if (lane < R) {
         r64[lane] = rv;
@@ -859,13 +1048,13 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
         rz = fma(rv, zv_out, rz);
       }
     }
-    s_real = real;
-    s_grow = grow;
-    s_x = xn;
-    s_r = rv;
-    s_z = zv_out;
+    nh.real = real;
+    nh.grow = grow;
+    nh.r = rv;
+    nh.z = zv_out;
+    hold = nh;
   }
-  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+  row_store<MODE>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -901,16 +1090,14 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
-  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const UpdCoef cf = upd_coef<MODE>(a);
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float *r32 = r32s[wv];
   double *r64 = r64s[wv];
   double *zt = zts[wv];
   double rr = 0.0, rz = 0.0;
-  bool s_real = false;   // results of the previous tile, stored after this tile's loads
-  int s_grow = 0;
-  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
+  RowHold hold;   // results of the previous tile, stored after this tile's loads
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
     const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
@@ -937,13 +1124,10 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
     const bool real = li >= 0 && li < bsz;
     const int grow = row0 + li;
     const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
-    double rv = v.r, xn = 0.0, zv_out = 0.0;
-    if constexpr (T::UPD) {
-      xn = fma(alpha, v.p, v.x);
-      rv = fma(-alpha, v.q, v.r);
-      rr = fma(rv, rv, rr);
-    }
+    row_store<MODE>(a, hold);
+    RowHold nh;
+    const double rv = row_update<MODE>(v, cf, rr, nh);
+    double zv_out = 0.0;
     if constexpr (T::APP) {
       if (lane < cum) {
         r64[lane] = rv;
@@ -956,12 +1140,11 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
         const int prec = readlane_i(mtag, i);
         const uint8_t *blk = a.map.base + readlane_l(moff, i);
         const double sc = bcast(msc, i);
-        if (B == 32 && a.map.sym) {
-          switch (prec) {
-            case P64: sym32_apply<P64>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
-            case P32: sym32_apply<P32>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
-            case PBF16: sym32_apply<PBF16>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
-            default: sym32_apply<P16>(blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+        if (B >= 32 && a.map.sym) {
+          switch (B) {
+            case 32: sym_apply_p<32>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            case 48: sym_apply_p<48>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            default: sym_apply_p<64>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
           }
           cb += B;
           continue;
@@ -984,13 +1167,13 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
         rz = fma(rv, zv_out, rz);
       }
     }
-    s_real = real;
-    s_grow = grow;
-    s_x = xn;
-    s_r = rv;
-    s_z = zv_out;
+    nh.real = real;
+    nh.grow = grow;
+    nh.r = rv;
+    nh.z = zv_out;
+    hold = nh;
   }
-  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+  row_store<MODE>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -1151,12 +1334,10 @@ __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
-  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const UpdCoef cf = upd_coef<MODE>(a);
   const int lane = threadIdx.x & 63;
   double rr = 0.0, rz = 0.0;
-  bool s_real = false;   // results of the previous tile, stored after this tile's loads
-  int s_grow = 0;
-  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
+  RowHold hold;   // results of the previous tile, stored after this tile's loads
   for (WaveIter it(a.ntiles); it.t < it.end; it.t += it.step) {
     const int k0 = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t]);
     const int nk = __builtin_amdgcn_readfirstlane(a.tile_blk[it.t + 1]) - k0;
@@ -1194,22 +1375,18 @@ __global__ __launch_bounds__(256) void apply_band_kernel(ApplyArgs a) {
     BandRaw<PU> raw0;
     band_load_round<PU>(raw0, a.map.base + off, Bp, max(li, 0), max(wl, 0), 0, tg);
     const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
-    double rv = v.r, xn = 0.0;
-    if constexpr (T::UPD) {
-      xn = fma(alpha, v.p, v.x);
-      rv = fma(-alpha, v.q, v.r);
-      rr = fma(rv, rv, rr);
-    }
+    row_store<MODE>(a, hold);
+    RowHold nh;
+    const double rv = row_update<MODE>(v, cf, rr, nh);
     const double zv = band_product<PU>(a.map.base + off, Bp, li, wl, wmax, tg, sc, rv, raw0);
     if (real) rz = fma(rv, zv, rz);
-    s_real = real;
-    s_grow = grow;
-    s_x = xn;
-    s_r = rv;
-    s_z = zv;
+    nh.real = real;
+    nh.grow = grow;
+    nh.r = rv;
+    nh.z = zv;
+    hold = nh;
   }
-  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+  row_store<MODE>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -1225,7 +1402,7 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
   __shared__ double sh[4];
   __shared__ int flag[2];
   if (apply_skip<MODE>(a)) return;
-  const double alpha = T::UPD ? a.st->alpha : 0.0;
+  const UpdCoef cf = upd_coef<MODE>(a);
   const int lane = threadIdx.x & 63;
   const int j = lane / B, li0 = lane - j * B;
   double rr = 0.0, rz = 0.0;
@@ -1234,9 +1411,7 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
   int kn = min(it.t * NB + j, a.nb - 1);
   int64_t off_n = a.map.off[kn];
   int w_n = a.map.w[kn];
-  bool s_real = false;   // results of the previous tile, stored after this tile's loads
-  int s_grow = 0;
-  double s_x = 0.0, s_r = 0.0, s_z = 0.0;
+  RowHold hold;   // results of the previous tile, stored after this tile's loads
   for (; it.t < it.end; it.t += it.step) {
     const int kb = it.t * NB + j;
     const int kc = min(kb, a.nb - 1);
@@ -1253,25 +1428,21 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
     BandRaw<PU> raw0;
     band_load_round<PU>(raw0, a.map.base + off, B, inb ? li0 : 0, max(wl, 0), 0, tg);
     const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);   // the previous tile's results
-    double rv = v.r, xn = 0.0;
-    if constexpr (T::UPD) {
-      xn = fma(alpha, v.p, v.x);
-      rv = fma(-alpha, v.q, v.r);
-      rr = fma(rv, rv, rr);
-    }
+    row_store<MODE>(a, hold);   // the previous tile's results
+    RowHold nh;
+    const double rv = row_update<MODE>(v, cf, rr, nh);
     int wmax = 0;
 #pragma unroll
     for (int q = 0; q < NB; ++q) wmax = max(wmax, readlane_i(wl, q * B));
     const double zv = band_product<PU>(a.map.base + off, B, inb ? li0 : -1, wl, wmax, tg, sc, rv, raw0);
     if (real) rz = fma(rv, zv, rz);
-    s_real = real;
-    s_grow = grow;
-    s_x = xn;
-    s_r = rv;
-    s_z = zv;
+    nh.real = real;
+    nh.grow = grow;
+    nh.r = rv;
+    nh.z = zv;
+    hold = nh;
   }
-  row_store<MODE>(a, s_real, s_grow, s_x, s_r, s_z);
+  row_store<MODE>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -1295,13 +1466,17 @@ __global__ void state_init_kernel(PcgState *st, double tol, int maxit, double ad
   *st = s;
 }
 
+// x = 0, r = b and zeros in the work vectors the first iteration reads (the
+// single-reduction form also reads u and s, scaled by beta = 0)
 __global__ __launch_bounds__(256) void pcg_fill_kernel(int64_t n, double *x, double *r, const double *b, double *p,
-                                                       double *q) {
+                                                       double *q, double *u, double *s) {
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     x[i] = 0.0;
     r[i] = b[i];
     p[i] = 0.0;
     q[i] = 0.0;
+    if (u) u[i] = 0.0;
+    if (s) s[i] = 0.0;
   }
 }
 
@@ -1335,6 +1510,7 @@ __global__ __launch_bounds__(256) void restart_kernel(PcgState *st, const double
     if (st->status == ST_CONVERGED && sqrt(rr) > st->tol * st->rnorm0 && st->iter < st->maxit) {
       st->status = ST_RUNNING;
       st->alpha = 0.0;
+      st->beta = 0.0;
       st->restart = 1;
     }
   }
@@ -1607,8 +1783,10 @@ int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_
 }
 
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
-                        PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr) {
+                        PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr,
+                        const double *rv = nullptr) {
   SpmvArgs a{};
+  a.rv = rv;
   a.o16 = o16;
   a.n = (int32_t)A->n;
   a.ntiles = (int)((A->n + kSpmvRows - 1) / kSpmvRows);
@@ -1625,11 +1803,14 @@ static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, 
   const uintptr_t al = (uintptr_t)A->val | (uintptr_t)A->col_idx | (uintptr_t)o16;
   a.vec = (al & 15) == 0;
   if (mode == SPMV_PCG) {
-    const void *k = (const void *)spmv_kernel<true>;
-    hipLaunchKernelGGL(spmv_kernel<true>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+    const void *k = (const void *)spmv_kernel<SPMV_PCG>;
+    hipLaunchKernelGGL(spmv_kernel<SPMV_PCG>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+  } else if (mode == SPMV_CG) {
+    const void *k = (const void *)spmv_kernel<SPMV_CG>;
+    hipLaunchKernelGGL(spmv_kernel<SPMV_CG>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
   } else {
-    const void *k = (const void *)spmv_kernel<false>;
-    hipLaunchKernelGGL(spmv_kernel<false>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+    const void *k = (const void *)spmv_kernel<SPMV_PLAIN>;
+    hipLaunchKernelGGL(spmv_kernel<SPMV_PLAIN>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
   }
 }
 
@@ -1657,13 +1838,13 @@ static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a, int p
 
 template <int B, int MODE>
 static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
-  if constexpr (B == 32 && MODE != M_UPD) {
+  if constexpr (B >= 32 && MODE != M_UPD) {
     if (a.map.sym) {
       switch (prec) {
-        case P64: launch_persistent(apply_fast_kernel<32, P64, MODE, true>, s, a); break;
-        case P32: launch_persistent(apply_fast_kernel<32, P32, MODE, true>, s, a); break;
-        case PBF16: launch_persistent(apply_fast_kernel<32, PBF16, MODE, true>, s, a); break;
-        default: launch_persistent(apply_fast_kernel<32, P16, MODE, true>, s, a); break;
+        case P64: launch_persistent(apply_fast_kernel<B, P64, MODE, true>, s, a); break;
+        case P32: launch_persistent(apply_fast_kernel<B, P32, MODE, true>, s, a); break;
+        case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE, true>, s, a); break;
+        default: launch_persistent(apply_fast_kernel<B, P16, MODE, true>, s, a); break;
       }
       return;
     }
@@ -1736,8 +1917,10 @@ static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, co
 // One launch of the application kernel in the given mode and map.
 static void launch_apply(const bjac_handle *h, int mode, int want_high, const MapSel &m, double *x, double *r,
                          double *z, const double *p, const double *q, const double *rin, PcgState *st, double *part,
-                         hipStream_t s) {
+                         hipStream_t s, double *pw = nullptr, double *sw = nullptr) {
   ApplyArgs a{};
+  a.pw = pw;
+  a.sw = sw;
   a.ntiles = h->ntiles;
   a.nb = h->nb;
   a.n = (int32_t)h->n;
@@ -1759,6 +1942,7 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
     case M_FUSED: launch_mode<M_FUSED>(h, m, s, a); break;
     case M_UPD: launch_mode<M_UPD>(h, m, s, a); break;
     case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a); break;
+    case M_CG: launch_mode<M_CG>(h, m, s, a); break;
     default: launch_mode<M_APP>(h, m, s, a); break;
   }
 }
@@ -1787,12 +1971,13 @@ static SolveWs carve_solve(void *ws, int64_t n, int64_t nnz16 = 0) {
   return w;
 }
 
-static hipStream_t capture_stream() {
-  static hipStream_t s = nullptr;
-  if (!s) {
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
-  }
-  return s;
+// The handle's own stream for capturing its iteration graph (created on the
+// first capture, destroyed with the handle): captures of distinct handles from
+// distinct threads never share a stream.
+static hipStream_t capture_stream(bjac_handle *M) {
+  if (!M->cap_stream && hipStreamCreateWithFlags(&M->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    M->cap_stream = nullptr;
+  return M->cap_stream;
 }
 
 // The x / r update and the application: fused, or (adaptive switch) an update
@@ -1839,10 +2024,25 @@ static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs 
   }
 }
 
-// One PCG iteration: q = A p (p updated on the fly), then update + apply.
-static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
-                              const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev) {
+// The single-reduction iteration's update + application: p = u + beta p,
+// s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r (u in z, w in q, p in
+// pa, s in pb; p, s and u are updated in place: each row reads only itself).
+static void enqueue_cg_apply(const bjac_handle *M, double *x, const SolveWs &w, hipStream_t s, hipEvent_t *ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
+  launch_apply(M, M_CG, 0, sel_lo(M), x, w.r, w.z, nullptr, w.q, nullptr, w.st, nullptr, s, w.pa, w.pb);
+  if (ev) (void)hipEventRecord(ev[1], s);
+}
+
+// One PCG iteration: q = A p (p updated on the fly), then update + apply;
+// single-reduction form: w = A u with the three dots, then update + apply.
+static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
+                              const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg = false) {
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (cg) {
+    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r);
+    enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr);
+    return;
+  }
   launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16);
   enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr);
 }
@@ -1855,7 +2055,8 @@ struct Prof {
 };
 
 static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
-                        int chunk, int max_launches, hipStream_t s, PcgState &hs, int &launches, Prof &prof) {
+                        int chunk, int max_launches, hipStream_t s, PcgState &hs, int &launches, Prof &prof,
+                        bool cg) {
   constexpr int EV = 4;  // events per iteration: spmv start, update/apply start, split point, end
   std::vector<hipEvent_t> ev((size_t)EV * chunk);
   // timing-only events: no system-scope cache writeback and invalidation at
@@ -1868,7 +2069,7 @@ static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, cons
     const int it0 = hs.iter;
     for (int i = 0; i < chunk; ++i) {
       const bool even = (i & 1) == 0;
-      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, ev.data() + EV * i);
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, ev.data() + EV * i, cg);
     }
     ++launches;
     if (hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1957,6 +2158,11 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   if (w.bytes > workspace_bytes) return BJAC_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
+  if (opts->variant != BJAC_PCG_TEXTBOOK && opts->variant != BJAC_PCG_SINGLE_REDUCTION) return BJAC_EINVAL;
+  const bool cg = opts->variant == BJAC_PCG_SINGLE_REDUCTION;
+  // the single-reduction form serves stored-inverse maps without the
+  // adaptive switch (its update has no relres of the new residual yet)
+  if (cg && (temporal || M->kind != 0)) return BJAC_EINVAL;
   int chunk = opts->chunk > 0 ? opts->chunk : 16;
   chunk += chunk & 1;  // even: the p buffers return to their roles
 
@@ -1967,30 +2173,35 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
                      M->policy.temporal, opts->relres_hist, opts->high_hist);
   if (w.o16) launch_off16((int)A->n, A->row_ptr, A->col_idx, w.o16, &w.st->rel16, s);
-  hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q);
+  hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q,
+                     cg ? w.z : nullptr, cg ? w.pb : nullptr);
   hipLaunchKernelGGL(fill_empty_kernel, dim3(24), dim3(256), 0, s, w.part1, 3 * kMaxGrid);
   // first application z_0 = M^-1 r_0 (alpha = 0 leaves x = 0, r = b)
-  enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
+  if (cg) enqueue_cg_apply(M, x, w, s, nullptr);
+  else enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
   MPB_HIP(hipGetLastError());
 
   // captured chunk of iterations, cached in the handle per argument set
   std::vector<uintptr_t> key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val,
                                 (uintptr_t)A->n, (uintptr_t)x, (uintptr_t)workspace, (uintptr_t)chunk,
-                                (uintptr_t)w.o16};
+                                (uintptr_t)w.o16, (uintptr_t)cg};
   if (!opts->profile && (!M->gexec || M->gkey != key)) {
     if (M->gexec) {
       (void)hipGraphExecDestroy(M->gexec);
       M->gexec = nullptr;
     }
-    hipStream_t cs = capture_stream();
+    hipStream_t cs = capture_stream(M);
     if (!cs) return BJAC_EHIP;
     MPB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < chunk; ++i) {
       const bool even = (i & 1) == 0;
-      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, cs, nullptr);
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, cs, nullptr, cg);
     }
     hipGraph_t g = nullptr;
-    MPB_HIP(hipStreamEndCapture(cs, &g));
+    if (hipStreamEndCapture(cs, &g) != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return BJAC_EHIP;
+    }
     hipError_t ie = hipGraphInstantiate(&M->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ie != hipSuccess) {
@@ -2008,7 +2219,7 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   MPB_HIP(hipStreamSynchronize(s));
   Prof prof;
   if (opts->profile) {
-    int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof);
+    int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof, cg);
     if (rc) return rc;
   } else {
     for (;;) {
@@ -2032,7 +2243,8 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
         break;
       }
       ++restarts;
-      enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
+      if (cg) enqueue_cg_apply(M, x, w, s, nullptr);
+      else enqueue_update_apply(M, x, w, temporal, w.pa, s, nullptr);
       MPB_HIP(hipGetLastError());
       MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
       MPB_HIP(hipStreamSynchronize(s));

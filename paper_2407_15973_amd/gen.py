@@ -202,16 +202,16 @@ def config2(seed=0, N=128, b=32, contrast=2.0) -> Problem:
                    rhs_uniform(A.n, rng), 1e-10, 5000)
 
 
-def aniso_jump_problem(seed=0, N=160, b=48, name="aniso_jump", ratio=1e3) -> Problem:
+def aniso_jump_problem(seed=0, N=160, b=48, name="aniso_jump", ratio=1e3, strong="x") -> Problem:
     """Anisotropic diffusion K = diag(ratio, 1, 1) * kappa, kappa = 1e4 on 16
     random subcubes and 1 elsewhere, row blocks of 48. The strong coupling runs
-    along x, the fastest index, so that the contiguous row blocks contain it;
-    with the strong axes across the blocks (the orientation of the paper's
-    Ani(s), diag(1, s, s)) block-Jacobi with 48-row blocks drops every strong
-    coupling and PCG stalls near a relative residual of 1e-3."""
+    along x, the fastest index, so that the contiguous row blocks contain it.
+    strong="yz" gives the orientation of the paper's Ani(s), K = diag(1, s, s):
+    the strong axes then run across the blocks, and block-Jacobi with 48-row
+    blocks drops every strong coupling."""
     rng = np.random.default_rng(seed)
     kap = kappa_subcube_jumps(N, rng)
-    A = diffusion3d(kap, aniso=(ratio, 1.0, 1.0))
+    A = diffusion3d(kap, aniso=(ratio, 1.0, 1.0) if strong == "x" else (1.0, ratio, ratio))
     return Problem(f"{name}_{N}^3_b{b}", A, uniform_blocks(A.n, b), rhs_uniform(A.n, rng), 1e-10, 5000)
 
 

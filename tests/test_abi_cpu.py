@@ -29,7 +29,7 @@ def test_library_loads_and_exports_all_symbols():
     L = binding.load()
     for name in _declared():
         assert hasattr(L, name), name
-    assert L.bjac_abi_version() == 1
+    assert L.bjac_abi_version() == 2
     assert L.bjac_strerror(-2).decode().startswith("a diagonal block")
 
 
@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     import ctypes as C
     assert C.sizeof(binding.bjac_csr) == 40
     assert C.sizeof(binding.bjac_policy) == 64
-    assert C.sizeof(binding.bjac_solve_opts) == 40
+    assert C.sizeof(binding.bjac_solve_opts) == 48
     assert C.sizeof(binding.bjac_stats) == 88
     assert C.sizeof(binding.bjac_info) == 64
     assert C.sizeof(binding.bjac_batch_cfg) == 16

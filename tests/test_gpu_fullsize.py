@@ -1,0 +1,110 @@
+"""Full-size parity of the benchmark workloads against the oracle.
+
+The oracle's PCG iteration counts at the benchmark sizes are stored under
+tests/golden/ (oracle_iters_<workload>_<map>.json, written by
+tests/golden/make_oracle_iters.py, which calls only oracle/). On the GPU the
+same workloads are solved in the storage the benchmark times (symmetric
+block inverses); the FP64 map must stay within 2 iterations of the oracle's
+FP64 count, a reduced map within 2 of the oracle's count for the same map
+(both read the same seeded inputs), and every solution's FP64 true relative
+residual is checked on the host. Sampled blocks and rows of the 128^3
+workload are compared with the oracle's application."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import blocks as OB
+from oracle import pcg as OP
+from oracle import precision as OPr
+from paper_2407_15973_amd import binding as mb
+from paper_2407_15973_amd import gen
+
+from gpu_helpers import dev, gamma, tensor
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+WORKLOADS = {
+    "diff3d_128": lambda: gen.config2(seed=0, N=128, b=32),
+    "aniso_160": lambda: gen.config3(seed=0, N=160, b=48),
+    "heldout_192": lambda: gen.config5_eval(seed=100, N=192, b=48),
+}
+POLICIES = {
+    "fp64": mb.Policy(mode=mb.UNIFORM, storage=mb.STORE_SYM),
+    "fp32": mb.Policy(mode=mb.FIXED, low=mb.FP32, storage=mb.STORE_SYM),
+    "fp16": mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM),
+    "rule": mb.Policy(mode=mb.RULE, storage=mb.STORE_SYM),
+}
+CASES = [(w, m) for w in WORKLOADS for m in POLICIES
+         if os.path.exists(os.path.join(GOLDEN, f"oracle_iters_{w}_{m}.json"))]
+_problems = {}
+
+
+def golden(workload, pmap):
+    with open(os.path.join(GOLDEN, f"oracle_iters_{workload}_{pmap}.json")) as f:
+        return json.load(f)
+
+
+def problem(workload):
+    if workload not in _problems:
+        _problems.clear()          # one large problem held at a time
+        _problems[workload] = WORKLOADS[workload]()
+    return _problems[workload]
+
+
+@pytest.mark.parametrize("workload,pmap", CASES)
+def test_iterations_against_oracle_at_full_size(workload, pmap):
+    g = golden(workload, pmap)
+    p = problem(workload)
+    print(f"[fullsize] {workload} {pmap}: n = {p.A.n}", flush=True)
+    assert (g["n"], g["nnz"], g["blocks"]) == (p.A.n, p.A.nnz, len(p.block_ptr) - 1)
+    Ad = mb.DeviceCSR(p.A, dev())
+    M = mb.BlockJacobi(Ad, p.block_ptr, POLICIES[pmap])
+    hist = list(M.info()["blocks_per_prec"])
+    if pmap == "rule":
+        # the rule compares each block's kappa_1 u_p with theta; the two sides
+        # compute kappa_1 from different FP64 inverses, so a block within
+        # rounding of the threshold may fall either way
+        assert sum(abs(a - c) for a, c in zip(hist, g["blocks_per_prec"])) <= max(2, g["blocks"] // 10000)
+    else:
+        assert hist == g["blocks_per_prec"]
+    res = mb.Solver(p.A.n, dev()).solve(Ad, M, tensor(p.b), tol=p.tol, maxit=p.maxit)
+    x = res.x.cpu().numpy()
+    print(f"[fullsize] gpu {res.iters} oracle {g['iters']} iterations", flush=True)
+    assert res.status == mb.OK and g["status"] == OP.CONVERGED
+    assert abs(res.iters - g["iters"]) <= 2, (res.iters, g["iters"])
+    assert OP.true_relres(p.A, x, p.b) <= 2 * p.tol
+
+
+@pytest.mark.parametrize("storage", [mb.STORE_FULL, mb.STORE_SYM])
+def test_full_size_config2_sampled_parity(storage):
+    # the 128^3 workload the benchmark times, FP16 storage, checked on sampled
+    # blocks and rows against the oracle's full product (symmetric storage
+    # reads the lower quarters as transposes of the upper ones: within the
+    # one-ulp allowance of the stored values) and by the FP64 true residual
+    p = problem("diff3d_128")
+    nb = len(p.block_ptr) - 1
+    Ad = mb.DeviceCSR(p.A, dev())
+    M = mb.BlockJacobi(Ad, p.block_ptr, mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=storage))
+    rng = np.random.default_rng(10)
+    ks = rng.choice(nb, size=48, replace=False)
+    sub = np.concatenate([[0], np.cumsum(np.diff(p.block_ptr)[ks])]).astype(np.int32)
+    rows = np.concatenate([np.arange(p.block_ptr[k], p.block_ptr[k + 1]) for k in ks])
+    S = p.A.to_scipy()[rows][:, rows]
+    Asub = gen.CSR(len(rows), S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+    H = OB.invert_blocks(Asub, sub)
+    store = OB.store_blocks(H, np.full(len(ks), OPr.FP16, np.uint8))
+    r = rng.uniform(-1, 1, p.A.n)
+    z = M.apply(tensor(r)).cpu().numpy()
+    zref = OB.apply(store, sub, r[rows])
+    bound = (gamma(32, 2.0 ** -24) + 2.0 ** -10) * OB.apply_abs(store, sub, r[rows])
+    assert np.all(np.abs(z[rows] - zref) <= bound)
+    for j, k in enumerate(ks[:8]):
+        got, s = M.block(int(k))
+        Hh, sref, _ = store[j]
+        assert s == sref and np.all(np.abs(got - Hh) <= 2.0 ** -10 * np.abs(Hh) + 2.0 ** -24)
+    res = mb.Solver(p.A.n, dev()).solve(Ad, M, tensor(p.b), tol=1e-10, maxit=5000)
+    assert res.status == mb.OK
+    assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2e-10

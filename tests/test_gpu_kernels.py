@@ -252,22 +252,38 @@ def test_temporal_handle_stores_both_maps():
     assert info["high_bytes"] == (len(bp) - 1) * 48 * 48 * 8 and info["low_bytes"] == (len(bp) - 1) * 48 * 48 * 2
 
 
-# ------------------------------------------------ symmetric storage (blocks of 32)
+# ------------------------------------ symmetric storage (blocks of 32 to 64)
+def _sym_elems(B):
+    # stored entries of a symmetric block of padded size B: row tile I keeps
+    # its columns 16 I .. B-1, i.e. 16 (B - 16 I) entries
+    return sum(16 * (B - 16 * i) for i in range(B // 16))
+
+
+def _assert_mirrored(got):
+    # an entry left of its row tile's stored strip reads back as the mirror of
+    # the stored entry (the quarters below the diagonal are not stored)
+    b = got.shape[0]
+    i, j = np.nonzero(np.ones((b, b), bool))
+    low = (j // 16) < (i // 16)
+    np.testing.assert_array_equal(got[i[low], j[low]], got[j[low], i[low]])
+
+
+@pytest.mark.parametrize("b", [32, 48, 64])
 @pytest.mark.parametrize("prec", [OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16])
-def test_sym_storage_exact_family(prec):
-    # integer inverses are exactly symmetric: the three stored quarters read
-    # back as the oracle's full rounded block, and the application stays within
-    # the FP32 (FP64) accumulation bound of the oracle's full product
-    rng = np.random.default_rng(11)
-    A = gen.spd_exact_inverse_blocks(40, 32, rng)
-    bp = gen.uniform_blocks(A.n, 32)
+def test_sym_storage_exact_family(prec, b):
+    # integer inverses are exactly symmetric: the stored strips read back as
+    # the oracle's full rounded block, and the application stays within the
+    # FP32 (FP64) accumulation bound of the oracle's full product
+    rng = np.random.default_rng(11 + b)
+    A = gen.spd_exact_inverse_blocks(40, b, rng)
+    bp = gen.uniform_blocks(A.n, b)
     nb = len(bp) - 1
     tags = np.full(nb, prec, np.uint8)
     H, store = oracle_setup(A, bp, tags)
     Ad = mb.DeviceCSR(A, dev())
     M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=prec, storage=mb.STORE_SYM))
     full = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=prec))
-    assert M.info()["low_bytes"] * 4 == full.info()["low_bytes"] * 3
+    assert M.info()["low_bytes"] * b * b == full.info()["low_bytes"] * _sym_elems(b)
     for k in range(nb):
         got, s = M.block(k)
         Hh, s_ref, _ = store[k]
@@ -278,17 +294,19 @@ def test_sym_storage_exact_family(prec):
         r = rng.uniform(-1, 1, A.n) * np.exp(rng.uniform(-30, 0, A.n))
         z = M.apply(tensor(r)).cpu().numpy()
         ref = OB.apply(store, bp, r)
-        bound = gamma(32, u) * OB.apply_abs(store, bp, r)
+        bound = gamma(b, u) * OB.apply_abs(store, bp, r)
         assert np.all(np.abs(z - ref) <= bound + 1e-300)
 
 
-@pytest.mark.parametrize("sizes", [None, (16, 32, 48, 64), (7, 33, 64, 32)])
-def test_sym_storage_general_mixed_map(sizes):
-    # blocks of padded size 32 stored symmetric, the others full; mixed formats
-    # run the generic kernel. H10 of the oracle's inverse and the transpose of
-    # its H01 differ by the FP64 inversion's rounding, bounded like the stored
-    # one-ulp differences of the full-storage test
-    A, bp, rng = _diffusion_case(seed=6, shape=(16, 12, 10), sizes=sizes, b=32)
+@pytest.mark.parametrize("b,sizes", [(32, None), (48, None), (64, None), (0, (16, 32, 48, 64)), (0, (7, 33, 64, 32)),
+                                     (0, (40, 48, 61))])
+def test_sym_storage_general_mixed_map(b, sizes):
+    # blocks of padded size 32 to 64 stored symmetric, blocks of 16 full; mixed
+    # formats run the generic kernel. The lower quarters of the oracle's
+    # inverse and the transposes of its upper ones differ by the FP64
+    # inversion's rounding, bounded like the stored one-ulp differences of the
+    # full-storage test
+    A, bp, rng = _diffusion_case(seed=6 + b, shape=(16, 12, 10), sizes=sizes, b=b)
     nb = len(bp) - 1
     tags = rng.choice([OPr.FP64, OPr.FP32, OPr.BF16, OPr.FP16], size=nb).astype(np.uint8)
     if sizes is None:
@@ -308,13 +326,12 @@ def test_sym_storage_general_mixed_map(sizes):
         zb = OB.apply_abs(store, bp, r)
         bound = (gamma(bmax, 2.0 ** -24) + per_row + 8 * bmax * kap * 2.0 ** -53) * zb
         assert np.all(np.abs(z - ref) <= bound + 1e-300)
-    # a read-back block of padded size 32 mirrors its upper-right quarter
+    # read-back blocks of more than 16 rows mirror their stored quarters
     nsym = 0
     for k in range(nb):
         got, _ = M.block(k)
-        b = got.shape[0]
-        if 16 < b <= 32:
-            np.testing.assert_array_equal(got[16:, :16], got[:16, 16:].T)
+        if got.shape[0] > 16:
+            _assert_mirrored(got)
             nsym += 1
     assert nsym > 0
 
