@@ -141,6 +141,20 @@ def measured_traffic(key):
     return e[1] if e is not None and e[0] == sources_digest() else None
 
 
+def calibration_copy():
+    """One device-to-device copy of 1 GiB (read 1 GiB, write 1 GiB): the
+    reference dispatch that scales rocprofv3's FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    log("calibration copy: 1 GiB read, 1 GiB written")
+
+
 def stream_ceilings(dev, gib=1):
     """Achievable streaming rates of this GPU, measured with PyTorch's own
     kernels on gib-GiB FP64 tensors: a reduction (read only), a fill (write
@@ -204,14 +218,6 @@ def bench_diff3d(args):
         solve = [r[2][1].elapsed_time(r[2][2]) for r in runs]
         return (t1 - t0) * 1e3 / k, float(np.median(setup)), float(np.median(solve)), runs[-1]
 
-    if args.calibrate:
-        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("calibration copy: 1 GiB read, 1 GiB written")
     log(f"warmup {args.warmup} steps")
     for _ in range(args.warmup):
         step(pol16)
@@ -594,6 +600,8 @@ def bench_policies(args):
     else:
         pols = {"rule": pols["rule"], "fp16": pols["fp16"], "fp64": pols["fp64"]}
     cmp_steps = min(args.steps, args.cmp_steps)
+    if cmp_steps < 1:   # profiling runs: the headline map only
+        pols = {head: pols[head]}
 
     def step(policy, profile=False):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -674,9 +682,9 @@ def bench_policies(args):
         "iters": hv["iters"], "iters_oracle_fp64": g64["iters"] if g64 else None,
         "delay_vs_oracle_fp64": hv["delay_vs_oracle_fp64"],
         "true_relres": hv["true_relres"], "setup_ms": hv["setup_ms"], "solve_ms": hv["solve_ms"],
-        "speedup_vs_fp64": rows["fp64"]["ms_per_step"] / hv["ms_per_step"],
-        "speedup_vs_rule": rows["rule"]["ms_per_step"] / hv["ms_per_step"],
-        "speedup_vs_fp16": rows["fp16"]["ms_per_step"] / hv["ms_per_step"],
+        "speedup_vs_fp64": rows["fp64"]["ms_per_step"] / hv["ms_per_step"] if "fp64" in rows else None,
+        "speedup_vs_rule": rows["rule"]["ms_per_step"] / hv["ms_per_step"] if "rule" in rows else None,
+        "speedup_vs_fp16": rows["fp16"]["ms_per_step"] / hv["ms_per_step"] if "fp16" in rows else None,
         "policies": rows, "comparison_steps": cmp_steps,
         "us_per_iter": hv["solve_ms"] * 1e3 / max(1, hv["iters"]), "bytes_per_iter": iter_bytes,
         "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
@@ -1035,6 +1043,8 @@ def main():
         print("bench.py runs on one GPU only: the solver has no multi-GPU path, so --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.calibrate:
+        calibration_copy()
     if args.workload == "diff3d":
         args.N = args.N or 128
         line = bench_diff3d(args)

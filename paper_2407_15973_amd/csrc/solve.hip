@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstddef>
 #include <type_traits>
 #include <cstring>
@@ -2145,31 +2146,48 @@ extern "C" int pcg_workspace_query_csr(const bjac_csr *A, size_t *workspace_byte
   return BJAC_OK;
 }
 
-extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double *b, double *x,
-                         const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes, bjac_stats *stats,
-                         void *stream) {
-  if (!A || !Mc || !b || !x || !opts || !workspace || b == x) return BJAC_EINVAL;
-  if (A->n != Mc->n || !A->row_ptr || !A->col_idx || !A->val) return BJAC_EINVAL;
+// Checks shared by the PCG entry points; 0 or an error code.
+static int check_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *x,
+                       const bjac_solve_opts *opts) {
+  if (!A || !M || !b || !x || !opts || b == x) return BJAC_EINVAL;
+  if (A->n != M->n || !A->row_ptr || !A->col_idx || !A->val) return BJAC_EINVAL;
   if (!(opts->tol >= 0.0) || opts->maxit < 1) return BJAC_EINVAL;
-  bjac_handle *M = const_cast<bjac_handle *>(Mc);
-  // with room for the 16-bit index copy the products use it, else the CSR's own
-  SolveWs w = carve_solve(workspace, A->n, A->nnz);
-  if (w.bytes > workspace_bytes || A->nnz < 1) w = carve_solve(workspace, A->n);
-  if (w.bytes > workspace_bytes) return BJAC_ENOMEM;
-  hipStream_t s = (hipStream_t)stream;
-  const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
   if (opts->variant != BJAC_PCG_TEXTBOOK && opts->variant != BJAC_PCG_SINGLE_REDUCTION) return BJAC_EINVAL;
-  const bool cg = opts->variant == BJAC_PCG_SINGLE_REDUCTION;
   // the single-reduction form serves stored-inverse maps without the
   // adaptive switch (its update has no relres of the new residual yet)
-  if (cg && (temporal || M->kind != 0)) return BJAC_EINVAL;
+  if (opts->variant == BJAC_PCG_SINGLE_REDUCTION && (M->policy.temporal != BJAC_TEMPORAL_NONE || M->kind != 0))
+    return BJAC_EINVAL;
+  return BJAC_OK;
+}
+
+// Events destroyed on every exit path.
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~EventPair() {
+    for (auto &v : e)
+      if (v) (void)hipEventDestroy(v);
+  }
+};
+
+// The body of pcg_solve on a carved workspace.
+// graphs: chunks of iterations replayed from a graph captured once per
+// handle and argument set, timed with events; otherwise every chunk's
+// kernels are launched directly and the time is taken on the host (no graph,
+// event or allocation). Both launch the same kernels in the same order.
+static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double *x, const bjac_solve_opts *opts,
+                     const SolveWs &w, const void *workspace, hipStream_t s, bool graphs, bjac_stats *stats) {
+  const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
+  const bool cg = opts->variant == BJAC_PCG_SINGLE_REDUCTION;
   int chunk = opts->chunk > 0 ? opts->chunk : 16;
   chunk += chunk & 1;  // even: the p buffers return to their roles
 
-  hipEvent_t e0, e1;
-  MPB_HIP(hipEventCreate(&e0));
-  MPB_HIP(hipEventCreate(&e1));
-  MPB_HIP(hipEventRecord(e0, s));
+  EventPair ev;
+  const auto h0 = std::chrono::steady_clock::now();
+  if (graphs) {
+    MPB_HIP(hipEventCreate(&ev.e[0]));
+    MPB_HIP(hipEventCreate(&ev.e[1]));
+    MPB_HIP(hipEventRecord(ev.e[0], s));
+  }
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
                      M->policy.temporal, opts->relres_hist, opts->high_hist);
   if (w.o16) launch_off16((int)A->n, A->row_ptr, A->col_idx, w.o16, &w.st->rel16, s);
@@ -2182,10 +2200,11 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   MPB_HIP(hipGetLastError());
 
   // captured chunk of iterations, cached in the handle per argument set
-  std::vector<uintptr_t> key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val,
-                                (uintptr_t)A->n, (uintptr_t)x, (uintptr_t)workspace, (uintptr_t)chunk,
-                                (uintptr_t)w.o16, (uintptr_t)cg};
-  if (!opts->profile && (!M->gexec || M->gkey != key)) {
+  std::vector<uintptr_t> key;
+  if (graphs && !opts->profile)
+    key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val, (uintptr_t)A->n, (uintptr_t)x,
+           (uintptr_t)workspace, (uintptr_t)chunk, (uintptr_t)w.o16, (uintptr_t)cg};
+  if (graphs && !opts->profile && (!M->gexec || M->gkey != key)) {
     if (M->gexec) {
       (void)hipGraphExecDestroy(M->gexec);
       M->gexec = nullptr;
@@ -2224,7 +2243,15 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   } else {
     for (;;) {
       while (hs.status == ST_RUNNING && launches < max_launches + restarts) {
-        MPB_HIP(hipGraphLaunch(M->gexec, s));
+        if (graphs) {
+          MPB_HIP(hipGraphLaunch(M->gexec, s));
+        } else {
+          for (int i = 0; i < chunk; ++i) {
+            const bool even = (i & 1) == 0;
+            enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, nullptr, cg);
+          }
+          MPB_HIP(hipGetLastError());
+        }
         ++launches;
         MPB_HIP(hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         MPB_HIP(hipStreamSynchronize(s));
@@ -2250,12 +2277,15 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
       MPB_HIP(hipStreamSynchronize(s));
     }
   }
-  MPB_HIP(hipEventRecord(e1, s));
-  MPB_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (graphs) {
+    MPB_HIP(hipEventRecord(ev.e[1], s));
+    MPB_HIP(hipEventSynchronize(ev.e[1]));
+    (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
+  } else {
+    MPB_HIP(hipStreamSynchronize(s));
+    ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - h0).count();
+  }
   int rc;
   switch (hs.status) {
     case ST_CONVERGED: rc = BJAC_OK; break;
@@ -2282,3 +2312,17 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   }
   return rc;
 }
+
+extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double *b, double *x,
+                         const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes, bjac_stats *stats,
+                         void *stream) {
+  int rc = check_solve(A, Mc, b, x, opts);
+  if (rc) return rc;
+  if (!workspace) return BJAC_EINVAL;
+  // with room for the 16-bit index copy the products use it, else the CSR's own
+  SolveWs w = carve_solve(workspace, A->n, A->nnz);
+  if (w.bytes > workspace_bytes || A->nnz < 1) w = carve_solve(workspace, A->n);
+  if (w.bytes > workspace_bytes) return BJAC_ENOMEM;
+  return solve_run(A, const_cast<bjac_handle *>(Mc), b, x, opts, w, workspace, (hipStream_t)stream, true, stats);
+}
+

@@ -1,0 +1,164 @@
+"""GPU parity of the single-reduction PCG (Chronopoulos-Gear recurrence,
+bjac_solve_opts.variant = BJAC_PCG_SINGLE_REDUCTION) against the oracle's
+plain statement of the same recurrence (oracle.pcg.pcg_single_reduction):
+iteration counts, relres histories, the FP64 true residual, across the
+stored-inverse kernels (fast tile path, symmetric storage, the per-block
+dispatch path of a rule map, band storage), the verification restart, the
+profile mode and the degenerate cases. All calls go through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import pcg as OP
+from oracle import precision as OPr
+from paper_2407_15973_amd import binding as mb
+from paper_2407_15973_amd import gen
+
+from gpu_helpers import dev, tensor
+
+pytestmark = pytest.mark.gpu
+SR = mb.PCG_SINGLE_REDUCTION
+
+
+def _solve(A, bp, b, pol, tol, maxit, **kw):
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, pol)
+    return mb.Solver(A.n, dev()).solve(Ad, M, tensor(b), tol=tol, maxit=maxit, variant=SR, **kw), M
+
+
+def _oracle(A, bp, b, tags, tol, maxit, band=False):
+    M = OP.BJAC(A, bp, tags, band=band)
+    S = A.to_scipy()
+    return OP.pcg_single_reduction(lambda v: S @ v, b, M.low, tol, maxit)
+
+
+def test_config1_matches_oracle():
+    p = gen.config1(0)
+    res, _ = _solve(p.A, p.block_ptr, p.b, mb.Policy(), p.tol, p.maxit, history=True)
+    ref = _oracle(p.A, p.block_ptr, p.b, None, p.tol, p.maxit)
+    hs = OP.solve_bjac(p.A, p.block_ptr, p.b, tol=p.tol, maxit=p.maxit)
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= 2 and abs(res.iters - hs.iters) <= 2
+    m = min(res.iters, ref.iters) - 1
+    np.testing.assert_allclose(res.relres_hist[:m], ref.history[:m], rtol=1e-6)
+    assert OP.true_relres(p.A, res.x.cpu().numpy(), p.b) <= 2 * p.tol
+
+
+@pytest.mark.parametrize("b,prec,storage,slack", [
+    (32, OPr.FP64, mb.STORE_FULL, 2), (32, OPr.FP16, mb.STORE_FULL, 2), (32, OPr.FP16, mb.STORE_SYM, 2),
+    (48, OPr.FP32, mb.STORE_SYM, 2), (64, OPr.FP16, mb.STORE_FULL, 2), (32, OPr.FP16, mb.STORE_BAND, 2)])
+def test_diffusion_maps_match_oracle(b, prec, storage, slack):
+    rng = np.random.default_rng(61 + b + prec)
+    A = gen.diffusion3d(gen.kappa_loguniform((24, 20, 16), rng))
+    bp = gen.uniform_blocks(A.n, b)
+    rhs = rng.uniform(-1, 1, A.n)
+    nb = len(bp) - 1
+    pol = (mb.Policy(mode=mb.UNIFORM, storage=storage) if prec == OPr.FP64
+           else mb.Policy(mode=mb.FIXED, low=prec, storage=storage))
+    res, _ = _solve(A, bp, rhs, pol, 1e-10, 3000, history=True)
+    ref = _oracle(A, bp, rhs, np.full(nb, prec, np.uint8), 1e-10, 3000, band=storage == mb.STORE_BAND)
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= slack, (res.iters, ref.iters)
+    m = min(res.iters, ref.iters, 60)
+    np.testing.assert_allclose(res.relres_hist[:m], ref.history[:m], rtol=1e-4)
+    assert OP.true_relres(A, res.x.cpu().numpy(), rhs) <= 2e-10
+
+
+def test_rule_map_generic_kernel_matches_oracle():
+    # a per-block rule map of several formats: the per-block dispatch kernel
+    p = gen.aniso_jump_problem(seed=3, N=24, b=48)
+    A, bp, rhs = p.A, p.block_ptr, p.b
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.RULE))
+    tags = M.tags()
+    assert len(set(tags.tolist())) > 1
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(rhs), tol=1e-10, maxit=3000, variant=SR)
+    ref = _oracle(A, bp, rhs, tags, 1e-10, 3000)
+    assert res.status == mb.OK and ref.status == OP.CONVERGED
+    assert abs(res.iters - ref.iters) <= 2, (res.iters, ref.iters)
+    assert OP.true_relres(A, res.x.cpu().numpy(), rhs) <= 2e-10
+
+
+def test_same_iterates_as_textbook_form_on_the_gpu():
+    # exact arithmetic gives both recurrences the same iterates: counts within
+    # 2, solutions within the stopping tolerance's reach of each other
+    rng = np.random.default_rng(68)
+    A = gen.diffusion3d(gen.kappa_loguniform((24, 24, 24), rng))
+    bp = gen.uniform_blocks(A.n, 32)
+    rhs = rng.uniform(-1, 1, A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16, storage=mb.STORE_SYM))
+    S = mb.Solver(A.n, dev())
+    r1 = S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=3000)
+    r2 = S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=3000, variant=SR)
+    assert r1.status == r2.status == mb.OK
+    assert abs(r1.iters - r2.iters) <= 2, (r1.iters, r2.iters)
+    for r in (r1, r2):
+        assert OP.true_relres(A, r.x.cpu().numpy(), rhs) <= 2e-10
+
+
+def test_profile_mode_and_chunking_give_identical_iterates():
+    rng = np.random.default_rng(69)
+    A = gen.diffusion3d(gen.kappa_loguniform((16, 16, 16), rng))
+    bp = gen.uniform_blocks(A.n, 32)
+    rhs = rng.uniform(-1, 1, A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16))
+    S = mb.Solver(A.n, dev())
+    ra = S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=2000, variant=SR, history=True)
+    rb = S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=2000, variant=SR, history=True, chunk=6)
+    rp = S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=2000, variant=SR, history=True, profile=True)
+    for r in (rb, rp):
+        assert r.iters == ra.iters
+        np.testing.assert_array_equal(r.relres_hist, ra.relres_hist)
+        np.testing.assert_array_equal(r.x.cpu().numpy(), ra.x.cpu().numpy())
+    assert rp.kernel_ms["spmv"][1] > 0 and rp.kernel_ms["apply"][1] > 0
+
+
+def test_verification_restart_keeps_the_true_residual():
+    # tol near the FP64 floor of the recursive residual: the FP64 check may
+    # restart from b - A x; either the true residual meets tol or every
+    # allowed restart was spent
+    rng = np.random.default_rng(70)
+    A = gen.diffusion3d(gen.kappa_loguniform((20, 20, 20), rng, lo=-3, hi=3))
+    bp = gen.uniform_blocks(A.n, 32)
+    rhs = rng.uniform(-1, 1, A.n)
+    res, _ = _solve(A, bp, rhs, mb.Policy(mode=mb.FIXED, low=mb.FP16), 1e-13, 5000, verify=3)
+    tr = OP.true_relres(A, res.x.cpu().numpy(), rhs)
+    if res.status == mb.OK:
+        assert tr <= 1e-13 * 1.01
+        assert res.true_relres <= 1e-13
+    else:
+        assert res.status == mb.NOT_CONVERGED and res.restarts == 3
+
+
+def test_degenerate_cases():
+    A = gen.poisson2d(16, 16)
+    bp = gen.uniform_blocks(A.n, 16)
+    rng = np.random.default_rng(71)
+    rhs = rng.uniform(-1, 1, A.n)
+    r, _ = _solve(A, bp, np.zeros(A.n), mb.Policy(), 1e-10, 30)
+    assert r.status == mb.OK and r.iters == 0 and not np.any(r.x.cpu().numpy())
+    r, _ = _solve(A, bp, rhs, mb.Policy(), 1e-20, 7, raise_on_error=False)
+    assert r.status == mb.NOT_CONVERGED and r.iters == 7
+    # one block holding the whole matrix: the exact solve, one iteration
+    B = gen.poisson2d(8, 8)
+    rb = rng.uniform(-1, 1, B.n)
+    r, _ = _solve(B, np.array([0, B.n], np.int32), rb, mb.Policy(), 1e-10, 10)
+    assert r.status == mb.OK and r.iters == 1
+
+
+def test_rejected_for_adaptive_and_paper_mode_handles():
+    A = gen.poisson2d(16, 16)
+    bp = gen.uniform_blocks(A.n, 16)
+    rhs = np.ones(A.n)
+    Ad = mb.DeviceCSR(A, dev())
+    S = mb.Solver(A.n, dev())
+    for M in (mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.FIXED, low=mb.FP16, temporal=mb.TEMPORAL_HL, adp_tol=1e-3)),
+              mb.PaperBJAC(Ad, bp, k=2, t=2, low=True)):
+        with pytest.raises(mb.MpbjacError) as e:
+            S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=50, variant=SR)
+        assert e.value.code == mb.EINVAL
+    M = mb.BlockJacobi(Ad, bp, mb.Policy())
+    with pytest.raises(mb.MpbjacError) as e:
+        S.solve(Ad, M, tensor(rhs), tol=1e-10, maxit=50, variant=2)
+    assert e.value.code == mb.EINVAL
