@@ -311,6 +311,24 @@ int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *
               const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes,
               bjac_stats *stats, void *stream);
 
+/* ---- PCG without allocation --------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pcg_solve
+ * with the solver workspace in a static device array of the library
+ * (5 n + 8192 doubles and the device state, for n up to 1,048,576 rows:
+ * about 40 MiB per GPU, held until the process ends). Arguments as
+ * pcg_solve without the workspace; A, M, b and x remain the caller's. The
+ * call allocates nothing: no hipMalloc or hipFree, no graph and no event;
+ * each chunk of opts->chunk iterations is launched directly (the same
+ * kernels in the same order as pcg_solve, so the same iterates) and
+ * stats->solve_ms is host time. The products read the 4-byte column indices.
+ * Returns BJAC_ENOMEM for n > 1,048,576 and BJAC_EINVAL for opts->profile.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call re-initialises what it reads): calls that overlap on one
+ * GPU, from several threads or streams, race and must not be made. */
+int pcg_solve_noalloc(const bjac_csr *A, const bjac_handle *M, const double *b, double *x,
+                      const bjac_solve_opts *opts, bjac_stats *stats, void *stream);
+
 /* ---- batched multi-RHS PCG (Sec. 3.2 per system and column) -------------
  * nsys independent SPD systems stacked as one block-diagonal CSR A (system s
  * owns rows sys_row[s] .. sys_row[s+1]-1 and only couples inside them) with

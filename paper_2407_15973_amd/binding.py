@@ -34,7 +34,7 @@ SYMBOLS = (
     "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_workspace_query_csr", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
     "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
-    "bjac_poly_setup_query", "bjac_poly_setup",
+    "bjac_poly_setup_query", "bjac_poly_setup", "pcg_solve_noalloc",
 )
 
 
@@ -109,6 +109,7 @@ def load(path: str = LIB_PATH):
         "pcg_workspace_query": (C.c_int, [i64, P(sz)]),
         "pcg_workspace_query_csr": (C.c_int, [P(bjac_csr), P(sz)]),
         "pcg_solve": (C.c_int, [P(bjac_csr), vp, vp, vp, P(bjac_solve_opts), vp, sz, P(bjac_stats), vp]),
+        "pcg_solve_noalloc": (C.c_int, [P(bjac_csr), vp, vp, vp, P(bjac_solve_opts), P(bjac_stats), vp]),
         "bjac_mlp_forward": (C.c_int, [vp, vp, i32, vp, vp, vp]),
         "bjac_mlp_workspace_query": (C.c_int, [i32, P(sz)]),
         "bjac_mlp_backward": (C.c_int, [vp, vp, vp, i32, vp, vp, vp, sz, vp]),
@@ -360,6 +361,19 @@ class Solver:
             napp = st.iters if rc == OK else st.iters + 1   # no application after the converged update
             res.high_hist = hh[:napp].cpu().numpy()
         return res
+
+
+def solve_noalloc(A: DeviceCSR, M: BlockJacobi, b, x, tol=1e-10, maxit=5000, chunk=16, variant=PCG_TEXTBOOK,
+                  verify=0) -> SolveResult:
+    """pcg_solve_noalloc: the solve with the library's static device
+    workspace (no allocation inside the call; b and x are the caller's)."""
+    opts = bjac_solve_opts(tol, maxit, chunk, None, None, 0, int(verify), int(variant), 0)
+    st = bjac_stats()
+    rc = load().pcg_solve_noalloc(C.byref(A.c), M.h, _ptr(b), _ptr(x), C.byref(opts), C.byref(st), _stream())
+    if rc < 0:
+        raise MpbjacError(rc, "pcg_solve_noalloc")
+    return SolveResult(x, st.iters, rc, st.relres, st.rnorm0, st.high_applications, st.graph_launches,
+                       st.solve_ms, restarts=st.restarts, true_relres=st.true_relres)
 
 
 # ------------------------------------------------------------------- MLP

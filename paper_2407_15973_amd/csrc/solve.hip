@@ -2169,7 +2169,7 @@ struct EventPair {
   }
 };
 
-// The body of pcg_solve on a carved workspace.
+// The body of pcg_solve and pcg_solve_noalloc on a carved workspace.
 // graphs: chunks of iterations replayed from a graph captured once per
 // handle and argument set, timed with events; otherwise every chunk's
 // kernels are launched directly and the time is taken on the host (no graph,
@@ -2326,3 +2326,43 @@ extern "C" int pcg_solve(const bjac_csr *A, const bjac_handle *Mc, const double 
   return solve_run(A, const_cast<bjac_handle *>(Mc), b, x, opts, w, workspace, (hipStream_t)stream, true, stats);
 }
 
+// ---------------------------------------------------- no-allocation solve
+// The PCG workspace of pcg_solve_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends. Host code never passes its name to a
+// kernel or a copy (on the host the name is only a stand-in): it uses the
+// device address hipGetSymbolAddress returns, taken once per device with that
+// device current and kept in g_noalloc_ptr.
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 20;
+constexpr size_t kNoAllocBytes = ((5 * kNoAllocMaxRows + 4 * kMaxGrid) * sizeof(double) + sizeof(PcgState) +
+                                  16 * 256 + 255) & ~size_t(255);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+static std::mutex g_noalloc_mu;
+static std::map<int, void *> g_noalloc_ptr;
+
+static int noalloc_scratch(void **out) {
+  int dev = 0;
+  MPB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(dev);
+  if (it == g_noalloc_ptr.end()) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BJAC_EHIP;
+    it = g_noalloc_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return BJAC_OK;
+}
+
+extern "C" int pcg_solve_noalloc(const bjac_csr *A, const bjac_handle *Mc, const double *b, double *x,
+                                 const bjac_solve_opts *opts, bjac_stats *stats, void *stream) {
+  int rc = check_solve(A, Mc, b, x, opts);
+  if (rc) return rc;
+  if (opts->profile) return BJAC_EINVAL;          // profile mode creates events
+  if (A->n > kNoAllocMaxRows) return BJAC_ENOMEM;  // beyond the static workspace
+  void *ws = nullptr;
+  if ((rc = noalloc_scratch(&ws))) return rc;
+  const SolveWs w = carve_solve(ws, A->n);         // 32-bit column indices: no room for the 16-bit copy
+  if (w.bytes > kNoAllocBytes) return BJAC_ENOMEM;
+  return solve_run(A, const_cast<bjac_handle *>(Mc), b, x, opts, w, ws, (hipStream_t)stream, false, stats);
+}
