@@ -64,20 +64,26 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def index_bytes(A):
-    """Bytes per column index the PCG SpMV reads: 2 when every entry lies within
-    32767 rows of its row (the solver's 16-bit row-relative copy), else 4."""
+def index_bytes(A, codes=True):
+    """Bytes per column index the PCG SpMV reads: 1 when the matrix has at
+    most 256 distinct offsets col - row (the solver's 8-bit dictionary codes;
+    codes=False for the batched SpMV, which has none), else 2 when every entry
+    lies within 32767 rows of its row (16-bit offsets), else 4 (the CSR's own
+    indices)."""
     import numpy as np
     rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.row_ptr.astype(np.int64)))
-    far = np.max(np.abs(A.col_idx.astype(np.int64) - rows)) if A.nnz else 0
+    d = A.col_idx.astype(np.int64) - rows
+    if codes and A.nnz and len(np.unique(d)) <= 256:
+        return 1
+    far = np.max(np.abs(d)) if A.nnz else 0
     return 2 if far <= 32767 else 4
 
 
 def spmv_bytes(n, nnz, ib=4):
     """Algorithmic bytes of one SpMV launch with the folded p update: CSR values
-    and column indices (ib bytes each), row pointers, z and p_old read once,
-    p_new and q written."""
-    return (8 + ib) * nnz + 4 * (n + 1) + 32 * n
+    and column indices (ib bytes each; 1 KiB of dictionary with 8-bit codes),
+    row pointers, z and p_old read once, p_new and q written."""
+    return (8 + ib) * nnz + 4 * (n + 1) + 32 * n + (1024 if ib == 1 else 0)
 
 
 def apply_bytes(n, nb, ntiles, stored_bytes, band=False):
@@ -420,7 +426,7 @@ def bench_batched(args):
     log("profile pass")
     _, rp16, _ = step(pol16, profile=True)
     info16 = M16.info()
-    kb = {"spmv": batched_spmv_bytes(n, nnz, veclen, index_bytes(st.A)), "apply": batched_apply_bytes(nb, info16["low_bytes"], veclen)}
+    kb = {"spmv": batched_spmv_bytes(n, nnz, veclen, index_bytes(st.A, codes=False)), "apply": batched_apply_bytes(nb, info16["low_bytes"], veclen)}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp16.kernel_ms[name]

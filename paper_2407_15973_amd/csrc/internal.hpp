@@ -37,8 +37,9 @@ struct alignas(64) PcgState {
   int32_t iter;      // x updates done; -1 before the first application
   int32_t maxit;
   int32_t status;    // 0 running, 1 converged, 2 maxit, -3 breakdown
-  int32_t rel16;     // 1: the SpMV may read the 16-bit row-relative column
-                     // indices (next to status: both come in one load)
+  int32_t cidx;      // compact column indices the SpMV reads (next to status:
+                     // both come in one load): 0 none (the CSR's 32-bit
+                     // indices), 1 16-bit col - row, 2 8-bit codes of col - row
   int32_t use_high;  // map for the next application (temporal switch)
   int32_t temporal;
   int32_t n_high;    // applications that used the FP64 map

@@ -183,8 +183,8 @@ __device__ __forceinline__ double sum_partials(double *p, int n, int stride, dou
   return out[0];
 }
 
-static_assert(offsetof(PcgState, rel16) == offsetof(PcgState, status) + 4 && offsetof(PcgState, status) % 8 == 0,
-              "status and rel16 are read as one 8-byte word");
+static_assert(offsetof(PcgState, cidx) == offsetof(PcgState, status) + 4 && offsetof(PcgState, status) % 8 == 0,
+              "status and cidx are read as one 8-byte word");
 
 // The 16-bit row-relative copy of A's column indices (col - row) read by the
 // PCG SpMVs; any entry farther than 32767 rows from its row clears *flag, and
@@ -200,6 +200,90 @@ __global__ __launch_bounds__(256) void off16_kernel(int n, const int32_t *rp, co
     }
   }
   if (!ok) __hip_atomic_store(flag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 8-bit codes of the column offsets. Structured matrices have a handful of
+// distinct offsets col - row (7 for a 7-point stencil), so a 256-entry
+// dictionary of them lets every entry's column be stored in one byte: the
+// code is the offset's slot in an open-addressing table (multiplicative hash,
+// linear probing). The table is built per workgroup in LDS (a read before
+// every compare-and-swap, so the few hot slots are rarely written) and merged
+// into the global table; more than 256 distinct offsets set *overflow.
+constexpr int kDictSize = 256;
+constexpr int kDictEmpty = (int)0x80000000;   // no offset col - row of an int32 CSR takes this value
+
+__device__ __forceinline__ unsigned dict_hash(int d) { return ((unsigned)d * 2654435761u) >> 24; }
+
+template <bool GLOBAL>
+__device__ __forceinline__ bool dict_insert(int *tab, int d) {
+  unsigned h = dict_hash(d);
+  for (int probe = 0; probe < kDictSize; ++probe, h = (h + 1) & (kDictSize - 1)) {
+    const int cur = GLOBAL ? __hip_atomic_load(tab + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : __hip_atomic_load(tab + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == d) return true;
+    if (cur == kDictEmpty) {
+      const int old = atomicCAS(tab + h, kDictEmpty, d);
+      if (old == kDictEmpty || old == d) return true;
+    }
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void dict_fill_kernel(int *gtab, int *overflow) {
+  gtab[threadIdx.x] = kDictEmpty;
+  if (threadIdx.x == 0) *overflow = 0;
+}
+
+__global__ __launch_bounds__(256) void dict_build_kernel(int n, const int32_t *rp, const int32_t *ci, int *gtab,
+                                                         int *overflow) {
+  __shared__ int tab[kDictSize];
+  __shared__ int ovf;
+  tab[threadIdx.x] = kDictEmpty;
+  if (threadIdx.x == 0) ovf = 0;
+  __syncthreads();
+  bool ok = true;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n && ok; i += gridDim.x * 256)
+    for (int k = rp[i]; k < rp[i + 1] && ok; ++k) ok = dict_insert<false>(tab, ci[k] - i);
+  if (!ok) ovf = 1;
+  __syncthreads();
+  const int d = tab[threadIdx.x];
+  if (!ovf && d != kDictEmpty && !dict_insert<true>(gtab, d)) ovf = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && ovf) __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The compact copy of A's column structure the PCG SpMVs read: the 8-bit
+// codes when the dictionary holds every offset (*cidx = 2), else the 16-bit
+// offsets col - row when all fit (*cidx stays 1), else none (*cidx = 0).
+// o8 and o16 share the workspace region.
+__global__ __launch_bounds__(256) void idx_encode_kernel(int n, const int32_t *rp, const int32_t *ci, const int *gtab,
+                                                         const int *overflow, uint8_t *o8, int16_t *o16,
+                                                         int32_t *cidx) {
+  __shared__ int tab[kDictSize];
+  tab[threadIdx.x] = gtab[threadIdx.x];
+  __syncthreads();
+  if (*overflow == 0) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        const int d = ci[k] - i;
+        unsigned h = dict_hash(d);
+        // present: the build inserted every offset (the probe count is bounded all the same)
+        for (int probe = 0; probe < kDictSize && tab[h] != d; ++probe) h = (h + 1) & (kDictSize - 1);
+        o8[k] = (uint8_t)h;
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) __hip_atomic_store(cidx, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  bool ok = true;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      const int d = ci[k] - i;
+      ok = ok && d >= -32768 && d <= 32767;
+      o16[k] = (int16_t)d;
+    }
+  }
+  if (!ok) __hip_atomic_store(cidx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
@@ -221,10 +305,19 @@ struct SpmvArgs {
   double *pnew, *q;
   PcgState *st;
   double *part;
-  const int16_t *o16;   // PCG: col - row of every entry, valid while st->rel16
+  const int16_t *o16;   // PCG / CG: col - row of every entry (st->cidx == 1), or its 8-bit code
+                        // (st->cidx == 2: the same region read as bytes)
+  const int *dict;      // the codes' dictionary: offset of code c at dict[c]
   int32_t nnz8;         // nnz rounded down to a multiple of 8: whole 16-byte chunks of every array
+  int32_t nnz16;        // nnz rounded down to a multiple of 16 (8-bit codes: 16 per chunk)
   int32_t vec;          // values and indices 16-byte aligned: tiles may be staged in 16-byte chunks
 };
+
+// Column index modes of the SpMV tiles: the CSR's 32-bit indices, 16-bit
+// offsets col - row, 8-bit codes of col - row.
+enum IdxMode { IX32 = 0, IX16 = 1, IX8 = 2 };
+template <int IX>
+using IdxT = std::conditional_t<IX == IX32, int32_t, std::conditional_t<IX == IX16, int16_t, uint8_t>>;
 
 // Dot product of one CSR row with p_new = z + beta p_old (the p update of PCG
 // folded into the product; PLAIN mode reads p = z). Seven entries at a time
@@ -234,10 +327,11 @@ struct SpmvArgs {
 // end are clamped to its last entry and their values replaced by zero, so
 // there is no branch inside a group. Also returns p_new of the row itself
 // when the row stores its diagonal.
-template <bool PCG, class IT, bool FIND = PCG>
+template <bool PCG, int IX, bool FIND = PCG>
 __device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
-                                          const IT *__restrict__ cidx, const double *__restrict__ vals, double beta,
-                                          int base, int len, int row, double &prow, bool &found, int roff) {
+                                          const IdxT<IX> *__restrict__ cidx, const double *__restrict__ vals,
+                                          double beta, int base, int len, int row, double &prow, bool &found,
+                                          const int *dict) {
   constexpr int U = 7;
   double acc = 0.0;
   for (int k0 = 0; k0 < len; k0 += U) {
@@ -246,7 +340,9 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int idx = base + min(k0 + k, len - 1);
-      cs[k] = (int)cidx[idx] + roff;   // roff = row when the indices are row-relative
+      if constexpr (IX == IX32) cs[k] = cidx[idx];
+      else if constexpr (IX == IX16) cs[k] = (int)cidx[idx] + row;
+      else cs[k] = dict[cidx[idx]] + row;
       const double v = vals[idx];
       vs[k] = (k0 + k < len) ? v : 0.0;
     }
@@ -291,17 +387,18 @@ struct Dots3 {
   double a = 0.0, b = 0.0, c = 0.0;
 };
 
-template <int SM, bool REL>
-__device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc) {
+template <int SM, int IX>
+__device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc, const int *dict) {
   constexpr bool PCG = SM == SPMV_PCG;   // p = z + beta p_old gathered, (p, q)
   constexpr bool CG = SM == SPMV_CG;     // u gathered, (r, r), (r, u), (w, u)
   constexpr int SLOT = kSpmvSlot;
-  constexpr int NV = SLOT * 8 / 16 / 64;                  // value chunks per lane
-  constexpr int NC = SLOT * (REL ? 2 : 4) / 16 / 64;      // index chunks per lane
-  constexpr int EV = 2, EC = REL ? 8 : 4;                 // entries per chunk
-  using IT = typename std::conditional<REL, int16_t, int32_t>::type;
+  using IT = IdxT<IX>;
+  constexpr int NV = SLOT * 8 / 16 / 64;                              // value chunks per lane
+  constexpr int NC = (SLOT * (int)sizeof(IT) + 16 * 64 - 1) / 16 / 64;  // index chunks per lane
+  constexpr int EV = 2, EC = 16 / (int)sizeof(IT);                    // entries per chunk
+  constexpr int GA = EC > 8 ? EC : 8;                                 // window alignment (entries)
   const int32_t *__restrict__ rp = a.rp;
-  const IT *__restrict__ cix = REL ? (const IT *)a.o16 : (const IT *)a.ci;
+  const IT *__restrict__ cix = IX == IX32 ? (const IT *)a.ci : (const IT *)a.o16;
   const double *__restrict__ vv_g = a.v;
   const double *__restrict__ z = a.z;
   const double *__restrict__ pold = a.pold;
@@ -328,11 +425,12 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
     const int e0 = __builtin_amdgcn_readlane(s, 0);
     const int last = min(a.n, t * 64 + 64) - 1 - t * 64;
     const int cnt = t < it.end ? __builtin_amdgcn_readlane(e, last) - e0 : 0;
-    base = e0 & ~7;
+    base = e0 & ~(GA - 1);
     need = e0 - base + cnt;
     // every chunk read starts below base + need and lies below base + need
-    // rounded up to 8 entries, which must not pass the last whole group
-    if (!a.vec || cnt <= 0 || need > SLOT || base + ((need + 7) & ~7) > a.nnz8) need = 0;
+    // rounded up to GA entries, which must not pass the last whole group
+    if (!a.vec || cnt <= 0 || need > SLOT || base + ((need + GA - 1) & ~(GA - 1)) > (GA == 8 ? a.nnz8 : a.nnz16))
+      need = 0;
   };
   auto stage = [&](int base, int need, u32x4 (&gv)[NV], u32x4 (&gc)[NC]) {
     const u32x4 zero = {0u, 0u, 0u, 0u};
@@ -388,12 +486,10 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
         if (c * EC < need_c) ((u32x4 *)sc)[c] = gc[q];
       }
       wave_lds_sync();
-      acc = row_dot<PCG, IT, PCG || CG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, REL ? row : 0);
+      acc = row_dot<PCG, IX, PCG || CG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, dict);
       wave_lds_sync();
-    } else if (REL) {
-      acc = row_dot<PCG, int16_t, PCG || CG>(z, pold, a.o16, vv_g, beta, s_c, len, row, prow, found, row);
     } else {
-      acc = row_dot<PCG, int32_t, PCG || CG>(z, pold, a.ci, vv_g, beta, s_c, len, row, prow, found, 0);
+      acc = row_dot<PCG, IX, PCG || CG>(z, pold, cix, vv_g, beta, s_c, len, row, prow, found, dict);
     }
     s_has = has;
     s_row = row;
@@ -485,18 +581,27 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   __shared__ __align__(16) int scs[4][SLOT];
   __shared__ double sh[4];
   __shared__ int flag, ok;
-  // status and rel16 are adjacent: one load before the early exit
+  __shared__ int sdict[kDictSize];
+  // status and cidx are adjacent: one load before the early exit
   int2 sr = make_int2(ST_RUNNING, 0);
   if (PCG || CG) sr = *(const int2 *)&a.st->status;
   if ((PCG || CG) && sr.x != ST_RUNNING) return;
   const double beta = PCG ? a.st->beta : 0.0;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ix = (PCG || CG) && a.o16 ? sr.y : IX32;   // uniform over the grid
   Dots3 dot;
   if constexpr (PCG || CG) {
-    if (a.o16 && sr.y) dot = spmv_tiles<SM, true>(a, beta, svs[wv], scs[wv]);
-    else dot = spmv_tiles<SM, false>(a, beta, svs[wv], scs[wv]);
+    if (ix == IX8) {
+      sdict[threadIdx.x] = a.dict[threadIdx.x];
+      __syncthreads();
+      dot = spmv_tiles<SM, IX8>(a, beta, svs[wv], scs[wv], sdict);
+    } else if (ix == IX16) {
+      dot = spmv_tiles<SM, IX16>(a, beta, svs[wv], scs[wv], sdict);
+    } else {
+      dot = spmv_tiles<SM, IX32>(a, beta, svs[wv], scs[wv], sdict);
+    }
   } else {
-    dot = spmv_tiles<SPMV_PLAIN, false>(a, beta, svs[wv], scs[wv]);
+    dot = spmv_tiles<SPMV_PLAIN, IX32>(a, beta, svs[wv], scs[wv], sdict);
   }
   if constexpr (PCG) {
     const double bs = block_sum(dot.a, sh);
@@ -1451,7 +1556,7 @@ __global__ __launch_bounds__(256) void apply_band_fast_kernel(ApplyArgs a) {
 __global__ void state_init_kernel(PcgState *st, double tol, int maxit, double adp_tol, int temporal,
                                   double *relres_hist, uint8_t *high_hist) {
   PcgState s{};
-  s.rel16 = 1;
+  s.cidx = 1;   // the index compaction kernels lower or raise it
   s.tol = tol;
   s.maxit = maxit;
   s.adp_tol = adp_tol;
@@ -1785,10 +1890,11 @@ int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_
 
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
                         PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr,
-                        const double *rv = nullptr) {
+                        const double *rv = nullptr, const int *dict = nullptr) {
   SpmvArgs a{};
   a.rv = rv;
   a.o16 = o16;
+  a.dict = dict;
   a.n = (int32_t)A->n;
   a.ntiles = (int)((A->n + kSpmvRows - 1) / kSpmvRows);
   a.rp = A->row_ptr;
@@ -1801,6 +1907,7 @@ static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, 
   a.st = st;
   a.part = part;
   a.nnz8 = (int32_t)(A->nnz & ~(int64_t)7);
+  a.nnz16 = (int32_t)(A->nnz & ~(int64_t)15);
   const uintptr_t al = (uintptr_t)A->val | (uintptr_t)A->col_idx | (uintptr_t)o16;
   a.vec = (al & 15) == 0;
   if (mode == SPMV_PCG) {
@@ -1951,7 +2058,8 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
 struct SolveWs {
   double *r, *z, *pa, *pb, *q, *part1, *part2, *part3;
   PcgState *st;
-  int16_t *o16;   // [nnz] row-relative column indices, or null
+  int16_t *o16;   // [nnz] row-relative column indices (or their 8-bit codes), or null
+  int *dict;      // [256] the codes' dictionary, then the overflow flag
   size_t bytes;
 };
 
@@ -1968,6 +2076,7 @@ static SolveWs carve_solve(void *ws, int64_t n, int64_t nnz16 = 0) {
   w.part3 = c.take<double>(kMaxGrid);      // true-residual partials
   w.st = c.take<PcgState>(1);
   w.o16 = nnz16 > 0 ? c.take<int16_t>(nnz16) : nullptr;
+  w.dict = nnz16 > 0 ? c.take<int>(kDictSize + 64) : nullptr;
   w.bytes = c.used;
   return w;
 }
@@ -2040,11 +2149,11 @@ static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x
                               const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg = false) {
   if (ev) (void)hipEventRecord(ev[0], s);
   if (cg) {
-    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r);
+    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict);
     enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr);
     return;
   }
-  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16);
+  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict);
   enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr);
 }
 
@@ -2190,7 +2299,15 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
   }
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(1), 0, s, w.st, opts->tol, opts->maxit, M->policy.adp_tol,
                      M->policy.temporal, opts->relres_hist, opts->high_hist);
-  if (w.o16) launch_off16((int)A->n, A->row_ptr, A->col_idx, w.o16, &w.st->rel16, s);
+  if (w.o16) {
+    // the compact copy of the column structure: 8-bit codes or 16-bit offsets
+    const int n = (int)A->n, G = poly_grid(n);
+    hipLaunchKernelGGL(dict_fill_kernel, dim3(1), dim3(kDictSize), 0, s, w.dict, w.dict + kDictSize);
+    hipLaunchKernelGGL(dict_build_kernel, dim3(G), dim3(256), 0, s, n, A->row_ptr, A->col_idx, w.dict,
+                       w.dict + kDictSize);
+    hipLaunchKernelGGL(idx_encode_kernel, dim3(G), dim3(256), 0, s, n, A->row_ptr, A->col_idx, (const int *)w.dict,
+                       (const int *)(w.dict + kDictSize), (uint8_t *)w.o16, w.o16, &w.st->cidx);
+  }
   hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q,
                      cg ? w.z : nullptr, cg ? w.pb : nullptr);
   hipLaunchKernelGGL(fill_empty_kernel, dim3(24), dim3(256), 0, s, w.part1, 3 * kMaxGrid);

@@ -265,8 +265,9 @@ def _solve_pair(A, bp, b, maxit, pol=None):
 
 
 def test_compact_column_index_gives_identical_iterates():
-    # the 16-bit row-relative copy of the column indices changes only the bytes
-    # the SpMV reads: the same products in the same order, identical iterates
+    # the compact copy of the column indices (8-bit dictionary codes of
+    # col - row here: 7 distinct offsets) changes only the bytes the SpMV
+    # reads: the same products in the same order, identical iterates
     rng = np.random.default_rng(23)
     A = gen.diffusion3d(gen.kappa_loguniform((14, 12, 10), rng))
     b = rng.uniform(-1, 1, A.n)
@@ -308,9 +309,46 @@ def test_unaligned_matrix_arrays_read_unstaged_with_identical_iterates():
         assert np.array_equal(r.x.cpu().numpy(), out[0].x.cpu().numpy())
 
 
+def _random_sparse_spd(n, per_row, far, rng):
+    # diagonally dominant SPD matrix with `per_row` random couplings per row,
+    # columns up to `far` rows away: hundreds of distinct offsets col - row
+    rows = np.repeat(np.arange(n), per_row)
+    cols = (rows + rng.integers(-far, far + 1, size=rows.size)) % n
+    keep = cols != rows
+    rows, cols = rows[keep], cols[keep]
+    vals = -rng.uniform(0.1, 1.0, size=rows.size)
+    r = np.concatenate([rows, cols])
+    c = np.concatenate([cols, rows])
+    v = np.concatenate([vals, vals])
+    import scipy.sparse as sp
+    S = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+    S.sum_duplicates()
+    S = S + sp.diags(np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)
+    S = S.tocsr()
+    S.sort_indices()
+    return gen.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data)
+
+
+@pytest.mark.parametrize("n,far", [(6000, 3000), (70000, 35000)])
+def test_compact_column_index_beyond_the_dictionary(n, far):
+    # more than 256 distinct offsets: the dictionary overflows and the products
+    # read the 16-bit offsets (n = 6000) or the CSR's 32-bit indices (offsets
+    # beyond 16 bits), identical to the plain workspace either way
+    rng = np.random.default_rng(25)
+    A = _random_sparse_spd(n, 3, far, rng)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    assert len(np.unique(A.col_idx - rows)) > 256
+    b = rng.uniform(-1, 1, A.n)
+    r1, r2 = _solve_pair(A, gen.uniform_blocks(A.n, 32), b, 500)
+    assert r1.status == mb.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.relres_hist, r2.relres_hist)
+    assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
+
+
 def test_compact_column_index_falls_back_for_far_couplings():
-    # a 33000 x 2 grid couples rows 33000 apart, beyond 16 bits: the products
-    # keep the 32-bit indices, still identical to the plain workspace
+    # a 33000 x 2 grid couples rows 33000 apart, beyond 16 bits, with five
+    # distinct offsets: the products read the 8-bit codes, identical to the
+    # plain workspace
     A = gen.poisson2d(33000, 2)
     rng = np.random.default_rng(24)
     b = rng.uniform(-1, 1, A.n)
