@@ -19,4 +19,6 @@ blocks     diagonal-block extraction, textbook Cholesky inverse, block
 pcg        preconditioned CG with fMP / aMP(hl) / aMP(lh), the paper's
            polynomial BJAC(k, t) with inner Jacobi sweeps
 mlp        16-64-64-3 ReLU MLP, softmax cross-entropy, backward, Adam
+labels     per-block precision labels from the method's own runs (a ladder
+           of global tolerances, the largest whose delay stays within 5 %)
 """
