@@ -94,32 +94,6 @@ def apply_bytes(n, nb, ntiles, stored_bytes, band=False):
     return stored_bytes + (22 if band else 21) * nb + 4 * (ntiles + 1) + 56 * n
 
 
-def cpu_baseline(p, iters_hint, budget_iters=8):
-    """The oracle as it stands on the host: full FP64 setup of every block and
-    FP16 storage, then a few PCG iterations; scaled to a full solve with the
-    GPU's iteration count. BLAS limited to one thread."""
-    import numpy as np
-    from threadpoolctl import threadpool_limits
-
-    from oracle import blocks as OB
-    from oracle import pcg as OP
-    from oracle import precision as OPr
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        nb = len(p.block_ptr) - 1
-        M = OP.BJAC(p.A, p.block_ptr, np.full(nb, OPr.FP16, np.uint8))
-        t1 = time.perf_counter()
-        S = p.A.to_scipy()
-        res = OP.pcg(lambda v: S @ v, p.b, M.low, 0.0, budget_iters)
-        t2 = time.perf_counter()
-    per_iter = (t2 - t1) / max(1, res.iters)
-    total_ms = 1e3 * ((t1 - t0) + per_iter * iters_hint)
-    return {"value": total_ms, "unit": "ms", "cores": 1, "kind": "oracle",
-            "sample": f"oracle setup of all {nb} blocks (Cholesky inverse, FP16 storage) "
-                      f"{(t1 - t0):.1f} s + {res.iters} PCG iterations at {per_iter * 1e3:.0f} ms each, "
-                      f"scaled to {iters_hint} iterations"}
-
-
 METRIC = "PCG time-to-1e-10 residual + BJAC-apply HBM GB/s, mixed/learned vs FP64"
 # every timed solve checks ||b - A x|| / ||b|| <= tol in FP64 on the device and
 # restarts from the true residual (at most this many times) when it is above
@@ -129,7 +103,10 @@ VERIFY = 3
 # FETCH_SIZE / WRITE_SIZE runs (profiles/, scaled by a 1 GiB copy), keyed by
 # workload and kernel. Valid only for the kernel sources they were measured
 # on: reported when the digest of those sources matches, null otherwise.
-TRAFFIC = {}
+TRAFFIC = {
+    "heldout_192:apply": ("1c98752db4f5c5db44f888fd054fa46330afbddc5ae3fb91edc2725d078ee668", 851017765),
+    "heldout_192:spmv": ("1c98752db4f5c5db44f888fd054fa46330afbddc5ae3fb91edc2725d078ee668", 754355794),
+}
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
 
@@ -161,28 +138,45 @@ def calibration_copy():
     log("calibration copy: 1 GiB read, 1 GiB written")
 
 
-def stream_ceilings(dev, gib=1):
-    """Achievable streaming rates of this GPU, measured with PyTorch's own
-    kernels on gib-GiB FP64 tensors: a reduction (read only), a fill (write
-    only) and a copy (read + write). Context for the roofline fraction: the
-    hot kernels mix reads and writes like the copy."""
+def stream_ceilings(dev, mib=512):
+    """Achievable streaming rates of this GPU for the read:write mixes of the
+    hot kernels, measured with the library's streaming probe
+    (bjac_stream_probe) on eight or fewer `mib`-MiB FP64 streams (several GiB
+    in all, far beyond the 256 MiB Infinity Cache): read only, write only,
+    copy (1:1), 4 reads : 1 write (the fused update + application reads about
+    four bytes per byte written) and 6:1 (the SpMV). Each mix takes the best
+    of a few launch shapes (grid of 1024 to 8192 workgroups, 1 to 4 accesses
+    per lane and stream in flight), each timed as the median of 3 launches;
+    bytes = streams x stream size."""
     import torch
-    n = gib * (2 ** 30) // 8
-    a = torch.ones(n, dtype=torch.float64, device=dev)
-    b = torch.empty_like(a)
-    out = {}
-    for name, fn, nbytes in (("read", lambda: a.sum(), n * 8), ("write", lambda: b.fill_(2.0), n * 8),
-                             ("copy", lambda: b.copy_(a), 2 * n * 8)):
-        fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            fn()
-        e1.record()
-        e1.synchronize()
-        out[name] = nbytes * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
+
+    from paper_2407_15973_amd import binding as mb
+    n = mib * (2 ** 20) // 8
+    bufs = [torch.ones(n, dtype=torch.float64, device=dev) for _ in range(8)]
+    sink = torch.empty(8192 * 256, dtype=torch.float64, device=dev)
+    out, shape = {}, {}
+    for name, ni, no in (("read", 8, 0), ("write", 0, 2), ("copy", 1, 1), ("r4w1", 4, 1), ("r6w1", 6, 1)):
+        ins, outs = bufs[:ni], bufs[ni:ni + no] if ni else bufs[:no]
+        best = 0.0
+        for grid in (1024, 2048, 4096, 8192):
+            for unroll in (1, 2, 4):
+                mb.stream_probe(ins, outs, grid=grid, unroll=unroll, sink=sink)
+                ts = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    mb.stream_probe(ins, outs, grid=grid, unroll=unroll, sink=sink)
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                ts.sort()
+                rate = (ni + no) * n * 8 / ts[1] / 1e9
+                if rate > best:
+                    best, shape[name] = rate, (grid, unroll)
+        out[name] = best
+    del bufs, sink
     torch.cuda.empty_cache()
+    out["shapes"] = shape
     return out
 
 
@@ -266,10 +260,11 @@ def bench_diff3d(args):
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(p, r16.iters)
+        cpu = cpu_baseline_full(p, r16.iters)
     ceil = stream_ceilings(dev)
-    roofline["copy_ceiling_gbs"] = ceil["copy"]
-    roofline["frac_of_copy_ceiling"] = dk["gbs"] / ceil["copy"]
+    mix = ceil["r6w1"] if dom == "spmv" else ceil["r4w1"]
+    roofline["mix_ceiling_gbs"] = mix
+    roofline["frac_of_mix_ceiling"] = dk["gbs"] / mix
 
     line = {
         "metric": METRIC,
@@ -307,9 +302,13 @@ def batched_apply_bytes(nb, stored_bytes, veclen):
 
 
 def cpu_baseline_batched(st, col_iters, nsample=2, budget_iters=8):
-    """Oracle on the first ``nsample`` systems: block setup (FP16 storage) and
-    a few PCG iterations of every column; scaled by rows (setup) and by
-    rows x iterations summed over every column of the batch (solve)."""
+    """Oracle on the first ``nsample`` systems, thread pools set to the host's
+    core count: block setup (FP16 storage) and a few PCG iterations of every
+    column; scaled by rows (setup) and by rows x iterations summed over every
+    column of the batch (solve). `cores` is the oracle's CPU time over its
+    wall time."""
+    import resource
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -319,7 +318,10 @@ def cpu_baseline_batched(st, col_iters, nsample=2, budget_iters=8):
     rows_s = np.diff(st.sys_row).astype(np.int64)
     t_setup = t_iter = 0.0
     row_sample = row_iter_sample = 0
-    with threadpool_limits(limits=1):
+    ncores, model = host_cores()
+    ru0 = resource.getrusage(resource.RUSAGE_SELF)
+    w0 = time.perf_counter()
+    with threadpool_limits(limits=ncores):
         for s in range(nsample):
             r0, r1 = int(st.sys_row[s]), int(st.sys_row[s + 1])
             k0, k1 = (int(np.searchsorted(st.block_ptr, v)) for v in (r0, r1))
@@ -344,7 +346,10 @@ def cpu_baseline_batched(st, col_iters, nsample=2, budget_iters=8):
     col_rows = np.repeat(rows_s, st.sys_m)
     total_row_iters = float(np.sum(col_rows * np.asarray(col_iters, dtype=np.int64)))
     est = t_setup / row_sample * rows_s.sum() + t_iter / row_iter_sample * total_row_iters
-    return {"value": est * 1e3, "unit": "ms", "cores": 1, "kind": "oracle",
+    ru1 = resource.getrusage(resource.RUSAGE_SELF)
+    used = (ru1.ru_utime + ru1.ru_stime - ru0.ru_utime - ru0.ru_stime) / max(1e-9, time.perf_counter() - w0)
+    return {"value": est * 1e3, "unit": "ms", "cores": max(1, round(used)), "kind": "oracle",
+            "host_cores": ncores, "host_cpu": model, "threads_allowed": ncores,
             "sample": f"oracle setup + {budget_iters} PCG iterations per column on the first {nsample} systems "
                       f"({row_sample} rows, {t_setup + t_iter:.1f} s), scaled by rows (setup) and by "
                       f"rows x iterations of every column (solve)"}
@@ -676,6 +681,9 @@ def bench_policies(args):
     torch.cuda.empty_cache()
     extra = bench_config2_keys(args) if (selector_mode and not args.no_config2) else None
     ceil = stream_ceilings(dev)
+    mix = ceil["r6w1"] if dom == "spmv" else ceil["r4w1"]
+    roofline["mix_ceiling_gbs"] = mix
+    roofline["frac_of_mix_ceiling"] = dk["gbs"] / mix
     return {
         "metric": METRIC, "value": hv["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": hv["ms_per_step"], "higher_is_better": False, "scaling": "weak",
@@ -823,7 +831,7 @@ def bench_band(args):
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        cpu = cpu_baseline(p, rows[head]["iters"])
+        cpu = cpu_baseline_full(p, rows[head]["iters"])
     hv = rows[head]
     return {
         "metric": METRIC, "value": hv["ms_per_step"], "unit": "ms", "n_gpus": 1, "steps": args.steps,

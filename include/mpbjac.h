@@ -311,6 +311,20 @@ int pcg_solve(const bjac_csr *A, const bjac_handle *M, const double *b, double *
               const bjac_solve_opts *opts, void *workspace, size_t workspace_bytes,
               bjac_stats *stats, void *stream);
 
+/* ---- streaming probe (a measurement aid, not a step of the method) ------
+ * The HBM rate a plain streaming kernel reaches for a mix of n_in read and
+ * n_out write streams (0..8, 0..2, at least one), the practical ceiling the
+ * hot kernels' roofline fractions are read against: the SpMV reads about six
+ * bytes for each one it writes, the fused update + application about four.
+ * in[n_in], out[n_out]: HOST arrays of device pointers to `count` doubles
+ * each (16-byte aligned, count even); out[j][i] = sum_k in[k][i] + j, with
+ * non-temporal loads and stores, `unroll` (1, 2 or 4) 16-byte accesses per
+ * lane and stream in flight, grid-stride over `grid` workgroups of 256
+ * (0 = 8192). The read-only mix (n_out = 0) writes one double per thread to
+ * sink (device, grid * 256 doubles). */
+int bjac_stream_probe(const double *const *in, int32_t n_in, double *const *out, int32_t n_out,
+                      int64_t count, int32_t grid, int32_t unroll, double *sink, void *stream);
+
 /* ---- PCG without allocation --------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): pcg_solve

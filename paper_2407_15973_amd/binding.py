@@ -34,7 +34,7 @@ SYMBOLS = (
     "bjac_spmv", "bjac_round", "pcg_workspace_query", "pcg_workspace_query_csr", "pcg_solve", "bjac_mlp_forward",
     "bjac_mlp_workspace_query", "bjac_mlp_backward", "bjac_mlp_adam",
     "pcg_batched_workspace_query", "pcg_solve_batched", "pcg_batched_tune", "bjac_apply_multi",
-    "bjac_poly_setup_query", "bjac_poly_setup", "pcg_solve_noalloc",
+    "bjac_poly_setup_query", "bjac_poly_setup", "pcg_solve_noalloc", "bjac_stream_probe",
 )
 
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "pcg_workspace_query_csr": (C.c_int, [P(bjac_csr), P(sz)]),
         "pcg_solve": (C.c_int, [P(bjac_csr), vp, vp, vp, P(bjac_solve_opts), vp, sz, P(bjac_stats), vp]),
         "pcg_solve_noalloc": (C.c_int, [P(bjac_csr), vp, vp, vp, P(bjac_solve_opts), P(bjac_stats), vp]),
+        "bjac_stream_probe": (C.c_int, [vp, i32, vp, i32, C.c_int64, i32, i32, vp, vp]),
         "bjac_mlp_forward": (C.c_int, [vp, vp, i32, vp, vp, vp]),
         "bjac_mlp_workspace_query": (C.c_int, [i32, P(sz)]),
         "bjac_mlp_backward": (C.c_int, [vp, vp, vp, i32, vp, vp, vp, sz, vp]),
@@ -374,6 +375,16 @@ def solve_noalloc(A: DeviceCSR, M: BlockJacobi, b, x, tol=1e-10, maxit=5000, chu
         raise MpbjacError(rc, "pcg_solve_noalloc")
     return SolveResult(x, st.iters, rc, st.relres, st.rnorm0, st.high_applications, st.graph_launches,
                        st.solve_ms, restarts=st.restarts, true_relres=st.true_relres)
+
+
+def stream_probe(ins, outs, grid=0, unroll=1, sink=None):
+    """bjac_stream_probe on lists of equal-length device FP64 tensors (one
+    launch on the current stream)."""
+    n = (ins[0] if ins else outs[0]).numel()
+    pin = (C.c_void_p * max(1, len(ins)))(*[t.data_ptr() for t in ins])
+    pout = (C.c_void_p * max(1, len(outs)))(*[t.data_ptr() for t in outs])
+    _check(load().bjac_stream_probe(pin, len(ins), pout, len(outs), n, grid, unroll, _ptr(sink), _stream()),
+           "bjac_stream_probe")
 
 
 # ------------------------------------------------------------------- MLP

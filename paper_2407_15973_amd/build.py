@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmpbjac.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["setup.hip", "solve.hip", "batched.hip", "poly.hip", "mlp.hip", "api.cpp"]
+SOURCES = ["setup.hip", "solve.hip", "batched.hip", "poly.hip", "mlp.hip", "probe.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

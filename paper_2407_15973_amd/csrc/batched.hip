@@ -78,6 +78,8 @@ struct BSpmvArgs {
   const int32_t *sched;   // [9] chunk run of each XCD
   const int16_t *o16;     // col - row of every entry (16-bit copy), read while *rel16
   const int32_t *rel16;
+  int32_t nnz8;           // nnz rounded down to 8: whole 16-byte chunks of every array
+  int32_t vec;            // values and indices 16-byte aligned: tiles may be staged in 16-byte chunks
 };
 
 // floor(e / m) for 0 <= e < 4096 and 1 <= m <= 8 (multiply by ceil(2^16/m);
@@ -95,11 +97,15 @@ __device__ __forceinline__ int div_small(int e, int m) {
 // row read its CSR entries from LDS. q = A p with p = z + beta p_old formed
 // at every read; p_new is the diagonal term's p. H elements per lane are in
 // flight together.
+constexpr int kBSlot = 512;   // LDS entries per wave: a tile's CSR window in 16-byte chunks
+
 struct SpmvLds {
-  double v[kSpmvNnzCap];
-  int c[kSpmvNnzCap];
+  __align__(16) double v[kBSlot];
+  __align__(16) int c[kBSlot];   // 32-bit indices, or the 16-bit copy in the first half
   int rp[kBWaveRows + 1];
 };
+
+using bu32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
 template <int VW>
 struct VecT;
@@ -149,9 +155,45 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
     const int e0 = __builtin_amdgcn_readfirstlane(a.rp[r0]);
     const int cnt = __builtin_amdgcn_readfirstlane(a.rp[r1]) - e0;
     const int rpl = a.rp[r0 + min(lane, nr)] - e0;
+    // 16-byte chunks from the 8-entry boundary at or below the tile's first
+    // entry (4 loads of values, 1 or 2 of indices per lane instead of one per
+    // entry and array), when the window fits the slice and lies below the
+    // last whole 8-entry group; otherwise one entry per lane and load
+    constexpr int SL = kBSlot;
+    constexpr int NV = SL * 8 / 16 / 64, NC = SL * (REL ? 2 : 4) / 16 / 64;
+    constexpr int EV = 2, EC = REL ? 8 : 4;
+    const int base = e0 & ~7;
+    const int need = e0 - base + cnt;
+    const bool chunked = a.vec && cnt > 0 && need <= SL && base + ((need + 7) & ~7) <= a.nnz8;
     // cnt = 0 (all rows empty): no entry is read below
-    const bool staged = cnt > 0 && cnt <= CAP;
-    if (staged) {
+    const bool staged = chunked || (cnt > 0 && cnt <= CAP);
+    const int soff = chunked ? e0 - base : 0;   // LDS position of the tile's first entry
+    if (chunked) {
+      const bu32x4 zero = {0u, 0u, 0u, 0u};
+      const bu32x4 *vp = (const bu32x4 *)(a.v + base);
+      const bu32x4 *cp = REL ? (const bu32x4 *)(a.o16 + base) : (const bu32x4 *)(a.ci + base);
+      bu32x4 gv[NV], gc[NC];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int c = lane + 64 * q;
+        gv[q] = c * EV < need ? __builtin_nontemporal_load(vp + c) : zero;
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = lane + 64 * q;
+        gc[q] = c * EC < need ? __builtin_nontemporal_load(cp + c) : zero;
+      }
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EV < need) ((bu32x4 *)L.v)[c] = gv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EC < need) ((bu32x4 *)L.c)[c] = gc[q];
+      }
+    } else if (staged) {
       double vv[NL];
       int cc[NL];
 #pragma unroll
@@ -206,8 +248,11 @@ __device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, S
           for (int k = 0; k < U; ++k) {
             const int idx = min(sidx[h] + min(k0 + k, max(len[h] - 1, 0)), cnt - 1);
             const bool ok = k0 + k < len[h];
-            cs[h][k] = staged ? L.c[idx] + (REL ? r0 + row[h] : 0) : a.ci[e0 + idx];
-            const double vv = staged ? L.v[idx] : a.v[e0 + idx];
+            int cl;
+            if (chunked) cl = REL ? (int)((const int16_t *)L.c)[soff + idx] : L.c[soff + idx];
+            else cl = staged ? L.c[idx] : a.ci[e0 + idx];
+            cs[h][k] = cl + (staged && REL ? r0 + row[h] : 0);
+            const double vv = staged ? L.v[soff + idx] : a.v[e0 + idx];
             vs[h][k] = ok ? vv : 0.0;
           }
 #pragma unroll
@@ -1128,6 +1173,8 @@ static void benq_spmv_k(const BCtx &c, const double *pold, double *pnew, hipStre
   a.sched = c.sched1;
   a.o16 = c.w.o16;
   a.rel16 = c.w.rel16;
+  a.nnz8 = (int32_t)(c.A->nnz & ~(int64_t)7);
+  a.vec = (((uintptr_t)c.A->val | (uintptr_t)c.A->col_idx | (uintptr_t)c.w.o16) & 15) == 0;
   if (c.ilp == 1)
     hipLaunchKernelGGL(bspmv_kernel<1>, dim3(c.G1), dim3(256), 0, s, a);
   else

@@ -20,7 +20,14 @@ relative residual 1e-10 (Sec. 4.2), the status, the final recursive and true
 relative residuals, the map's histogram, the solution's 2-norm and its values
 at 1024 seeded sample rows (for the ||x - x_oracle|| / ||x_oracle|| report).
 
-Usage: python tests/golden/make_oracle_iters.py <workload> <map>
+Perturbations (a third argument; the file name gains _<perturbation>): the
+same solve after a change of the inputs at the level of FP64 rounding, to
+measure how far the iteration count of a long CG moves under rounding alone:
+  b1ulp   every b_i times (1 + s_i 2^-52), s_i = +-1 from a fixed seed
+  upper   every block inverse replaced by its upper triangle mirrored (the
+          symmetric storage of the GPU path keeps only that triangle)
+
+Usage: python tests/golden/make_oracle_iters.py <workload> <map> [perturbation]
 Runtime (one core): minutes at 128^3, about half an hour per map at 160^3 and
 an hour at 192^3.
 """
@@ -56,12 +63,20 @@ def sample_rows(n: int) -> np.ndarray:
     return np.sort(np.random.default_rng(12345).choice(n, size=min(n, NSAMPLE), replace=False))
 
 
-def main(workload: str, pmap: str) -> None:
+PERTURBATIONS = ("b1ulp", "upper")
+
+
+def main(workload: str, pmap: str, perturb: str | None = None) -> None:
     t0 = time.perf_counter()
     p = WORKLOADS[workload]()
+    if perturb == "b1ulp":
+        sgn = np.random.default_rng(4242).choice([-1.0, 1.0], size=p.b.size)
+        p.b = p.b * (1.0 + sgn * 2.0 ** -52)
     nb = len(p.block_ptr) - 1
     print(f"[golden] {workload} {pmap}: n = {p.A.n}, nnz = {p.A.nnz}, blocks = {nb}", flush=True)
     H = OB.invert_blocks(p.A, p.block_ptr)
+    if perturb == "upper":
+        H = [np.triu(h) + np.triu(h, 1).T for h in H]
     if pmap == "fp64":
         tags = np.full(nb, OPr.FP64, np.uint8)
     elif pmap == "fp32":
@@ -91,7 +106,7 @@ def main(workload: str, pmap: str) -> None:
     out = {
         "source": "oracle/ (textbook PCG, x0 = 0, recursive relres stopping test of Sec. 4.2) "
                   "written by tests/golden/make_oracle_iters.py",
-        "workload": p.name, "seed_workload": workload, "map": pmap,
+        "workload": p.name, "seed_workload": workload, "map": pmap, "perturbation": perturb,
         "n": int(p.A.n), "nnz": int(p.A.nnz), "blocks": nb, "tol": p.tol, "maxit": p.maxit,
         "iters": int(res.iters), "status": int(res.status), "relres": float(res.relres),
         "true_relres": OP.true_relres(p.A, res.x, p.b),
@@ -100,7 +115,8 @@ def main(workload: str, pmap: str) -> None:
         "sample_rows": [int(v) for v in rows], "x_sample": [float(v) for v in res.x[rows]],
         "setup_s": t1 - t0, "solve_s": t2 - t1,
     }
-    path = os.path.join(HERE, f"oracle_iters_{workload}_{pmap}.json")
+    suffix = f"_{perturb}" if perturb else ""
+    path = os.path.join(HERE, f"oracle_iters_{workload}_{pmap}{suffix}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -109,6 +125,7 @@ def main(workload: str, pmap: str) -> None:
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 3 or sys.argv[1] not in WORKLOADS or sys.argv[2] not in MAPS:
-        sys.exit(f"usage: {sys.argv[0]} {{{','.join(WORKLOADS)}}} {{{','.join(MAPS)}}}")
-    main(sys.argv[1], sys.argv[2])
+    if (len(sys.argv) not in (3, 4) or sys.argv[1] not in WORKLOADS or sys.argv[2] not in MAPS
+            or (len(sys.argv) == 4 and sys.argv[3] not in PERTURBATIONS)):
+        sys.exit(f"usage: {sys.argv[0]} {{{','.join(WORKLOADS)}}} {{{','.join(MAPS)}}} [{{{','.join(PERTURBATIONS)}}}]")
+    main(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) == 4 else None)
