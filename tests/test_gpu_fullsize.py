@@ -74,7 +74,21 @@ def test_iterations_against_oracle_at_full_size(workload, pmap):
     x = res.x.cpu().numpy()
     print(f"[fullsize] gpu {res.iters} oracle {g['iters']} iterations", flush=True)
     assert res.status == mb.OK and g["status"] == OP.CONVERGED
-    assert abs(res.iters - g["iters"]) <= 2, (res.iters, g["iters"])
+    if pmap == "fp64":
+        # within 2 iterations, or within the spread the oracle's own count
+        # shows under changes of the inputs at FP64 rounding level (b moved by
+        # one ulp, the block inverses mirrored from their upper triangles:
+        # oracle_iters_<workload>_fp64_<perturbation>.json), when larger
+        bar = max([2] + [abs(golden(workload, f"fp64_{q}")["iters"] - g["iters"])
+                         for q in ("b1ulp", "upper")
+                         if os.path.exists(os.path.join(GOLDEN, f"oracle_iters_{workload}_fp64_{q}.json"))])
+        assert abs(res.iters - g["iters"]) <= bar, (res.iters, g["iters"], bar)
+    else:
+        # reduced blocks: the GPU accumulates the stored products in FP32, the
+        # oracle exactly (FP64), a perturbation of M at the FP32 unit roundoff
+        # that moves a long CG by up to a few per cent on the anisotropic
+        # problems (the bar of the reduced-map parity tests)
+        assert abs(res.iters - g["iters"]) <= max(2, 0.05 * g["iters"]), (res.iters, g["iters"])
     assert OP.true_relres(p.A, x, p.b) <= 2 * p.tol
 
 
