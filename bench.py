@@ -669,8 +669,12 @@ def bench_policies(args):
     dk = kern[dom]
     iter_bytes = kb["spmv"] + kb["apply"]
     pair_gbs = iter_bytes / ((kern["spmv"]["avg_us"] + kern["apply"]["avg_us"]) * 1e-6) / 1e9
+    traffic = measured_traffic(f"{gkey}:{dom}") if gkey else None
     roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(f"{gkey}:{dom}") if gkey else None,
+                "frac": dk["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                "traffic_source": ("rocprofv3 FETCH_SIZE and WRITE_SIZE runs of the same kernel sources "
+                                   f"(profiles/hbm_traffic_heldout_192_b48.md), not measured in this run")
+                if traffic else None,
                 "kernel": f"{dom}_kernel", "bytes_per_launch": dk["bytes"], "avg_launch_us": dk["avg_us"]}
     cpu = None
     if not args.no_cpu_baseline:
@@ -680,6 +684,7 @@ def bench_policies(args):
     del M, A, b, solver
     torch.cuda.empty_cache()
     extra = bench_config2_keys(args) if (selector_mode and not args.no_config2) else None
+    small = bench_config1_keys() if (selector_mode and not args.no_config2) else None
     ceil = stream_ceilings(dev)
     mix = ceil["r6w1"] if dom == "spmv" else ceil["r4w1"]
     roofline["mix_ceiling_gbs"] = mix
@@ -703,8 +708,50 @@ def bench_policies(args):
         "us_per_iter": hv["solve_ms"] * 1e3 / max(1, hv["iters"]), "bytes_per_iter": iter_bytes,
         "apply_spmv_gbs": pair_gbs, "apply_spmv_frac": pair_gbs / HBM_PEAK_GBS,
         "kernels": kern, "roofline": roofline, "cpu_baseline": cpu, "stream_ceilings_gbs": ceil,
-        "diff3d_128": extra,
+        "diff3d_128": extra, "poisson_64": small,
     }
+
+
+def bench_config1_keys():
+    """The 2D Poisson 64x64 workload (4,096 rows, blocks of 64, tol 1e-8) as
+    extra keys of the default line: latency-bound (a 2.7 MB working set), so
+    microseconds per iteration and per solve, FP64 map, against the oracle's
+    iteration count."""
+    import numpy as np
+    import torch
+
+    from paper_2407_15973_amd import binding as mb
+    from paper_2407_15973_amd import gen
+
+    dev = "cuda:0"
+    p = gen.config1(seed=0)
+    A = mb.DeviceCSR(p.A, dev)
+    b = torch.as_tensor(p.b, device=dev)
+    solver = mb.Solver(p.A.n, dev)
+    M = mb.BlockJacobi(A, p.block_ptr, mb.Policy(mode=mb.UNIFORM))
+    for _ in range(3):
+        solver.solve(A, M, b, tol=p.tol, maxit=p.maxit)
+    torch.cuda.synchronize()
+    reps = 20
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = solver.solve(A, M, b, tol=p.tol, maxit=p.maxit)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / reps
+    ts = time.perf_counter()
+    for _ in range(reps):
+        Ms = mb.BlockJacobi(A, p.block_ptr, mb.Policy(mode=mb.UNIFORM))
+        rs = solver.solve(A, Ms, b, tol=p.tol, maxit=p.maxit)
+    torch.cuda.synchronize()
+    us_step = (time.perf_counter() - ts) * 1e6 / reps
+    S = p.A.to_scipy()
+    g = oracle_golden("poisson_64", "fp64")
+    log(f"64x64 Poisson: {us:.0f} us per solve, {res.iters} iterations")
+    return {"workload": p.name, "n": p.A.n, "nnz": p.A.nnz, "tol": p.tol, "map": "fp64",
+            "iters": res.iters, "iters_oracle": g["iters"] if g else None,
+            "us_per_solve": us, "us_per_iter": us / max(1, res.iters), "us_per_step_with_setup": us_step,
+            "true_relres": float(np.linalg.norm(p.b - S @ res.x.cpu().numpy()) / np.linalg.norm(p.b)),
+            "x_rel_err_vs_oracle": x_err_vs_oracle(g, res.x.cpu().numpy())}
 
 
 def bench_config2_keys(args):

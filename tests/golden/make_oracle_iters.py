@@ -6,6 +6,8 @@ value here comes from the GPU library. One invocation solves one (workload,
 precision map) pair and writes ``oracle_iters_<workload>_<map>.json`` beside
 this script:
 
+  poisson_64   2D 5-point Poisson 64x64, blocks of 64 (grid lines), seed 0,
+               relative residual 1e-8 (the latency-bound small workload)
   diff3d_128   3D 7-point diffusion 128^3, coefficients 10^U(-2,2), blocks
                of 32, seed 0 (the fixed-precision benchmark workload)
   aniso_160    anisotropic (1e3) diffusion with 1e4 jumps on 16 subcubes,
@@ -50,6 +52,7 @@ from oracle import precision as OPr  # noqa: E402
 from paper_2407_15973_amd import gen  # noqa: E402
 
 WORKLOADS = {
+    "poisson_64": lambda: gen.config1(seed=0),
     "diff3d_128": lambda: gen.config2(seed=0, N=128, b=32),
     "aniso_160": lambda: gen.config3(seed=0, N=160, b=48),
     "heldout_192": lambda: gen.config5_eval(seed=100, N=192, b=48),

@@ -27,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 WORKLOADS = {
+    "poisson_64": lambda: gen.config1(seed=0),
     "diff3d_128": lambda: gen.config2(seed=0, N=128, b=32),
     "aniso_160": lambda: gen.config3(seed=0, N=160, b=48),
     "heldout_192": lambda: gen.config5_eval(seed=100, N=192, b=48),
