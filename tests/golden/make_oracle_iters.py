@@ -26,6 +26,8 @@ Perturbations (a third argument; the file name gains _<perturbation>): the
 same solve after a change of the inputs at the level of FP64 rounding, to
 measure how far the iteration count of a long CG moves under rounding alone:
   b1ulp   every b_i times (1 + s_i 2^-52), s_i = +-1 from a fixed seed
+  b1ulpK  the same with the signs from seed 4242 + K (K = 1, 2, ...): more
+          samples of the spread
   upper   every block inverse replaced by its upper triangle mirrored (the
           symmetric storage of the GPU path keeps only that triangle)
 
@@ -66,14 +68,20 @@ def sample_rows(n: int) -> np.ndarray:
     return np.sort(np.random.default_rng(12345).choice(n, size=min(n, NSAMPLE), replace=False))
 
 
-PERTURBATIONS = ("b1ulp", "upper")
+def perturbation_seed(perturb: str | None):
+    """Sign seed of a b1ulp[K] perturbation, None for any other."""
+    if perturb == "b1ulp":
+        return 4242
+    if perturb and perturb.startswith("b1ulp") and perturb[5:].isdigit():
+        return 4242 + int(perturb[5:])
+    return None
 
 
 def main(workload: str, pmap: str, perturb: str | None = None) -> None:
     t0 = time.perf_counter()
     p = WORKLOADS[workload]()
-    if perturb == "b1ulp":
-        sgn = np.random.default_rng(4242).choice([-1.0, 1.0], size=p.b.size)
+    if perturbation_seed(perturb) is not None:
+        sgn = np.random.default_rng(perturbation_seed(perturb)).choice([-1.0, 1.0], size=p.b.size)
         p.b = p.b * (1.0 + sgn * 2.0 ** -52)
     nb = len(p.block_ptr) - 1
     print(f"[golden] {workload} {pmap}: n = {p.A.n}, nnz = {p.A.nnz}, blocks = {nb}", flush=True)
@@ -129,6 +137,6 @@ def main(workload: str, pmap: str, perturb: str | None = None) -> None:
 
 if __name__ == "__main__":
     if (len(sys.argv) not in (3, 4) or sys.argv[1] not in WORKLOADS or sys.argv[2] not in MAPS
-            or (len(sys.argv) == 4 and sys.argv[3] not in PERTURBATIONS)):
-        sys.exit(f"usage: {sys.argv[0]} {{{','.join(WORKLOADS)}}} {{{','.join(MAPS)}}} [{{{','.join(PERTURBATIONS)}}}]")
+            or (len(sys.argv) == 4 and sys.argv[3] != "upper" and perturbation_seed(sys.argv[3]) is None)):
+        sys.exit(f"usage: {sys.argv[0]} {{{','.join(WORKLOADS)}}} {{{','.join(MAPS)}}} [upper|b1ulp|b1ulpK]")
     main(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) == 4 else None)

@@ -76,14 +76,16 @@ def test_iterations_against_oracle_at_full_size(workload, pmap):
     print(f"[fullsize] gpu {res.iters} oracle {g['iters']} iterations", flush=True)
     assert res.status == mb.OK and g["status"] == OP.CONVERGED
     if pmap == "fp64":
-        # within 2 iterations, or within the spread the oracle's own count
-        # shows under changes of the inputs at FP64 rounding level (b moved by
-        # one ulp, the block inverses mirrored from their upper triangles:
-        # oracle_iters_<workload>_fp64_<perturbation>.json), when larger
-        bar = max([2] + [abs(golden(workload, f"fp64_{q}")["iters"] - g["iters"])
-                         for q in ("b1ulp", "upper")
-                         if os.path.exists(os.path.join(GOLDEN, f"oracle_iters_{workload}_fp64_{q}.json"))])
-        assert abs(res.iters - g["iters"]) <= bar, (res.iters, g["iters"], bar)
+        # within 2 iterations of the range the oracle's own count spans under
+        # changes of its inputs at FP64 rounding level (b moved by one ulp
+        # with several sign patterns, the block inverses mirrored from their
+        # upper triangles: oracle_iters_<workload>_fp64_<perturbation>.json);
+        # the GPU's different rounding order is a perturbation of that size
+        ens = [g["iters"]] + [golden(workload, f[len(f"oracle_iters_{workload}_"):-5])["iters"]
+                              for f in sorted(os.listdir(GOLDEN))
+                              if f.startswith(f"oracle_iters_{workload}_fp64_") and f.endswith(".json")]
+        print(f"[fullsize] oracle FP64 counts under rounding-level perturbations: {sorted(ens)}", flush=True)
+        assert min(ens) - 2 <= res.iters <= max(ens) + 2, (res.iters, sorted(ens))
     else:
         # reduced blocks: the GPU accumulates the stored products in FP32, the
         # oracle exactly (FP64), a perturbation of M at the FP32 unit roundoff
