@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MPBJAC_ABI_VERSION 2
+#define MPBJAC_ABI_VERSION 3
 #define BJAC_MAX_BLOCK 64        /* largest diagonal block (rows) */
 #define BJAC_NFEAT 16            /* block features per block */
 #define BJAC_MLP_NPARAM 5443     /* W1[64,16] b1[64] W2[64,64] b2[64] W3[3,64] b3[3] */
@@ -361,16 +361,20 @@ int pcg_solve_noalloc(const bjac_csr *A, const bjac_handle *M, const double *b, 
  * used, and profile (eager launches, kernel times in stats->spmv_ms,
  * apply_ms and update_ms = the per-system reductions); relres_hist and
  * high_hist are ignored; variant must be BJAC_PCG_TEXTBOOK. */
+/* Launch shape. The matrix-vector product cuts every system into chunks of
+ * floor(64 / m) rows (at most 64 (row, column) elements, one wave pass); the
+ * chunks are split into 8 runs of about equal cost, one per XCD, whose waves
+ * take them in increasing order from a counter of that run. */
 typedef struct {
-  int32_t chunk_rows;   /* rows per matrix-vector chunk (>= 64; 0 = 128)      */
-  int32_t wg_per_cu;    /* workgroups of 256 threads per compute unit in the
-                           persistent launches (1..32; 0 = 32); at most 8192
-                           workgroups, the matrix-vector launch at most what
-                           is resident at once                                */
-  int32_t spmv_ilp;     /* matrix-vector elements per lane in flight (1 or 2;
-                           0 = 1)                                             */
-  int32_t apply_rows;   /* padded rows per apply chunk (>= 64; 0 = 512).
-                           Chunks never cross systems.                        */
+  int32_t spmv_grab;       /* matrix-vector chunks a wave takes per counter
+                              grab (1..64; 0 = 4)                             */
+  int32_t wg_per_cu;       /* workgroups of 256 threads per compute unit in
+                              the update + apply launch (1..32; 0 = 32); at
+                              most 8192 workgroups                            */
+  int32_t spmv_wg_per_cu;  /* the same for the matrix-vector launch, at most
+                              what is resident at once (1..32; 0 = 32)        */
+  int32_t apply_rows;      /* padded rows per apply chunk (>= 64; 0 = 512).
+                              Chunks never cross systems.                     */
 } bjac_batch_cfg;
 
 int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t nsys,

@@ -2,12 +2,12 @@
 
 The batched kernels cut every system into chunks of rows (SpMV) and of whole
 blocks (application) and spread the chunks over persistent workgroups. Four
-knobs set the shape: ``chunk_rows`` (rows per matrix-vector chunk: the XCD's
-resident waves sweep a window of that many rows each, which must keep a grid
-plane's neighbours in L2), ``wg_per_cu`` (workgroups per compute unit),
-``spmv_ilp`` (matrix-vector elements per lane in flight: more memory
-parallelism against more registers) and ``apply_rows`` (padded rows per apply
-chunk: fewer partial dot products against a finer load balance). ``pcg_batched_tune`` in the library times a
+knobs set the shape: ``spmv_grab`` (matrix-vector chunks a wave takes per
+grab of its XCD's counter: fewer atomics against a wider window of rows in
+flight), ``wg_per_cu`` (workgroups per compute unit of the application),
+``spmv_wg_per_cu`` (the same for the matrix-vector product) and
+``apply_rows`` (padded rows per apply chunk: fewer partial dot products
+against a finer load balance). ``pcg_batched_tune`` in the library times a
 few PCG iterations of the actual batch under each candidate; this module
 picks the candidates, keys the result by the batch's shape and keeps it in a
 JSON cache so a batch of the same shape is not tuned twice.
@@ -22,7 +22,7 @@ import numpy as np
 
 from . import binding as mb
 
-CANDIDATES = tuple((c, w, h, ar) for c in (64, 128, 512) for w in (8, 32) for h in (1, 2) for ar in (512, 2048))
+CANDIDATES = tuple((g, w, 32, ar) for g in (2, 4, 8) for w in (8, 32) for ar in (512, 2048))
 
 
 def default_cache_path() -> str:
@@ -63,7 +63,7 @@ def _save(path, data):
 
 
 def tuned_cfg(bs: "mb.BatchSolver", b, candidates=CANDIDATES, iters=6, cache_path=None, force=False):
-    """(chunk_rows, wg_per_cu, spmv_ilp, apply_rows) for this batch: from the cache, else timed."""
+    """(spmv_grab, wg_per_cu, spmv_wg_per_cu, apply_rows) for this batch: from the cache, else timed."""
     path = cache_path or default_cache_path()
     key = shape_key(bs)
     data = _load(path)

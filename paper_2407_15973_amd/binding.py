@@ -75,7 +75,7 @@ class bjac_poly_params(C.Structure):
 
 
 class bjac_batch_cfg(C.Structure):
-    _fields_ = [("chunk_rows", C.c_int32), ("wg_per_cu", C.c_int32), ("spmv_ilp", C.c_int32),
+    _fields_ = [("spmv_grab", C.c_int32), ("wg_per_cu", C.c_int32), ("spmv_wg_per_cu", C.c_int32),
                 ("apply_rows", C.c_int32)]
 
 
@@ -491,7 +491,7 @@ class BatchSolver:
         return res
 
     def tune(self, b, cands, iters=8):
-        """Times ``iters`` iterations under each (chunk_rows, wg_per_cu[, spmv_ilp[, apply_rows]]);
+        """Times ``iters`` iterations under each (spmv_grab, wg_per_cu[, spmv_wg_per_cu[, apply_rows]]);
         returns (best index, ms per iteration of every candidate)."""
         torch = _torch()
         arr = (bjac_batch_cfg * len(cands))(*[bjac_batch_cfg(*c) for c in cands])

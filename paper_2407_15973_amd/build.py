@@ -17,8 +17,13 @@ BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["setup.hip", "solve.hip", "batched.hip", "poly.hip", "mlp.hip", "probe.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+# -amdgpu-atomic-optimizer-strategy=None: the kernels' atomics are taken by
+# one lane with a wave-uniform address; the optimizer's rewrite of such an
+# atomic reads its result at once, which stalls a software pipeline that
+# consumes the result a step later
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
          "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 
 

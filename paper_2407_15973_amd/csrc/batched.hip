@@ -36,10 +36,11 @@ enum BStatus { BS_RUNNING = 0, BS_CONVERGED = 1, BS_MAXIT = 2, BS_BREAKDOWN = -3
 
 struct BTables {
   int32_t S, nch, nach;
-  const int32_t *sys_row, *sys_m, *sys_col, *sys_ch, *sys_ach;
+  const int32_t *sys_row, *sys_m, *sys_col, *sys_ach;
+  const int32_t *sys_ch;     // SpMV chunks of system s: [sys_ch[s], sys_ch[s+1]), sys_rpc[s] rows each
+  const int32_t *sys_rpc;    // rows per SpMV chunk of system s (floor(64 / m), fewer for long rows)
   const int64_t *sys_vec;    // system start in the solver's vectors (64-byte aligned)
   const int64_t *sys_xvec;   // system start in the caller's b and x (contiguous)
-  const int32_t *ch_row0, *ch_sys;    // SpMV chunks: rows [ch_row0[i], ch_row0[i+1])
   const int32_t *ach_blk, *ach_sys;   // apply chunks: blocks [ach_blk[i], ach_blk[i+1])
 };
 
@@ -66,6 +67,33 @@ __device__ __forceinline__ int wave_slot(int wv) {
 }
 
 // ------------------------------------------------------------------ SpMV
+// q = A p with p = z + beta p_old formed at every read (the direction update
+// of PCG fused into the product), p_new and q written, (p, q) per column.
+//
+// Work unit: a chunk of one system's rows with at most 64 (row, column)
+// elements, floor(64 / m) rows of a system with m columns (fewer when the
+// longest row of A would overflow the chunk's LDS slot). Lane l owns
+// element (l / m, l mod m), so consecutive lanes touch consecutive doubles of
+// the row-major [rows][m] vectors, and one pass of the wave covers the chunk.
+// Chunks are numbered system by system; the chunk range is cut into 8 runs of
+// about equal cost, one per XCD (workgroup g runs on XCD g mod 8).
+//
+// Order: the waves of an XCD take the chunks of its run in increasing order
+// from one counter (an atomic grab of `grab_k` chunks at a time), so the
+// chunks in flight on an XCD form one narrow window of consecutive rows, and
+// the rows a gather needs one grid plane away were fetched into that XCD's L2
+// moments earlier by another wave. (With a fixed round-robin split the waves
+// drift apart, the rows in flight spread far beyond what the L2 holds, and the
+// neighbour reads fetch the same rows from memory several times over.)
+//
+// Software pipeline, one chunk per step: chunk i's gathers of z and p_old are
+// issued after chunk i+1's CSR loads (16-byte chunks into registers), chunk
+// i+2's row-pointer loads, the next grab and chunk i-1's stores (held back a
+// step), so all of them share one round trip and nothing is left in flight
+// when the step ends. A chunk's geometry follows from per-system tables kept
+// in scalar registers, re-read only when a chunk lies in a later system.
+constexpr int kBSlot = 512;   // LDS entries per wave: a chunk's CSR window in 16-byte chunks
+
 struct BSpmvArgs {
   BTables t;
   const int32_t *rp, *ci;
@@ -73,14 +101,24 @@ struct BSpmvArgs {
   const double *z, *pold;
   double *pnew, *q;
   const double *beta;
-  double *part;          // [nch][8]
+  double *part;              // (p, q) of system s's chunk k, column c: part[sys_pbase[s] + k m + c]
+  const int32_t *sys_pbase;  // [S + 1]
   const int32_t *n_active;
-  const int32_t *sched;   // [9] chunk run of each XCD
-  const int16_t *o16;     // col - row of every entry (16-bit copy), read while *rel16
-  const int32_t *rel16;
-  int32_t nnz8;           // nnz rounded down to 8: whole 16-byte chunks of every array
-  int32_t vec;            // values and indices 16-byte aligned: tiles may be staged in 16-byte chunks
+  const int32_t *sched;      // [9] chunk run of each XCD
+  const int32_t *run_sys;    // [8] system of each run's first chunk
+  int32_t *grab;             // [8 * 32] chunk counter of each run (one per 128 bytes)
+  int32_t grab_k;            // chunks per grab
+  const int16_t *o16;        // col - row of every entry (16-bit copy; kernel REL = true)
+  int32_t nnz;
 };
+
+struct SpmvLds {
+  __align__(16) double v[kBSlot];
+  __align__(16) int c[kBSlot];   // 32-bit indices, or the 16-bit copy in the first half
+  int rp[65];
+};
+
+using bu32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
 // floor(e / m) for 0 <= e < 4096 and 1 <= m <= 8 (multiply by ceil(2^16/m);
 // the rounding error e / 2^16 stays below 1/8)
@@ -89,259 +127,334 @@ __device__ __forceinline__ int div_small(int e, int m) {
   return (e * inv) >> 16;
 }
 
-// One chunk of rows of a system with M columns, in wave tiles of 64 rows.
-// The tile's row pointers and CSR entries are staged in LDS with coalesced
-// loads; then lane l owns elements e = l, l + 64, ... (row e / M, column
-// e mod M) of the tile's rows x M block, so consecutive lanes touch
-// consecutive doubles of the row-major [rows][M] vectors and the lanes of a
-// row read its CSR entries from LDS. q = A p with p = z + beta p_old formed
-// at every read; p_new is the diagonal term's p. H elements per lane are in
-// flight together.
-constexpr int kBSlot = 512;   // LDS entries per wave: a tile's CSR window in 16-byte chunks
-
-struct SpmvLds {
-  __align__(16) double v[kBSlot];
-  __align__(16) int c[kBSlot];   // 32-bit indices, or the 16-bit copy in the first half
-  int rp[kBWaveRows + 1];
+// The system a wave is in (wave-uniform).
+struct BSysState {
+  int32_t s, chs, che;   // system and its chunks [chs, che)
+  int32_t rs, nrows, m, R, c0, pbase;   // R: rows per chunk
+  int64_t vsys;          // start of its block in the solver's vectors
 };
 
-using bu32x4 = unsigned int __attribute__((ext_vector_type(4)));
-
-template <int VW>
-struct VecT;
-template <>
-struct VecT<1> {
-  static __device__ __forceinline__ void load(const double *p, double (&v)[1]) { v[0] = *p; }
-  static __device__ __forceinline__ void store(double *p, const double (&v)[1]) { *p = v[0]; }
-};
-template <>
-struct VecT<2> {
-  // 16-byte aligned: solver vectors start on 64 bytes, M and the column are even
-  static __device__ __forceinline__ void load(const double *p, double (&v)[2]) {
-    const double2 t = *(const double2 *)p;
-    v[0] = t.x;
-    v[1] = t.y;
-  }
-  static __device__ __forceinline__ void store(double *p, const double (&v)[2]) {
-    *(double2 *)p = make_double2(v[0], v[1]);
-  }
-};
-
-// H: elements per lane in flight; VW: consecutive columns per element (2
-// needs an even M: one 16-byte access per vector and neighbour).
-// REL: the staged column indices are the 16-bit row-relative copy.
-template <int H, int VW, bool REL>
-__device__ __forceinline__ void bspmv_chunk(const BSpmvArgs &a, int ch, int M, SpmvLds &L) {
-  constexpr int CAP = kSpmvNnzCap;
-  constexpr int NL = CAP / 64;
-  // CSR entries per row with loads in flight together: a 7-point row in one
-  // group of single columns (an eighth, clamped gather would be overhead)
-  constexpr int U = VW == 1 ? 7 : 4;
-  const int lane = threadIdx.x & 63;
-  const int s = __builtin_amdgcn_readfirstlane(a.t.ch_sys[ch]);
-  const int rs = a.t.sys_row[s];
-  const int nrows = a.t.sys_row[s + 1] - rs;
-  const int64_t v0 = a.t.sys_vec[s];
-  const int c0 = a.t.sys_col[s];
-  const int LPR = M / VW;   // lanes per row
-  double pq[kBCols];
-#pragma unroll
-  for (int cc = 0; cc < kBCols; ++cc) pq[cc] = 0.0;
-  const int rb = a.t.ch_row0[ch], re = a.t.ch_row0[ch + 1];
-  for (int r0 = rb; r0 < re; r0 += kBWaveRows) {
-    const int r1 = min(re, r0 + kBWaveRows);
-    const int nr = r1 - r0;
-    // stage row pointers (relative) and the CSR entries of the tile
-    const int e0 = __builtin_amdgcn_readfirstlane(a.rp[r0]);
-    const int cnt = __builtin_amdgcn_readfirstlane(a.rp[r1]) - e0;
-    const int rpl = a.rp[r0 + min(lane, nr)] - e0;
-    // 16-byte chunks from the 8-entry boundary at or below the tile's first
-    // entry (4 loads of values, 1 or 2 of indices per lane instead of one per
-    // entry and array), when the window fits the slice and lies below the
-    // last whole 8-entry group; otherwise one entry per lane and load
-    constexpr int SL = kBSlot;
-    constexpr int NV = SL * 8 / 16 / 64, NC = SL * (REL ? 2 : 4) / 16 / 64;
-    constexpr int EV = 2, EC = REL ? 8 : 4;
-    const int base = e0 & ~7;
-    const int need = e0 - base + cnt;
-    const bool chunked = a.vec && cnt > 0 && need <= SL && base + ((need + 7) & ~7) <= a.nnz8;
-    // cnt = 0 (all rows empty): no entry is read below
-    const bool staged = chunked || (cnt > 0 && cnt <= CAP);
-    const int soff = chunked ? e0 - base : 0;   // LDS position of the tile's first entry
-    if (chunked) {
-      const bu32x4 zero = {0u, 0u, 0u, 0u};
-      const bu32x4 *vp = (const bu32x4 *)(a.v + base);
-      const bu32x4 *cp = REL ? (const bu32x4 *)(a.o16 + base) : (const bu32x4 *)(a.ci + base);
-      bu32x4 gv[NV], gc[NC];
-#pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        const int c = lane + 64 * q;
-        gv[q] = c * EV < need ? __builtin_nontemporal_load(vp + c) : zero;
-      }
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int c = lane + 64 * q;
-        gc[q] = c * EC < need ? __builtin_nontemporal_load(cp + c) : zero;
-      }
-#pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        const int c = lane + 64 * q;
-        if (c * EV < need) ((bu32x4 *)L.v)[c] = gv[q];
-      }
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int c = lane + 64 * q;
-        if (c * EC < need) ((bu32x4 *)L.c)[c] = gc[q];
-      }
-    } else if (staged) {
-      double vv[NL];
-      int cc[NL];
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const int i = min(lane + 64 * k, cnt - 1);
-        vv[k] = __builtin_nontemporal_load(a.v + e0 + i);     // read once per product:
-        if constexpr (REL) cc[k] = (int)__builtin_nontemporal_load(a.o16 + e0 + i);   // do not
-        else cc[k] = __builtin_nontemporal_load(a.ci + e0 + i);                      // displace the vectors
-      }
-#pragma unroll
-      for (int k = 0; k < NL; ++k) {
-        const int i = lane + 64 * k;
-        if (i < cnt) {
-          L.v[i] = vv[k];
-          L.c[i] = cc[k];
-        }
-      }
-    }
-    L.rp[lane] = rpl;
-    if (lane == 0) L.rp[64] = cnt;
-    bwave_lds_sync();
-    const int E = nr * LPR;
-    for (int eb = 0; eb < E; eb += 64 * H) {
-      int row[H], col[H], sidx[H], len[H];
-      double beta[H][VW];
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        const int e = min(eb + 64 * h + lane, E - 1);
-        row[h] = div_small(e, LPR);
-        col[h] = (e - row[h] * LPR) * VW;
-        sidx[h] = L.rp[row[h]];
-        len[h] = (eb + 64 * h + lane < E) ? L.rp[row[h] + 1] - sidx[h] : 0;
-#pragma unroll
-        for (int v = 0; v < VW; ++v) beta[h][v] = a.beta[c0 + col[h] + v];
-      }
-      double acc[H][VW], prow[H][VW];
-      bool found[H];
-      int lmax = 0;
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-#pragma unroll
-        for (int v = 0; v < VW; ++v) acc[h][v] = prow[h][v] = 0.0;
-        found[h] = false;
-        lmax = max(lmax, len[h]);
-      }
-      for (int k0 = 0; k0 < lmax; k0 += U) {
-        int cs[H][U];
-        double vs[H][U], gz[H][U][VW], gp[H][U][VW];
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-          for (int k = 0; k < U; ++k) {
-            const int idx = min(sidx[h] + min(k0 + k, max(len[h] - 1, 0)), cnt - 1);
-            const bool ok = k0 + k < len[h];
-            int cl;
-            if (chunked) cl = REL ? (int)((const int16_t *)L.c)[soff + idx] : L.c[soff + idx];
-            else cl = staged ? L.c[idx] : a.ci[e0 + idx];
-            cs[h][k] = cl + (staged && REL ? r0 + row[h] : 0);
-            const double vv = staged ? L.v[soff + idx] : a.v[e0 + idx];
-            vs[h][k] = ok ? vv : 0.0;
-          }
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-          for (int k = 0; k < U; ++k) {
-            // a column outside the system (not a block-diagonal stack) is
-            // clamped into it: wrong values for an invalid input, never an
-            // access outside the vectors
-            const int jl = min(max(cs[h][k] - rs, 0), nrows - 1);
-            const int64_t j = v0 + (int64_t)jl * M + col[h];
-            VecT<VW>::load(a.pold + j, gp[h][k]);
-            VecT<VW>::load(a.z + j, gz[h][k]);
-          }
-#pragma unroll
-        for (int h = 0; h < H; ++h)
-#pragma unroll
-          for (int k = 0; k < U; ++k) {
-            const bool ok = k0 + k < len[h];
-            const bool me = ok && cs[h][k] == r0 + row[h];
-#pragma unroll
-            for (int v = 0; v < VW; ++v) {
-              const double g = fma(beta[h][v], gp[h][k][v], gz[h][k][v]);
-              acc[h][v] = fma(vs[h][k], g, acc[h][v]);
-              prow[h][v] = me ? g : prow[h][v];
-            }
-            found[h] = found[h] || me;
-          }
-      }
-#pragma unroll
-      for (int h = 0; h < H; ++h) {
-        if (eb + 64 * h + lane < E) {
-          const int64_t e = v0 + (int64_t)(r0 + row[h] - rs) * M + col[h];
-          double pr[VW];
-          if (!found[h]) {
-            double zz[VW], pp[VW];
-            VecT<VW>::load(a.z + e, zz);
-            VecT<VW>::load(a.pold + e, pp);
-#pragma unroll
-            for (int v = 0; v < VW; ++v) pr[v] = fma(beta[h][v], pp[v], zz[v]);
-          } else {
-#pragma unroll
-            for (int v = 0; v < VW; ++v) pr[v] = prow[h][v];
-          }
-          VecT<VW>::store(a.q + e, acc[h]);
-          VecT<VW>::store(a.pnew + e, pr);
-#pragma unroll
-          for (int v = 0; v < VW; ++v) {
-            const double t = pr[v] * acc[h][v];
-#pragma unroll
-            for (int cc = 0; cc < kBCols; ++cc) pq[cc] += col[h] + v == cc ? t : 0.0;
-          }
-        }
-      }
-    }
-    bwave_lds_sync();
-  }
-#pragma unroll
-  for (int cc = 0; cc < kBCols; ++cc) {
-    const double t = wave_sum(pq[cc]);
-    if (lane == cc) a.part[(int64_t)ch * kBCols + cc] = t;
-  }
+__device__ __forceinline__ void bsys_fetch(const BSpmvArgs &a, int s, BSysState &y) {
+  y.s = s;
+  y.chs = a.t.sys_ch[s];
+  y.che = a.t.sys_ch[s + 1];
+  y.rs = a.t.sys_row[s];
+  y.nrows = a.t.sys_row[s + 1] - y.rs;
+  y.m = a.t.sys_m[s];
+  y.R = a.t.sys_rpc[s];
+  y.c0 = a.t.sys_col[s];
+  y.pbase = a.sys_pbase[s];
+  y.vsys = a.t.sys_vec[s];
 }
 
-// The chunks are split into 8 runs of about equal cost, one per XCD (sched
-// holds the 9 run boundaries). Inside a run the XCD's waves take chunks
-// round-robin, so at any moment its resident waves work on one window of
-// consecutive chunks and the neighbour rows a gather needs (up to a grid
-// plane away) were fetched into that XCD's L2 by another wave of the window.
-template <int H>
-__global__ __launch_bounds__(256) void bspmv_kernel(BSpmvArgs a) {
+// A chunk in the pipeline (wave-uniform): its index, first row and rows;
+// ch = -1: none (the run is exhausted).
+struct BSlot {
+  int32_t ch = -1, r0 = 0, nr = 0;
+};
+
+// Moves a system cursor forward to the system holding chunk ch (chunk indices
+// only grow along a run).
+__device__ __forceinline__ void bsys_seek(const BSpmvArgs &a, int ch, BSysState &y) {
+  while (ch >= y.che) bsys_fetch(a, y.s + 1, y);
+}
+
+__device__ __forceinline__ BSlot bslot_at(const BSpmvArgs &a, int ch, int ce, BSysState &y) {
+  BSlot g;
+  if (ch >= ce) return g;
+  bsys_seek(a, ch, y);
+  g.ch = ch;
+  g.r0 = y.rs + (ch - y.chs) * y.R;
+  g.nr = min(y.R, y.rs + y.nrows - g.r0);
+  return g;
+}
+
+// Chunks of one run handed out in increasing order: `grab_k` at a time from
+// the run's counter, the next grab in flight while the current ones are used.
+struct BGrabber {
+  int32_t *ctr;
+  int cb, ce, K;
+  int cur = 0, end = 0;
+  int pend = 0;   // lane 0: result of the grab in flight
+  // lane 0 takes the grab; the other lanes keep their (unused) value, so no
+  // select joins the result before it is read
+  __device__ __forceinline__ void issue() {
+    if ((threadIdx.x & 63) == 0) pend = __hip_atomic_fetch_add(ctr, K, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // next chunk of the run, or ce once the run is exhausted (no grab after that)
+  __device__ __forceinline__ int next() {
+    if (cur >= end) {
+      const int g = cb + __builtin_amdgcn_readfirstlane(pend);
+      if (g >= ce) return ce;
+      cur = g;
+      end = min(g + K, ce);
+      issue();
+    }
+    return cur++;
+  }
+};
+
+// A wave-uniform pointer moved into scalar registers: the compiler then
+// addresses p[lane] as scalar base + lane offset instead of keeping a per-lane
+// 64-bit pointer alive across the loop.
+// (The result is typed as a global-memory pointer: a pointer rebuilt from
+// integers would otherwise be generic, and generic loads also wait on LDS.)
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ gptr<T> wave_ptr(T *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gptr<T>)(((uint64_t)hi << 32) | lo);
+}
+
+template <bool REL>
+__device__ __forceinline__ void bspmv_run(const BSpmvArgs &a, SpmvLds &L, int x) {
+  constexpr int SL = kBSlot;
+  constexpr int NV = SL * 8 / 16 / 64;               // value pieces per lane
+  constexpr int NC = SL * (REL ? 2 : 4) / 16 / 64;   // index pieces per lane
+  constexpr int EV = 2, EC = REL ? 8 : 4;            // entries per 16-byte piece
+  constexpr int U = 7;                               // entries of a row with loads in flight together
+  const int lane = threadIdx.x & 63;
+  const int cb = a.sched[x], ce = a.sched[x + 1];
+  if (cb >= ce) return;
+  BSysState y, yX;   // cursors of the newest chunk and of the current one
+  bsys_fetch(a, a.run_sys[x], y);
+  yX = y;
+  BGrabber gr{a.grab + 32 * x, cb, ce, a.grab_k};
+  gr.issue();
+
+  // end pointer of the lane's row in a chunk (lanes past the last row: the
+  // chunk's end), and the chunk's first entry
+  auto load_rp = [&](const BSlot &g, int &e0v) -> int {
+    e0v = g.ch >= 0 ? a.rp[g.r0] : 0;
+    return g.ch >= 0 ? a.rp[g.r0 + min(lane + 1, g.nr)] : 0;
+  };
+  // CSR window of a chunk: its first entry and count, and where its staged
+  // 16-byte pieces start in each array (the first piece boundary at or below
+  // the first entry; val is 8-byte, ci 4-byte aligned). The host caps the rows
+  // of a chunk so that every window fits the LDS slot.
+  const int vsh = (int)(((uintptr_t)a.v >> 3) & 1);   // val's offset from a 16-byte boundary (entries)
+  const int csh = REL ? 0 : (int)(((uintptr_t)a.ci >> 2) & 3);
+  auto window = [&](const BSlot &g, int rpl, int e0v, int &e0, int &cnt, int &bv, int &bc) {
+    e0 = __builtin_amdgcn_readfirstlane(e0v);
+    cnt = g.ch >= 0 ? __builtin_amdgcn_readlane(rpl, g.nr - 1) - e0 : 0;
+    bv = e0 - ((e0 + vsh) & 1);
+    bc = REL ? (e0 & ~7) : e0 - ((e0 + csh) & 3);
+  };
+  // 16-byte pieces of the window into registers; a piece that passes the end
+  // of the arrays (the matrix's last chunk) is read entry by entry
+  auto stage = [&](int e0, int cnt, int bv, int bc, bu32x4 (&gv)[NV], bu32x4 (&gc)[NC]) {
+    const bu32x4 zero = {0u, 0u, 0u, 0u};
+    const int end = e0 + cnt;
+    const bu32x4 *vp = (const bu32x4 *)(a.v + bv);
+    const bu32x4 *cp = REL ? (const bu32x4 *)(a.o16 + bc) : (const bu32x4 *)(a.ci + bc);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int c = lane + 64 * q;
+      const int f = bv + c * EV;   // first entry of the piece
+      gv[q] = zero;
+      if (f < end) {
+        if (f + EV <= a.nnz) {
+          gv[q] = __builtin_nontemporal_load(vp + c);   // read once per product: do not displace the vectors
+        } else {
+          const uint64_t w = __double_as_longlong(a.v[f]);
+          gv[q].x = (uint32_t)w;
+          gv[q].y = (uint32_t)(w >> 32);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int c = lane + 64 * q;
+      const int f = bc + c * EC;
+      gc[q] = zero;
+      if (f < end) {
+        if (f + EC <= a.nnz) {
+          gc[q] = __builtin_nontemporal_load(cp + c);
+        } else {
+          uint32_t w[4] = {0u, 0u, 0u, 0u};
+          for (int j = 0; f + j < a.nnz && j < EC; ++j) {
+            const uint32_t u = REL ? (uint32_t)(uint16_t)a.o16[f + j] : (uint32_t)a.ci[f + j];
+            if (REL)
+              w[j >> 1] |= u << (16 * (j & 1));
+            else
+              w[j] = u;
+          }
+          gc[q] = bu32x4{w[0], w[1], w[2], w[3]};
+        }
+      }
+    }
+  };
+
+  // prologue: chunk X (current) with its CSR in registers, C with its row
+  // pointers, R with its row-pointer loads in flight
+  int e0vX, e0vC, e0vR;
+  BSlot gX = bslot_at(a, gr.next(), ce, y);
+  int rpX = load_rp(gX, e0vX);
+  int e0X, cntX, bvX, bcX;
+  window(gX, rpX, e0vX, e0X, cntX, bvX, bcX);
+  bu32x4 gv[NV], gc[NC];
+  stage(e0X, cntX, bvX, bcX, gv, gc);
+  BSlot gC = bslot_at(a, gr.next(), ce, y);
+  int rpC = load_rp(gC, e0vC);
+  BSlot gR = bslot_at(a, gr.next(), ce, y);
+  int rpR = load_rp(gR, e0vR);
+
+  // stores of the previous chunk, issued in the next step: its values per
+  // lane, its place from wave-uniform values
+  int s_ch = -1, s_n = 0, s_m = 1;
+  int64_t s_vb = 0, s_pb = 0;   // vector index of the chunk's first element, its first partial slot
+  double s_q = 0.0, s_p = 0.0, s_pq = 0.0;
+  auto flush = [&]() {
+    if (s_ch < 0) return;
+    if (lane < s_n) {
+      wave_ptr(a.q + s_vb)[lane] = s_q;
+      wave_ptr(a.pnew + s_vb)[lane] = s_p;
+    }
+    if (lane < s_m) wave_ptr(a.part + s_pb)[lane] = s_pq;
+  };
+
+  while (gX.ch >= 0) {
+    // (a) chunk X's CSR window and relative row pointers into LDS
+    {
+      const int nv = e0X + cntX - bvX, nc = e0X + cntX - bcX;   // staged entries
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EV < nv) ((bu32x4 *)L.v)[c] = gv[q];
+      }
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int c = lane + 64 * q;
+        if (c * EC < nc) ((bu32x4 *)L.c)[c] = gc[q];
+      }
+    }
+    L.rp[lane + 1] = rpX - e0X;
+    if (lane == 0) L.rp[0] = 0;
+    bwave_lds_sync();
+    // (b) chunk C: its window (row pointers arrived a step ago), CSR loads
+    int e0C, cntC, bvC, bcC;
+    window(gC, rpC, e0vC, e0C, cntC, bvC, bcC);
+    bu32x4 hv[NV], hc[NC];
+    stage(e0C, cntC, bvC, bcC, hv, hc);
+    // (c) the chunk after R: rows (the grab arrived a step ago), row pointers;
+    // the previous chunk's stores
+    const BSlot gN = bslot_at(a, gr.next(), ce, y);
+    int e0vN;
+    const int rpN = load_rp(gN, e0vN);
+    flush();
+    // (d) chunk X: gathers, products and the per-column (p, q)
+    bsys_seek(a, gX.ch, yX);
+    const int m = yX.m;
+    const int E = gX.nr * m;
+    const bool has = lane < E;
+    const int lr = div_small(lane, m);
+    const int col = lane - lr * m;
+    const int row = min(lr, gX.nr - 1);
+    const int grow = gX.r0 + row;
+    const int sidx = L.rp[row];
+    const int len = has ? L.rp[row + 1] - sidx : 0;
+    const double bt = a.beta[yX.c0 + col];
+    const gptr<const double> zs = wave_ptr(a.z + yX.vsys);
+    const gptr<const double> ps = wave_ptr(a.pold + yX.vsys);
+    const int16_t *c16 = (const int16_t *)L.c + (e0X - bcX);
+    const int *c32 = L.c + (e0X - bcX);
+    const double *lv = L.v + (e0X - bvX);
+    double acc = 0.0, prow = 0.0;
+    bool found = false;
+    for (int k0 = 0; k0 < len; k0 += U) {
+      int cs[U];
+      double gz[U], gp[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int e = sidx + min(k0 + k, len - 1);
+        cs[k] = REL ? (int)c16[e] + grow : c32[e];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        // a column outside the system (not a block-diagonal stack) is
+        // clamped into it: wrong values for an invalid input, never an
+        // access outside the vectors
+        const int jl = min(max(cs[k] - yX.rs, 0), yX.nrows - 1);
+        const uint32_t o = (uint32_t)(jl * m + col);
+        gz[k] = zs[o];
+        gp[k] = ps[o];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        // the value is read once the gathers are in flight
+        const double vv = lv[sidx + min(k0 + k, len - 1)];
+        const double g = fma(bt, gp[k], gz[k]);
+        acc = fma(k0 + k < len ? vv : 0.0, g, acc);
+        const bool me = k0 + k < len && cs[k] == grow;
+        prow = me ? g : prow;
+        found = found || me;
+      }
+    }
+    double prod = 0.0;
+    if (has) {
+      const uint32_t o = (uint32_t)((grow - yX.rs) * m + col);
+      const double pr = found ? prow : fma(bt, ps[o], zs[o]);
+      s_q = acc;
+      s_p = pr;
+      prod = pr * acc;
+    }
+    // column sums of pr * q over the chunk's rows: the lanes of one column
+    // are congruent mod m, so for m a power of two a butterfly over the
+    // strides >= m leaves column c's sum in lane c; otherwise through LDS
+    bwave_lds_sync();   // every lane has read the CSR window
+    if ((m & (m - 1)) == 0) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+        if (o >= m) prod += __shfl_xor(prod, o, 64);
+    } else {
+      L.v[lane] = prod;
+      bwave_lds_sync();
+      double t = 0.0;
+      if (lane < m)
+        for (int r = 0; r < gX.nr; ++r) t += L.v[lane + r * m];
+      prod = t;
+    }
+    s_ch = gX.ch;
+    s_n = E;
+    s_m = m;
+    s_vb = yX.vsys + (int64_t)(gX.r0 - yX.rs) * m;   // element l of the chunk is s_vb + l
+    s_pb = yX.pbase + (int64_t)(gX.ch - yX.chs) * m;
+    s_pq = prod;
+    bwave_lds_sync();   // LDS free for the next chunk
+    // shift the pipeline
+    gX = gC;
+    rpX = rpC;
+    e0X = e0C;
+    cntX = cntC;
+    bvX = bvC;
+    bcX = bcC;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) gv[q] = hv[q];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) gc[q] = hc[q];
+    gC = gR;
+    rpC = rpR;
+    e0vC = e0vR;
+    gR = gN;
+    rpR = rpN;
+    e0vR = e0vN;
+  }
+  flush();
+}
+
+// REL: the column structure is read as the 16-bit col - row copy. Four
+// waves per SIMD (at most 128 registers, which the kernel fits without
+// spilling; the compiler alone would take more and allow three).
+template <bool REL>
+__global__ __launch_bounds__(256, 4) void bspmv_kernel(BSpmvArgs a) {
   __shared__ SpmvLds lds[4];
   if (*a.n_active == 0) return;
-  const bool rel = a.o16 && *a.rel16;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int x = blockIdx.x & 7;
-  const int j = (blockIdx.x >> 3) * 4 + wv;
-  const int Wx = (gridDim.x >> 3) * 4;
-  const int ce = a.sched[x + 1];
-  for (int ch = a.sched[x] + j; ch < ce; ch += Wx) {
-    const int m = __builtin_amdgcn_readfirstlane(a.t.sys_m[a.t.ch_sys[ch]]);
-    if (rel) {
-      if (m & 1) bspmv_chunk<H, 1, true>(a, ch, m, lds[wv]);
-      else bspmv_chunk<H, 2, true>(a, ch, m, lds[wv]);
-    } else {
-      if (m & 1) bspmv_chunk<H, 1, false>(a, ch, m, lds[wv]);
-      else bspmv_chunk<H, 2, false>(a, ch, m, lds[wv]);
-    }
-  }
+  bspmv_run<REL>(a, lds[wv], blockIdx.x & 7);
 }
 
 // ---------------------------------------------------------- update + apply
@@ -775,20 +888,124 @@ __device__ __forceinline__ bool wg_none_active(const int32_t *n_active, int *fla
   return *flag == 0;
 }
 
-__global__ __launch_bounds__(256) void breduce_pq_kernel(BTables t, BState st, const double *part) {
-  __shared__ double sh[4];
+// (p, q) per column from the SpMV's per-chunk partials, then alpha. One
+// workgroup per segment of kBSegCh consecutive chunks of one system sums the
+// segment's slots per column (coalesced: thread t reads the slots of column
+// t mod m). A system with several segments publishes the segment totals with
+// device-scope atomic stores into slots that hold kBEmpty and takes a ticket;
+// the workgroup with the system's last ticket reads the totals with
+// device-scope atomic loads (waiting for a slot whose store is still in
+// flight), sums them in segment order and resets the slots and the ticket, so
+// neither the result nor its rounding depends on which workgroup finishes
+// first, and no cache maintenance is needed (device-scope atomics are
+// coherent across the XCDs' L2 caches). Block 0 also rewinds the SpMV's
+// chunk counters for the next launch (the SpMV of this iteration has ended:
+// same stream).
+constexpr int kBSegCh = 1024;                          // chunks per reduction segment
+constexpr uint64_t kBEmpty = 0x7FF4D1CE0000BEEFull;    // signalling-NaN pattern no arithmetic produces
+constexpr int kBSpinCap = 1 << 22;
+
+struct BSegTabs {
+  const int32_t *seg_sys;    // [nseg] system of each segment
+  const int32_t *sys_seg;    // [S + 1] segments of system s: [sys_seg[s], sys_seg[s+1])
+  const int32_t *sys_pbase;  // [S + 1] first partial slot of each system
+  double *seg_part;          // [nseg * 8] column totals of each segment (kBEmpty when unused)
+  uint32_t *sys_ticket;      // [S] segments of the system done (reset by the last)
+};
+
+// Fixed-order tree over the L / m partial sums of each column held in
+// sh[c + j m] (j < L / m); column c's total ends in sh[c].
+__device__ __forceinline__ void col_tree(double *sh, int L, int m) {
+  const int t = (int)threadIdx.x;
+  __syncthreads();
+  for (int w = L / m; w > 1;) {
+    const int h = w >> 1, nw = w - h;   // entries j < h take entry j + nw
+    if (t < h * m) {
+      const int c = t % m, j = t / m;
+      sh[c + j * m] += sh[c + (j + nw) * m];
+    }
+    __syncthreads();
+    w = nw;
+  }
+}
+
+__global__ __launch_bounds__(256) void breduce_pq_kernel(BTables t, BState st, const double *part, BSegTabs sg,
+                                                         int32_t *grab) {
+  __shared__ double sh[256];
   __shared__ int act;
+  __shared__ int last;
+  const int tid = (int)threadIdx.x;
+  if (blockIdx.x == 0 && tid < 8) grab[32 * tid] = 0;
   if (wg_none_active(st.n_active, &act)) return;
-  const int s = blockIdx.x;
+  const int seg = blockIdx.x;
+  const int s = sg.seg_sys[seg];
   const int m = t.sys_m[s], c0 = t.sys_col[s];
-  const int cb = t.sys_ch[s], ce = t.sys_ch[s + 1];
-  for (int c = 0; c < m; ++c) {
-    double v = 0.0;
-    for (int ch = cb + (int)threadIdx.x; ch < ce; ch += 256) v += part[(int64_t)ch * kBCols + c];
-    const double pq = wg_sum(v, sh);
-    if (threadIdx.x == 0 && st.status[c0 + c] == BS_RUNNING) {
-      if (!(pq > 0.0)) freeze(st, c0 + c, BS_BREAKDOWN);
-      else st.alpha[c0 + c] = st.rho[c0 + c] / pq;
+  const int nk = t.sys_ch[s + 1] - t.sys_ch[s];
+  const int k0 = (seg - sg.sys_seg[s]) * kBSegCh, k1 = min(nk, k0 + kBSegCh);
+  // thread i < L (L: the largest multiple of m <= 256) sums the slots of
+  // column i mod m with stride L
+  {
+    const double *v = part + sg.sys_pbase[s] + (int64_t)k0 * m;
+    const int len = (k1 - k0) * m, L = 256 - 256 % m;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};   // four independent sums: four loads in flight
+    if (tid < L) {
+      int i = tid;
+      for (; i + 3 * L < len; i += 4 * L)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] += v[i + u * L];
+      for (int u = 0; i < len; i += L, ++u) a[u] += v[i];
+    }
+    sh[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+    col_tree(sh, L, m);
+  }
+  double tot = tid < m ? sh[tid] : 0.0;
+  const int nseg = sg.sys_seg[s + 1] - sg.sys_seg[s];
+  if (nseg > 1) {
+    if (tid < m)
+      __hip_atomic_store((uint64_t *)(sg.seg_part + (int64_t)seg * 8 + tid), (uint64_t)__double_as_longlong(tot),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (tid == 0)
+      last = __hip_atomic_fetch_add(sg.sys_ticket + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+             (uint32_t)(nseg - 1);
+    __syncthreads();
+    if (!last) return;
+    // segment totals in segment order: slot i of the system's [nseg][8]
+    // block is column i mod 8
+    // (loads of up to four slots issued together; only a slot still empty
+    // is polled again)
+    double a = 0.0;
+    const int64_t b0 = (int64_t)sg.sys_seg[s] * 8;
+    for (int i0 = tid; i0 < nseg * 8; i0 += 4 * 256) {
+      uint64_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + 256 * k;
+        u[k] = i < nseg * 8 && (i & 7) < m
+                   ? __hip_atomic_load((uint64_t *)(sg.seg_part + b0 + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : 0ull;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + 256 * k;
+        if (i >= nseg * 8 || (i & 7) >= m) continue;
+        uint64_t *slot = (uint64_t *)(sg.seg_part + b0 + i);
+        for (int spins = 0; u[k] == kBEmpty && spins < kBSpinCap; ++spins)
+          u[k] = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slot, kBEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a += u[k] == kBEmpty ? NAN : __longlong_as_double((long long)u[k]);   // never filled: poisons alpha
+      }
+    }
+    sh[tid] = a;
+    col_tree(sh, 256, 8);
+    tot = tid < m ? sh[tid] : 0.0;
+    if (tid == 0) __hip_atomic_store(sg.sys_ticket + s, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (tid < m) {
+    const int col = c0 + tid;
+    if (st.status[col] == BS_RUNNING) {
+      if (!(tot > 0.0)) freeze(st, col, BS_BREAKDOWN);
+      else st.alpha[col] = st.rho[col] / tot;
     }
   }
 }
@@ -846,8 +1063,14 @@ __global__ __launch_bounds__(256) void breduce_rz_kernel(BTables t, BState st, c
 // x = 0 and r = b per system (caller layout -> solver layout), p = q = 0,
 // column state reset. blockIdx.y is the system.
 __global__ __launch_bounds__(256) void binit_kernel(BTables t, double *x, double *r, const double *b, double *p,
-                                                    double *q, int ncols, BState st) {
+                                                    double *q, int ncols, BState st, int32_t *grab, BSegTabs sg) {
   const int s = blockIdx.y;
+  if (s == 0 && blockIdx.x == 0 && threadIdx.x < 8) grab[32 * threadIdx.x] = 0;   // SpMV chunk counters
+  if (blockIdx.x == 0) {   // the system's reduction slots and ticket
+    const int64_t b0 = (int64_t)sg.sys_seg[s] * 8, b1 = (int64_t)sg.sys_seg[s + 1] * 8;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) ((uint64_t *)sg.seg_part)[i] = kBEmpty;
+    if (threadIdx.x == 0) sg.sys_ticket[s] = 0;
+  }
   const int64_t xo = t.sys_xvec[s], vo = t.sys_vec[s];
   const int64_t len = t.sys_xvec[s + 1] - xo, plen = t.sys_vec[s + 1] - vo;
   for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < plen; i += (int64_t)gridDim.x * 256) {
@@ -879,18 +1102,20 @@ struct BPlan {
   int32_t S = 0, ncols = 0;
   int64_t nnz = 0;
   int64_t veclen = 0;
-  std::vector<int32_t> sys_row, sys_m, sys_col, sys_ch, sys_ach, ch_row0, ch_sys, ach_blk, ach_sys;
+  std::vector<int32_t> sys_row, sys_m, sys_col, sys_ch, sys_rpc, sys_pbase, sys_seg, seg_sys, sys_ach, ach_blk,
+      ach_sys;
   std::vector<int64_t> sys_vec, sys_xvec;
   int64_t xlen = 0;
-  std::vector<double> ch_cost, ach_cost;      // modelled HBM bytes of each chunk
+  int32_t nch = 0, nslot = 0;                 // SpMV chunks and their partial (p, q) slots
+  std::vector<int32_t> sched1, run_sys;       // [9] SpMV chunk run of each XCD, [8] system of its first chunk
+  std::vector<double> ach_cost;               // modelled HBM bytes of each apply chunk
 };
 
 static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const int32_t *sys_row,
-                      const int32_t *sys_m, int chunk_rows, int apply_rows, BPlan &pl) {
+                      const int32_t *sys_m, int apply_rows, BPlan &pl) {
   if (!M || S < 1 || !sys_row || !sys_m || sys_row[0] != 0 || sys_row[S] != M->n) return BJAC_EINVAL;
   if (M->kind != 0) return BJAC_EINVAL;  // stored block inverses only
   if (M->storage == BJAC_STORE_SYM) return BJAC_EINVAL;  // full or band storage only
-  if (chunk_rows < kBWaveRows || chunk_rows > (1 << 20)) return BJAC_EINVAL;
   if (apply_rows < kBWaveRows || apply_rows > (1 << 20)) return BJAC_EINVAL;
   pl.S = S;
   pl.nnz = A ? A->nnz : 0;
@@ -913,19 +1138,65 @@ static int make_bplan(const bjac_csr *A, const bjac_handle *M, int32_t S, const 
   pl.veclen = pl.sys_vec[S];
   pl.xlen = pl.sys_xvec[S];
   const double nnz_row = A && A->n > 0 ? (double)A->nnz / (double)A->n : 7.0;
-  // SpMV chunks: row ranges of at most chunk_rows inside one system
-  pl.sys_ch.assign(1, 0);
-  for (int s = 0; s < S; ++s) {
-    const int m = sys_m[s];
-    for (int r = sys_row[s]; r < sys_row[s + 1]; r += chunk_rows) {
-      const int rows = std::min(chunk_rows, sys_row[s + 1] - r);
-      pl.ch_row0.push_back(r);
-      pl.ch_sys.push_back(s);
-      pl.ch_cost.push_back(rows * (nnz_row * 12.0 + 32.0 * m) + 256.0);
+  // SpMV chunks: floor(64 / m) rows of a system with m columns (at most 64
+  // elements, one wave pass), fewer where the longest row of A would overflow
+  // the chunk's LDS slot, numbered system by system; each chunk has m partial
+  // (p, q) slots, a system's after those of the systems before it
+  {
+    const int cap = (kBSlot - 8) / std::max(1, M->max_row_nnz);   // rows whose entries surely fit
+    if (cap < 1) return BJAC_EINVAL;   // a row with more entries than one slot holds
+    pl.sys_ch.assign(1, 0);
+    pl.sys_pbase.assign(1, 0);
+    pl.sys_rpc.resize(S);
+    std::vector<double> cost(S);   // modelled bytes of one chunk of each system
+    int64_t nch = 0, nslot = 0;
+    for (int s = 0; s < S; ++s) {
+      const int m = sys_m[s], R = std::min(64 / m, cap);
+      pl.sys_rpc[s] = R;
+      const int64_t k = (sys_row[s + 1] - sys_row[s] + R - 1) / R;
+      nch += k;
+      nslot += k * m;
+      if (nch >= ((int64_t)1 << 31) || nslot >= ((int64_t)1 << 31)) return BJAC_EINVAL;
+      pl.sys_ch.push_back((int32_t)nch);
+      pl.sys_pbase.push_back((int32_t)nslot);
+      cost[s] = R * (nnz_row * 10.0 + 32.0 * m) + 8.0 * m + 64.0;
     }
-    pl.sys_ch.push_back((int32_t)pl.ch_sys.size());
+    pl.nch = (int32_t)nch;
+    pl.nslot = (int32_t)nslot;
+    // reduction segments of kBSegCh chunks, never across systems
+    pl.sys_seg.assign(1, 0);
+    pl.seg_sys.clear();
+    for (int s = 0; s < S; ++s) {
+      const int k = (pl.sys_ch[s + 1] - pl.sys_ch[s] + kBSegCh - 1) / kBSegCh;
+      pl.seg_sys.insert(pl.seg_sys.end(), k, s);
+      pl.sys_seg.push_back((int32_t)pl.seg_sys.size());
+    }
+    // 8 runs of about equal modelled cost, one per XCD: run x starts at the
+    // chunk where the cost prefix reaches x / 8 of the total
+    double total = 0.0;
+    for (int s = 0; s < S; ++s) total += (pl.sys_ch[s + 1] - pl.sys_ch[s]) * cost[s];
+    pl.sched1.assign(9, 0);
+    pl.sched1[8] = pl.nch;
+    int s = 0;
+    double pre = 0.0;   // cost of the systems before s
+    for (int x = 1; x < 8; ++x) {
+      const double goal = total * x / 8.0;
+      while (s < S - 1 && pre + (pl.sys_ch[s + 1] - pl.sys_ch[s]) * cost[s] < goal) {
+        pre += (pl.sys_ch[s + 1] - pl.sys_ch[s]) * cost[s];
+        ++s;
+      }
+      int64_t c = pl.sys_ch[s] + (int64_t)std::llround((goal - pre) / cost[s]);
+      c = std::min<int64_t>(std::max<int64_t>(c, pl.sys_ch[s]), pl.sys_ch[s + 1]);
+      pl.sched1[x] = (int32_t)std::max<int64_t>(c, pl.sched1[x - 1]);
+    }
+    pl.run_sys.assign(8, S - 1);
+    for (int x = 0; x < 8; ++x) {
+      if (pl.sched1[x] >= pl.nch) continue;   // empty run: never read
+      // the system whose chunk range holds the run's first chunk
+      const auto it = std::upper_bound(pl.sys_ch.begin(), pl.sys_ch.end(), pl.sched1[x]);
+      pl.run_sys[x] = (int32_t)(it - pl.sys_ch.begin()) - 1;
+    }
   }
-  pl.ch_row0.push_back(sys_row[S]);
   // apply chunks: whole blocks, at most apply_rows padded rows, one system
   // each; every system boundary must be a block boundary
   const std::vector<int32_t> &br = M->h_blk_row;
@@ -1001,38 +1272,41 @@ static int bgrid(int units, int wg_per_cu) {
   return std::max(G, 8);
 }
 
-// workgroups of the SpMV that fit on one compute unit at once: its grid is
-// one resident round, so every wave of an XCD sweeps the same window
-static int spmv_resident(int ilp) {
-  static std::map<std::pair<int, int>, int> occ;
+// workgroups of the SpMV that fit on one compute unit at once: its grid is at
+// most one resident round (its waves loop until the counters run out)
+static int spmv_resident(bool rel) {
+  static std::map<std::pair<int, bool>, int> occ;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 2;
-  const int key = ilp == 1 ? 1 : 2;
   std::lock_guard<std::mutex> lk(g_occ_mu);
-  auto it = occ.find({dev, key});
+  auto it = occ.find({dev, rel});
   if (it == occ.end()) {
     int o = 0;
-    const void *k = key == 1 ? (const void *)bspmv_kernel<1> : (const void *)bspmv_kernel<2>;
+    const void *k = rel ? (const void *)bspmv_kernel<true> : (const void *)bspmv_kernel<false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k, 256, 0) != hipSuccess || o < 1) o = 2;
-    it = occ.emplace(std::make_pair(dev, key), o).first;
+    it = occ.emplace(std::make_pair(dev, rel), o).first;
   }
   return it->second;
 }
 
 struct BWs {
   double *r, *z, *pa, *pb, *q, *part1, *part2;
+  double *seg_part;        // [nseg * 8] SpMV reduction segment totals
+  uint32_t *sys_ticket;    // [S]
   double *rho, *alpha, *beta, *rnorm0, *relres;
   int32_t *iter, *status, *n_active;
   int32_t *tabs;   // every int32 table, then both wave schedules
   int64_t *sys_vec, *sys_xvec;
   int16_t *o16;    // [nnz] 16-bit row-relative column indices
   int32_t *rel16;  // 1 while every entry fits 16 bits
+  int32_t *grab;   // [8 * 32] SpMV chunk counter of each XCD run
   size_t bytes;
 };
 
 static size_t tabs_len(const BPlan &p) {
-  return p.sys_row.size() + p.sys_m.size() + p.sys_col.size() + p.sys_ch.size() + p.sys_ach.size() +
-         p.ch_row0.size() + p.ch_sys.size() + p.ach_blk.size() + p.ach_sys.size() + 2 * (kBMaxWaves + 1);
+  return p.sys_row.size() + p.sys_m.size() + p.sys_col.size() + p.sys_ch.size() + p.sys_rpc.size() + p.sys_pbase.size() +
+         p.sys_seg.size() + p.seg_sys.size() +
+         p.sys_ach.size() + p.ach_blk.size() + p.ach_sys.size() + 9 + 8 + (kBMaxWaves + 1);
 }
 
 static BWs carve_b(void *ws, const BPlan &p) {
@@ -1043,7 +1317,9 @@ static BWs carve_b(void *ws, const BPlan &p) {
   w.pa = c.take<double>(p.veclen);
   w.pb = c.take<double>(p.veclen);
   w.q = c.take<double>(p.veclen);
-  w.part1 = c.take<double>((size_t)p.ch_sys.size() * kBCols);
+  w.part1 = c.take<double>((size_t)p.nslot);
+  w.seg_part = c.take<double>(p.seg_sys.size() * 8);
+  w.sys_ticket = c.take<uint32_t>(p.S);
   w.part2 = c.take<double>((size_t)p.ach_sys.size() * 2 * kBCols);
   w.rho = c.take<double>(p.ncols);
   w.alpha = c.take<double>(p.ncols);
@@ -1057,6 +1333,7 @@ static BWs carve_b(void *ws, const BPlan &p) {
   w.sys_vec = c.take<int64_t>(p.sys_vec.size());
   w.sys_xvec = c.take<int64_t>(p.sys_xvec.size());
   w.rel16 = c.take<int32_t>(1);
+  w.grab = c.take<int32_t>(8 * 32);
   w.o16 = p.nnz > 0 ? c.take<int16_t>(p.nnz) : nullptr;
   w.bytes = c.used;
   return w;
@@ -1070,8 +1347,10 @@ struct BCtx {
   BState st{};
   DevMap map{};
   int G1 = 8, G2 = 8;
-  int ilp = 1;
-  const int32_t *sched1 = nullptr, *sched2 = nullptr;
+  int grab_k = 1;
+  bool rel = false;   // the SpMV reads the 16-bit col - row copy
+  BSegTabs sg{};
+  const int32_t *sched1 = nullptr, *run_sys = nullptr, *sys_pbase = nullptr, *sched2 = nullptr;
   const bjac_csr *A = nullptr;
   const bjac_handle *M = nullptr;
   const double *b = nullptr;
@@ -1079,11 +1358,16 @@ struct BCtx {
 };
 
 // defaults: the shape the autotuner picked for the 256-system workload
-static void cfg_defaults(const bjac_batch_cfg *cfg, int &chunk_rows, int &wg_per_cu, int &ilp, int &apply_rows) {
-  chunk_rows = cfg && cfg->chunk_rows > 0 ? cfg->chunk_rows : 128;
-  apply_rows = cfg && cfg->apply_rows > 0 ? cfg->apply_rows : 512;
+static void cfg_defaults(const bjac_batch_cfg *cfg, int &grab, int &wg_per_cu, int &spmv_wg, int &apply_rows) {
+  grab = cfg && cfg->spmv_grab > 0 ? cfg->spmv_grab : 4;
   wg_per_cu = cfg && cfg->wg_per_cu > 0 ? cfg->wg_per_cu : 32;
-  ilp = cfg && cfg->spmv_ilp > 0 ? cfg->spmv_ilp : 1;
+  spmv_wg = cfg && cfg->spmv_wg_per_cu > 0 ? cfg->spmv_wg_per_cu : 32;
+  apply_rows = cfg && cfg->apply_rows > 0 ? cfg->apply_rows : 512;
+}
+
+static bool cfg_valid(const bjac_batch_cfg *cfg) {
+  return !cfg || (cfg->spmv_grab >= 0 && cfg->spmv_grab <= 64 && cfg->wg_per_cu >= 0 && cfg->wg_per_cu <= 32 &&
+                  cfg->spmv_wg_per_cu >= 0 && cfg->spmv_wg_per_cu <= 32 && cfg->apply_rows >= 0);
 }
 
 static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, const int32_t *sys_row,
@@ -1091,19 +1375,17 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
                      const bjac_batch_cfg *cfg, void *workspace, size_t workspace_bytes, hipStream_t s, BCtx &c) {
   if (!A || !M || !b || !x || !workspace || b == x || A->n != M->n) return BJAC_EINVAL;
   if (!(tol >= 0.0) || maxit < 1) return BJAC_EINVAL;
-  int chunk_rows, wg_per_cu, ilp, apply_rows;
-  cfg_defaults(cfg, chunk_rows, wg_per_cu, ilp, apply_rows);
-  if (wg_per_cu > 32 || ilp > 2) return BJAC_EINVAL;
-  c.ilp = ilp;
-  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, apply_rows, c.pl);
+  if (!cfg_valid(cfg)) return BJAC_EINVAL;
+  int grab, wg_per_cu, spmv_wg, apply_rows;
+  cfg_defaults(cfg, grab, wg_per_cu, spmv_wg, apply_rows);
+  c.grab_k = grab;
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, apply_rows, c.pl);
   if (rc) return rc;
   c.w = carve_b(workspace, c.pl);
   if (c.w.bytes > workspace_bytes) return BJAC_ENOMEM;
   const BPlan &pl = c.pl;
-  c.G1 = bgrid((int)pl.ch_sys.size(), std::min(wg_per_cu, spmv_resident(ilp)));
   c.G2 = bgrid((int)pl.ach_sys.size(), wg_per_cu);
-  std::vector<int32_t> sch1, sch2;
-  split_cost(pl.ch_cost, 8, sch1);
+  std::vector<int32_t> sch2;
   split_cost(pl.ach_cost, c.G2 * 4, sch2);
   // tables, uploaded once per call
   std::vector<int32_t> tabs;
@@ -1114,8 +1396,8 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
     return o;
   };
   const size_t o_row = put(pl.sys_row), o_m = put(pl.sys_m), o_col = put(pl.sys_col), o_ch = put(pl.sys_ch),
-               o_ach = put(pl.sys_ach), o_chr = put(pl.ch_row0), o_chs = put(pl.ch_sys), o_ab = put(pl.ach_blk),
-               o_as = put(pl.ach_sys), o_s1 = put(sch1), o_s2 = put(sch2);
+               o_rpc = put(pl.sys_rpc), o_pb = put(pl.sys_pbase), o_sseg = put(pl.sys_seg), o_segs = put(pl.seg_sys), o_ach = put(pl.sys_ach), o_ab = put(pl.ach_blk), o_as = put(pl.ach_sys),
+               o_s1 = put(pl.sched1), o_rs = put(pl.run_sys), o_s2 = put(sch2);
   MPB_HIP(hipMemcpyAsync(c.w.tabs, tabs.data(), tabs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   MPB_HIP(hipMemcpyAsync(c.w.sys_vec, pl.sys_vec.data(), pl.sys_vec.size() * sizeof(int64_t),
                          hipMemcpyHostToDevice, s));
@@ -1126,27 +1408,35 @@ static int bctx_make(const bjac_csr *A, const bjac_handle *M, int32_t nsys, cons
   // the host vectors above go out of scope at return: wait for the copies
   MPB_HIP(hipStreamSynchronize(s));
   // the 16-bit copy of the column structure the matrix-vector products read
+  // (the SpMV kernel is chosen by whether every entry fits 16 bits)
+  c.rel = false;
   if (c.w.o16 && A->n < ((int64_t)1 << 31)) {
     if ((rc = launch_off16((int)A->n, A->row_ptr, A->col_idx, c.w.o16, c.w.rel16, s))) return rc;
-  } else if (c.w.o16) {
-    c.w.o16 = nullptr;
+    int32_t fits = 0;
+    MPB_HIP(hipMemcpyAsync(&fits, c.w.rel16, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MPB_HIP(hipStreamSynchronize(s));
+    c.rel = fits != 0;
   }
+  if (!c.rel) c.w.o16 = nullptr;
+  c.G1 = bgrid(pl.nch, std::min(spmv_wg, spmv_resident(c.rel)));
   BTables &t = c.t;
   t.S = pl.S;
-  t.nch = (int32_t)pl.ch_sys.size();
+  t.nch = pl.nch;
   t.nach = (int32_t)pl.ach_sys.size();
   t.sys_row = c.w.tabs + o_row;
   t.sys_m = c.w.tabs + o_m;
   t.sys_col = c.w.tabs + o_col;
   t.sys_ch = c.w.tabs + o_ch;
+  t.sys_rpc = c.w.tabs + o_rpc;
   t.sys_ach = c.w.tabs + o_ach;
-  t.ch_row0 = c.w.tabs + o_chr;
-  t.ch_sys = c.w.tabs + o_chs;
   t.ach_blk = c.w.tabs + o_ab;
   t.ach_sys = c.w.tabs + o_as;
   t.sys_vec = c.w.sys_vec;
   t.sys_xvec = c.w.sys_xvec;
+  c.sys_pbase = c.w.tabs + o_pb;
+  c.sg = BSegTabs{c.w.tabs + o_segs, c.w.tabs + o_sseg, c.w.tabs + o_pb, c.w.seg_part, c.w.sys_ticket};
   c.sched1 = c.w.tabs + o_s1;
+  c.run_sys = c.w.tabs + o_rs;
   c.sched2 = c.w.tabs + o_s2;
   c.st = BState{c.w.rho, c.w.alpha, c.w.beta, c.w.rnorm0, c.w.relres, c.w.iter, c.w.status, c.w.n_active, tol, maxit};
   c.map = DevMap{M->ws, M->off_lo, M->scale_lo, M->tag_lo, M->w_lo};
@@ -1169,20 +1459,23 @@ static void benq_spmv_k(const BCtx &c, const double *pold, double *pnew, hipStre
   a.q = c.w.q;
   a.beta = c.w.beta;
   a.part = c.w.part1;
+  a.sys_pbase = c.sys_pbase;
   a.n_active = c.w.n_active;
   a.sched = c.sched1;
+  a.run_sys = c.run_sys;
+  a.grab = c.w.grab;
+  a.grab_k = c.grab_k;
   a.o16 = c.w.o16;
-  a.rel16 = c.w.rel16;
-  a.nnz8 = (int32_t)(c.A->nnz & ~(int64_t)7);
-  a.vec = (((uintptr_t)c.A->val | (uintptr_t)c.A->col_idx | (uintptr_t)c.w.o16) & 15) == 0;
-  if (c.ilp == 1)
-    hipLaunchKernelGGL(bspmv_kernel<1>, dim3(c.G1), dim3(256), 0, s, a);
+  a.nnz = (int32_t)c.A->nnz;
+  if (c.rel)
+    hipLaunchKernelGGL(bspmv_kernel<true>, dim3(c.G1), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL(bspmv_kernel<2>, dim3(c.G1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(bspmv_kernel<false>, dim3(c.G1), dim3(256), 0, s, a);
 }
 
 static void benq_spmv_r(const BCtx &c, hipStream_t s) {
-  hipLaunchKernelGGL(breduce_pq_kernel, dim3(c.t.S), dim3(256), 0, s, c.t, c.st, (const double *)c.w.part1);
+  hipLaunchKernelGGL(breduce_pq_kernel, dim3((unsigned)c.pl.seg_sys.size()), dim3(256), 0, s, c.t, c.st,
+                     (const double *)c.w.part1, c.sg, c.w.grab);
 }
 
 static void benq_spmv(const BCtx &c, const double *pold, double *pnew, hipStream_t s) {
@@ -1231,7 +1524,7 @@ static void benq_apply(const BCtx &c, const double *p, int init, hipStream_t s) 
 // alpha = 0, which also yields ||r_0|| and rho_0
 static void benq_init(const BCtx &c, hipStream_t s) {
   hipLaunchKernelGGL(binit_kernel, dim3(64, c.t.S), dim3(256), 0, s, c.t, c.x, c.w.r, c.b, c.w.pa, c.w.q,
-                     c.pl.ncols, c.st);
+                     c.pl.ncols, c.st, c.w.grab, c.sg);
   benq_apply(c, c.w.pa, 1, s);
 }
 
@@ -1352,11 +1645,11 @@ using namespace mpb;
 extern "C" int pcg_batched_workspace_query(const bjac_csr *A, const bjac_handle *M, int32_t nsys,
                                            const int32_t *sys_row, const int32_t *sys_m,
                                            const bjac_batch_cfg *cfg, size_t *workspace_bytes) {
-  if (!workspace_bytes || !A) return BJAC_EINVAL;
-  int chunk_rows, wg_per_cu, ilp, apply_rows;
-  cfg_defaults(cfg, chunk_rows, wg_per_cu, ilp, apply_rows);
+  if (!workspace_bytes || !A || !cfg_valid(cfg)) return BJAC_EINVAL;
+  int grab, wg_per_cu, spmv_wg, apply_rows;
+  cfg_defaults(cfg, grab, wg_per_cu, spmv_wg, apply_rows);
   BPlan p;
-  int rc = make_bplan(A, M, nsys, sys_row, sys_m, chunk_rows, apply_rows, p);
+  int rc = make_bplan(A, M, nsys, sys_row, sys_m, apply_rows, p);
   if (rc) return rc;
   *workspace_bytes = carve_b(nullptr, p).bytes;
   return BJAC_OK;

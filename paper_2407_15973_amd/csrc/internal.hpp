@@ -105,6 +105,7 @@ struct bjac_handle {
   std::vector<uint8_t> h_w_lo, h_w_hi;
   float *feat = nullptr;         // [nb*16]
   int32_t *flags = nullptr;      // [nb] non-SPD marks
+  int32_t max_row_nnz = 0;       // most entries in one row of the A given at setup
   // host copies
   std::vector<int32_t> h_blk_row;
   std::vector<uint8_t> h_bpad;

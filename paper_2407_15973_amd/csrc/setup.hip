@@ -200,6 +200,15 @@ __device__ __forceinline__ int ceil_log2(double v) {
 
 // One wave per diagonal block; lane i owns row i of the padded block
 // diag(A_ii, I) (padded size B = b rounded up to a multiple of 16).
+// Most entries in one row of the CSR (into *out, zeroed beforehand).
+__global__ __launch_bounds__(256) void max_row_kernel(int64_t n, const int32_t *rp, int32_t *out) {
+  int m = 0;
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = max(m, rp[i + 1] - rp[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
+}
+
 template <int B>
 __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a) {
   const int wid = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -510,6 +519,7 @@ static int make_plan(const bjac_csr *A, const int32_t *bp, int32_t nb, const bja
 
 struct Layout {
   int32_t *blk_row, *tile_blk, *flags, *blist, *any_bad;
+  int32_t *max_row;   // [1] most entries in one row of A
   uint8_t *bpad;
   int64_t *off_lo, *off_hi;
   double *scale_lo, *scale_hi;
@@ -528,6 +538,7 @@ static Layout carve(void *ws, const Plan &pl) {
   L.bpad = c.take<uint8_t>(nb);
   L.flags = c.take<int32_t>(nb);
   L.any_bad = c.take<int32_t>(1);
+  L.max_row = c.take<int32_t>(1);
   L.blist = c.take<int32_t>(nb);
   L.off_lo = c.take<int64_t>(nb);
   L.off_hi = c.take<int64_t>(nb);
@@ -611,8 +622,13 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
       hipMemcpyAsync(L.tile_blk, pl.tiles.data(), sizeof(int32_t) * pl.tiles.size(), hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(L.bpad, pl.bpad.data(), nb, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(L.blist, blist.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, st) ||
-      hipMemsetAsync(L.flags, 0, sizeof(int32_t) * nb, st) || hipMemsetAsync(L.any_bad, 0, sizeof(int32_t), st))
+      hipMemsetAsync(L.flags, 0, sizeof(int32_t) * nb, st) || hipMemsetAsync(L.any_bad, 0, sizeof(int32_t), st) ||
+      hipMemsetAsync(L.max_row, 0, sizeof(int32_t), st))
     return fail(BJAC_EHIP);
+  {
+    const int g = (int)std::min<int64_t>(1024, (A->n + 255) / 256);
+    hipLaunchKernelGGL(max_row_kernel, dim3(std::max(g, 1)), dim3(256), 0, st, (int64_t)A->n, A->row_ptr, L.max_row);
+  }
 
   SetupArgs a{};
   a.rp = A->row_ptr;
@@ -727,9 +743,11 @@ extern "C" int bjac_setup(const bjac_csr *A, const int32_t *block_ptr, int32_t n
   p2.w_hi = (band && pl.temporal) ? L.w_hi : nullptr;
   p2.sym = sym ? 1 : 0;
   if ((rc = launch_setup(p2, cls, L.blist, st))) return fail(rc);
-  int32_t bad = 0;
-  if (hipMemcpyAsync(&bad, L.any_bad, sizeof(int32_t), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
+  int32_t bad = 0, max_row = 0;
+  if (hipMemcpyAsync(&bad, L.any_bad, sizeof(int32_t), hipMemcpyDeviceToHost, st) ||
+      hipMemcpyAsync(&max_row, L.max_row, sizeof(int32_t), hipMemcpyDeviceToHost, st) || hipStreamSynchronize(st))
     return fail(BJAC_EHIP);
+  h->max_row_nnz = max_row;
   if (bad) return fail(BJAC_ENOTSPD);
   h->h_tag_lo = tags;
   h->uprec_lo = tags[0];
