@@ -104,8 +104,8 @@ VERIFY = 3
 # workload and kernel. Valid only for the kernel sources they were measured
 # on: reported when the digest of those sources matches, null otherwise.
 TRAFFIC = {
-    "heldout_192:apply": ("1c98752db4f5c5db44f888fd054fa46330afbddc5ae3fb91edc2725d078ee668", 851017765),
-    "heldout_192:spmv": ("1c98752db4f5c5db44f888fd054fa46330afbddc5ae3fb91edc2725d078ee668", 754355794),
+    "heldout_192:apply": ("3cc340f9aac6b0a933206cd6c944563e3173ab30d8c8c8ac21a00c3b1ca9956d", 850998990),
+    "heldout_192:spmv": ("3cc340f9aac6b0a933206cd6c944563e3173ab30d8c8c8ac21a00c3b1ca9956d", 752172012),
 }
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
