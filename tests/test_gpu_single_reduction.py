@@ -64,17 +64,25 @@ def test_diffusion_maps_match_oracle(b, prec, storage, slack):
 
 
 def test_rule_map_generic_kernel_matches_oracle():
-    # a per-block rule map of several formats: the per-block dispatch kernel
+    # a per-block rule map of several formats (FP64 and FP32 blocks): the
+    # per-block dispatch kernel. The GPU accumulates the FP32 blocks' products
+    # in FP32, the oracle exactly: a perturbation of M at the FP32 unit
+    # roundoff, which this recurrence carries further than the textbook one
+    # (its recursively updated s = A p drifts), so the count is held to the
+    # reduced-map bar, max(3, 5 %), and the histories to 1e-4 over the first
+    # 60 iterations
     p = gen.aniso_jump_problem(seed=3, N=24, b=48)
     A, bp, rhs = p.A, p.block_ptr, p.b
     Ad = mb.DeviceCSR(A, dev())
     M = mb.BlockJacobi(Ad, bp, mb.Policy(mode=mb.RULE))
     tags = M.tags()
     assert len(set(tags.tolist())) > 1
-    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(rhs), tol=1e-10, maxit=3000, variant=SR)
+    res = mb.Solver(A.n, dev()).solve(Ad, M, tensor(rhs), tol=1e-10, maxit=3000, variant=SR, history=True)
     ref = _oracle(A, bp, rhs, tags, 1e-10, 3000)
     assert res.status == mb.OK and ref.status == OP.CONVERGED
-    assert abs(res.iters - ref.iters) <= 2, (res.iters, ref.iters)
+    assert abs(res.iters - ref.iters) <= max(3, 0.05 * ref.iters), (res.iters, ref.iters)
+    m = min(res.iters, ref.iters, 60)
+    np.testing.assert_allclose(res.relres_hist[:m], ref.history[:m], rtol=1e-4)
     assert OP.true_relres(A, res.x.cpu().numpy(), rhs) <= 2e-10
 
 
