@@ -104,8 +104,8 @@ VERIFY = 3
 # workload and kernel. Valid only for the kernel sources they were measured
 # on: reported when the digest of those sources matches, null otherwise.
 TRAFFIC = {
-    "heldout_192:apply": ("3cc340f9aac6b0a933206cd6c944563e3173ab30d8c8c8ac21a00c3b1ca9956d", 850998990),
-    "heldout_192:spmv": ("3cc340f9aac6b0a933206cd6c944563e3173ab30d8c8c8ac21a00c3b1ca9956d", 752172012),
+    "heldout_192:apply": ("921e6c5eba8bd699af1d6a8e7db9bb220aabff4d6ea38e76a483fa9b632f3c0e", 873080704),
+    "heldout_192:spmv": ("921e6c5eba8bd699af1d6a8e7db9bb220aabff4d6ea38e76a483fa9b632f3c0e", 922992420),
 }
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 

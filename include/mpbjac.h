@@ -364,7 +364,9 @@ int pcg_solve_noalloc(const bjac_csr *A, const bjac_handle *M, const double *b, 
 /* Launch shape. The matrix-vector product cuts every system into chunks of
  * floor(64 / m) rows (at most 64 (row, column) elements, one wave pass); the
  * chunks are split into 8 runs of about equal cost, one per XCD, whose waves
- * take them in increasing order from a counter of that run. */
+ * take them in increasing order from a counter of that run. The update +
+ * apply cuts every system into chunks of whole blocks (at most apply_rows
+ * padded rows) and deals them round-robin over all waves of its grid. */
 typedef struct {
   int32_t spmv_grab;       /* matrix-vector chunks a wave takes per counter
                               grab (1..64; 0 = 4)                             */
@@ -373,7 +375,7 @@ typedef struct {
                               most 8192 workgroups                            */
   int32_t spmv_wg_per_cu;  /* the same for the matrix-vector launch, at most
                               what is resident at once (1..32; 0 = 32)        */
-  int32_t apply_rows;      /* padded rows per apply chunk (>= 64; 0 = 512).
+  int32_t apply_rows;      /* padded rows per apply chunk (>= 64; 0 = 256).
                               Chunks never cross systems.                     */
 } bjac_batch_cfg;
 
