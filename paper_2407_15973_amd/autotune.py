@@ -22,7 +22,7 @@ import numpy as np
 
 from . import binding as mb
 
-CANDIDATES = tuple((g, w, 32, ar) for g in (2, 4, 8) for w in (8, 32) for ar in (256, 512))
+CANDIDATES = tuple((g, w, sw, ar) for g in (4, 8) for w in (8, 32) for sw in (3, 32) for ar in (256, 512))
 
 
 def default_cache_path() -> str:

@@ -126,17 +126,25 @@ struct BSysState {
   int64_t vsys;          // start of its block in the solver's vectors
 };
 
+// Every field is moved into a scalar register as it is loaded, so the wait
+// for these loads stays inside the (rare) branch that fetches a new system:
+// values left in vector registers would make the compiler wait for them at
+// their first use after the branches join, on every step, and that wait
+// would also drain the next chunk's loads issued in between.
 __device__ __forceinline__ void bsys_fetch(const BSpmvArgs &a, int s, BSysState &y) {
+  const int32_t *ch = a.t.sys_ch + s, *row = a.t.sys_row + s;
   y.s = s;
-  y.chs = a.t.sys_ch[s];
-  y.che = a.t.sys_ch[s + 1];
-  y.rs = a.t.sys_row[s];
-  y.nrows = a.t.sys_row[s + 1] - y.rs;
-  y.m = a.t.sys_m[s];
-  y.R = a.t.sys_rpc[s];
-  y.c0 = a.t.sys_col[s];
-  y.pbase = a.sys_pbase[s];
-  y.vsys = a.t.sys_vec[s];
+  y.chs = __builtin_amdgcn_readfirstlane(ch[0]);
+  y.che = __builtin_amdgcn_readfirstlane(ch[1]);
+  y.rs = __builtin_amdgcn_readfirstlane(row[0]);
+  y.nrows = __builtin_amdgcn_readfirstlane(row[1]) - y.rs;
+  y.m = __builtin_amdgcn_readfirstlane(a.t.sys_m[s]);
+  y.R = __builtin_amdgcn_readfirstlane(a.t.sys_rpc[s]);
+  y.c0 = __builtin_amdgcn_readfirstlane(a.t.sys_col[s]);
+  y.pbase = __builtin_amdgcn_readfirstlane(a.sys_pbase[s]);
+  const uint64_t v = (uint64_t)a.t.sys_vec[s];
+  y.vsys = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+                     __builtin_amdgcn_readfirstlane((uint32_t)v));
 }
 
 // A chunk in the pipeline (wave-uniform): its index, first row and rows;
