@@ -362,6 +362,26 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
 constexpr int kVmcntZero = 0x0F70;
 
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+
+// Cache hints of the streaming solves (NT = true): non-temporal loads and
+// stores for data that one launch touches once, when the bytes of an
+// iteration are far beyond what the last-level cache can keep from one
+// iteration to the next; plain accesses otherwise.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_hint(const T *p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_hint(T v, T *p) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 // The tiles of one wave; returns the wave's partial (p_new, q). REL: the
 // column indices are the 16-bit row-relative copy (one loop per choice,
@@ -384,7 +404,7 @@ struct Dots3 {
   double a = 0.0, b = 0.0, c = 0.0;
 };
 
-template <int SM, int IX>
+template <int SM, int IX, bool NT>
 __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc, const int *dict) {
   constexpr bool PCG = SM == SPMV_PCG;   // p = z + beta p_old gathered, (p, q)
   constexpr bool CG = SM == SPMV_CG;     // u gathered, (r, r), (r, u), (w, u)
@@ -461,8 +481,8 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
     u32x4 hv[NV], hc[NC];
     stage(base_n, need_n, hv, hc);
     if (s_has) {
-      a.q[s_row] = s_q;
-      if (PCG) a.pnew[s_row] = s_p;
+      st_hint<NT>(s_q, a.q + s_row);
+      if (PCG) st_hint<NT>(s_p, a.pnew + s_row);
       s_has = false;
     }
     const int row = it.t * 64 + lane;
@@ -514,8 +534,8 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
     for (int q = 0; q < NC; ++q) gc[q] = hc[q];
   }
   if (s_has) {
-    a.q[s_row] = s_q;
-    if (PCG) a.pnew[s_row] = s_p;
+    st_hint<NT>(s_q, a.q + s_row);
+    if (PCG) st_hint<NT>(s_p, a.pnew + s_row);
   }
   return dot;
 }
@@ -569,7 +589,7 @@ __device__ __forceinline__ void cg_after_spmv(PcgState *st, double rr, double ga
   if (st->iter >= st->maxit) st->status = ST_MAXIT;
 }
 
-template <int SM>
+template <int SM, bool NT = false>
 __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   constexpr bool PCG = SM == SPMV_PCG;
   constexpr bool CG = SM == SPMV_CG;
@@ -591,14 +611,14 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
     if (ix == IX8) {
       sdict[threadIdx.x] = a.dict[threadIdx.x];
       __syncthreads();
-      dot = spmv_tiles<SM, IX8>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX8, NT>(a, beta, svs[wv], scs[wv], sdict);
     } else if (ix == IX16) {
-      dot = spmv_tiles<SM, IX16>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX16, NT>(a, beta, svs[wv], scs[wv], sdict);
     } else {
-      dot = spmv_tiles<SM, IX32>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX32, NT>(a, beta, svs[wv], scs[wv], sdict);
     }
   } else {
-    dot = spmv_tiles<SPMV_PLAIN, IX32>(a, beta, svs[wv], scs[wv], sdict);
+    dot = spmv_tiles<SPMV_PLAIN, IX32, NT>(a, beta, svs[wv], scs[wv], sdict);
   }
   if constexpr (PCG) {
     const double bs = block_sum(dot.a, sh);
@@ -677,15 +697,19 @@ struct Frag {
   static constexpr int G = (K + V - 1) / V;
   uint4 h[G];
 
+  // NT: non-temporal loads (streaming solves, where the stored inverses
+  // cannot stay in the last-level cache from one iteration to the next)
+  template <bool NT = false>
   __device__ __forceinline__ void load(const uint8_t *blk, int mt, int lane) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int vg = layout_vg(B, V, g);
       const uint8_t *src = blk + (layout_group_base(B, V, mt, g) + (int64_t)lane * vg) * BY;
       if (vg * BY == 16) {
-        h[g] = *(const uint4 *)src;
+        const u32x4 t = NT ? __builtin_nontemporal_load((const u32x4 *)src) : *(const u32x4 *)src;
+        h[g] = make_uint4(t.x, t.y, t.z, t.w);
       } else {
-        const uint2 t = *(const uint2 *)src;
+        const u32x2 t = NT ? __builtin_nontemporal_load((const u32x2 *)src) : *(const u32x2 *)src;
         h[g] = make_uint4(t.x, t.y, 0u, 0u);
       }
     }
@@ -787,12 +811,13 @@ struct SymB {
   Frag<W3, P> f3;
   using CT = std::conditional_t<P == P64, double, float>;
 
+  template <bool NT = false>
   __device__ __forceinline__ void load(const uint8_t *blk, int lane) {
     constexpr int BY = prec_bytes(P);
-    f0.load(blk, 0, lane);
-    f1.load(blk + (int64_t)sym_strip_off(B, 1) * BY, 0, lane);
-    if constexpr (M >= 3) f2.load(blk + (int64_t)sym_strip_off(B, 2) * BY, 0, lane);
-    if constexpr (M >= 4) f3.load(blk + (int64_t)sym_strip_off(B, 3) * BY, 0, lane);
+    f0.template load<NT>(blk, 0, lane);
+    f1.template load<NT>(blk + (int64_t)sym_strip_off(B, 1) * BY, 0, lane);
+    if constexpr (M >= 3) f2.template load<NT>(blk + (int64_t)sym_strip_off(B, 2) * BY, 0, lane);
+    if constexpr (M >= 4) f3.template load<NT>(blk + (int64_t)sym_strip_off(B, 3) * BY, 0, lane);
   }
 
   // lane (i, kq)'s share of (H_JI^T r_J)[4 s + kq] for every J < I: its entry
@@ -843,22 +868,22 @@ struct SymB {
   }
 };
 
-template <int B, int P>
+template <int B, int P, bool NT>
 __device__ __forceinline__ void sym_apply(const uint8_t *blk, const float *r32, const double *r64, double sc,
                                           double *zt, double *tt, int lane) {
   SymB<B, P> f;
-  f.load(blk, lane);
+  f.template load<NT>(blk, lane);
   f.apply(r32, r64, sc, zt, tt, lane);
 }
 
-template <int B>
+template <int B, bool NT>
 __device__ __forceinline__ void sym_apply_p(int prec, const uint8_t *blk, const float *r32, const double *r64,
                                             double sc, double *zt, double *tt, int lane) {
   switch (prec) {
-    case P64: sym_apply<B, P64>(blk, r32, r64, sc, zt, tt, lane); break;
-    case P32: sym_apply<B, P32>(blk, r32, r64, sc, zt, tt, lane); break;
-    case PBF16: sym_apply<B, PBF16>(blk, r32, r64, sc, zt, tt, lane); break;
-    default: sym_apply<B, P16>(blk, r32, r64, sc, zt, tt, lane); break;
+    case P64: sym_apply<B, P64, NT>(blk, r32, r64, sc, zt, tt, lane); break;
+    case P32: sym_apply<B, P32, NT>(blk, r32, r64, sc, zt, tt, lane); break;
+    case PBF16: sym_apply<B, PBF16, NT>(blk, r32, r64, sc, zt, tt, lane); break;
+    default: sym_apply<B, P16, NT>(blk, r32, r64, sc, zt, tt, lane); break;
   }
 }
 
@@ -950,15 +975,15 @@ __device__ __forceinline__ UpdCoef upd_coef(const ApplyArgs &a) {
   return c;
 }
 
-template <int MODE>
+template <int MODE, bool NT = false>
 __device__ __forceinline__ RowIn row_load(const ApplyArgs &a, bool real, int grow) {
   const int gc = min(max(grow, 0), a.n - 1);
   RowIn v{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if constexpr (ModeTraits<MODE>::UPD) {
-    v.x = a.x[gc];
-    v.p = a.p[gc];
-    v.q = a.q[gc];
-    v.r = a.r[gc];
+    v.x = ld_hint<NT>(a.x + gc);
+    v.p = ld_hint<NT>(a.p + gc);
+    v.q = ld_hint<NT>(a.q + gc);
+    v.r = ld_hint<NT>(a.r + gc);
   } else if constexpr (ModeTraits<MODE>::CG) {
     v.x = a.x[gc];
     v.p = a.pw[gc];
@@ -994,18 +1019,18 @@ __device__ __forceinline__ double row_update(const RowIn &v, const UpdCoef &c, d
   }
 }
 
-template <int MODE>
+template <int MODE, bool NT = false>
 __device__ __forceinline__ void row_store(const ApplyArgs &a, const RowHold &h) {
   if (!h.real) return;
   if constexpr (ModeTraits<MODE>::UPD || ModeTraits<MODE>::CG) {
-    a.x[h.grow] = h.x;
-    a.r[h.grow] = h.r;
+    st_hint<NT>(h.x, a.x + h.grow);
+    st_hint<NT>(h.r, a.r + h.grow);
   }
   if constexpr (ModeTraits<MODE>::CG) {
     a.pw[h.grow] = h.p;
     a.sw[h.grow] = h.s;
   }
-  if constexpr (ModeTraits<MODE>::APP) a.z[h.grow] = h.z;
+  if constexpr (ModeTraits<MODE>::APP) st_hint<NT>(h.z, a.z + h.grow);
 }
 
 // Reductions and the state machine at the end of a PCG launch.
@@ -1060,7 +1085,7 @@ __device__ __forceinline__ bool apply_skip(const ApplyArgs &a) {
 // a tile are all requested before the first wait.
 // SYM: blocks of 32 to 64 in symmetric storage (the quarters below the
 // diagonal taken as transposes of stored ones).
-template <int B, int P, int MODE, bool SYM = false>
+template <int B, int P, int MODE, bool SYM = false, bool NT = false>
 __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
   static_assert(!SYM || B >= 32, "symmetric storage holds blocks of 32 to 64");
   using T = ModeTraits<MODE>;
@@ -1101,14 +1126,15 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
       if constexpr (P != P64) scl = scale[min(k0 + lane % NB, a.nb - 1)];
       if constexpr (SYM) {
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) fs[jb].load(base + (int64_t)min(k0 + jb, a.nb - 1) * BLK, lane);
+        for (int jb = 0; jb < NB; ++jb) fs[jb].template load<NT>(base + (int64_t)min(k0 + jb, a.nb - 1) * BLK, lane);
       } else if constexpr (PRE) {
 #pragma unroll
-        for (int u = 0; u < MT; ++u) fr[u].load(base + (int64_t)min(k0 + u / MPB, a.nb - 1) * BLK, u % MPB, lane);
+        for (int u = 0; u < MT; ++u)
+          fr[u].template load<NT>(base + (int64_t)min(k0 + u / MPB, a.nb - 1) * BLK, u % MPB, lane);
       }
     }
-    const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, hold);
+    const RowIn v = row_load<MODE, NT>(a, real, grow);
+    row_store<MODE, NT>(a, hold);
     RowHold nh;
     const double rv = row_update<MODE>(v, cf, rr, nh);
     double zv_out = 0.0;
@@ -1138,7 +1164,7 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
             zv = fr[u].dot(r32 + cb, r64 + cb, lane);
           } else {
             F f;
-            f.load(base + (int64_t)(k0 + jb) * BLK, u % MPB, lane);
+            f.template load<NT>(base + (int64_t)(k0 + jb) * BLK, u % MPB, lane);
             zv = f.dot(r32 + cb, r64 + cb, lane);
           }
           const double sc = (P == P64) ? 1.0 : bcast(scl, jb);
@@ -1157,18 +1183,18 @@ __global__ __launch_bounds__(256) void apply_fast_kernel(ApplyArgs a) {
     nh.z = zv_out;
     hold = nh;
   }
-  row_store<MODE>(a, hold);
+  row_store<MODE, NT>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
-template <int B>
+template <int B, bool NT>
 __device__ __forceinline__ double mtile_dot(int prec, const uint8_t *blk, int mt, const float *r32, const double *r64,
                                             int lane) {
   switch (prec) {
-    case P64: { Frag<B, P64> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
-    case P32: { Frag<B, P32> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
-    case PBF16: { Frag<B, PBF16> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
-    default: { Frag<B, P16> f; f.load(blk, mt, lane); return f.dot(r32, r64, lane); }
+    case P64: { Frag<B, P64> f; f.template load<NT>(blk, mt, lane); return f.dot(r32, r64, lane); }
+    case P32: { Frag<B, P32> f; f.template load<NT>(blk, mt, lane); return f.dot(r32, r64, lane); }
+    case PBF16: { Frag<B, PBF16> f; f.template load<NT>(blk, mt, lane); return f.dot(r32, r64, lane); }
+    default: { Frag<B, P16> f; f.template load<NT>(blk, mt, lane); return f.dot(r32, r64, lane); }
   }
 }
 
@@ -1183,7 +1209,7 @@ __device__ __forceinline__ int64_t readlane_l(int64_t v, int src) {
 // (up to 4 blocks, at most 64 padded rows, from the setup's tile list) reads
 // its blocks' metadata with one lane-parallel load per array and broadcasts it;
 // each 16-row tile dispatches on its block's size and precision.
-template <int MODE>
+template <int MODE, bool NT = false>
 __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
   using T = ModeTraits<MODE>;
   __shared__ float r32s[4][64];
@@ -1226,8 +1252,8 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
     }
     const bool real = li >= 0 && li < bsz;
     const int grow = row0 + li;
-    const RowIn v = row_load<MODE>(a, real, grow);
-    row_store<MODE>(a, hold);
+    const RowIn v = row_load<MODE, NT>(a, real, grow);
+    row_store<MODE, NT>(a, hold);
     RowHold nh;
     const double rv = row_update<MODE>(v, cf, rr, nh);
     double zv_out = 0.0;
@@ -1245,9 +1271,9 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
         const double sc = bcast(msc, i);
         if (B >= 32 && a.map.sym) {
           switch (B) {
-            case 32: sym_apply_p<32>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
-            case 48: sym_apply_p<48>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
-            default: sym_apply_p<64>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            case 32: sym_apply_p<32, NT>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            case 48: sym_apply_p<48, NT>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
+            default: sym_apply_p<64, NT>(prec, blk, r32 + cb, r64 + cb, sc, zt + cb, tts[wv] + cb, lane); break;
           }
           cb += B;
           continue;
@@ -1255,10 +1281,10 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
         for (int mt = 0; mt < B / 16; ++mt) {
           double zv;
           switch (B) {
-            case 16: zv = mtile_dot<16>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
-            case 32: zv = mtile_dot<32>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
-            case 48: zv = mtile_dot<48>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
-            default: zv = mtile_dot<64>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            case 16: zv = mtile_dot<16, NT>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            case 32: zv = mtile_dot<32, NT>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            case 48: zv = mtile_dot<48, NT>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
+            default: zv = mtile_dot<64, NT>(prec, blk, mt, r32 + cb, r64 + cb, lane); break;
           }
           if (lane < 16) zt[cb + mt * 16 + lane] = zv * sc;
         }
@@ -1276,7 +1302,7 @@ __global__ __launch_bounds__(256) void apply_generic_kernel(ApplyArgs a) {
     nh.z = zv_out;
     hold = nh;
   }
-  row_store<MODE>(a, hold);
+  row_store<MODE, NT>(a, hold);
   if (T::PCG) apply_epilogue<MODE>(a, rr, rz, sh, flag);
 }
 
@@ -1887,7 +1913,7 @@ int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_
 
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
                         PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr,
-                        const double *rv = nullptr, const int *dict = nullptr) {
+                        const double *rv = nullptr, const int *dict = nullptr, bool nt = false) {
   SpmvArgs a{};
   a.rv = rv;
   a.o16 = o16;
@@ -1907,7 +1933,10 @@ static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, 
   a.nnz16 = (int32_t)(A->nnz & ~(int64_t)15);
   const uintptr_t al = (uintptr_t)A->val | (uintptr_t)A->col_idx | (uintptr_t)o16;
   a.vec = (al & 15) == 0;
-  if (mode == SPMV_PCG) {
+  if (mode == SPMV_PCG && nt) {
+    const void *k = (const void *)spmv_kernel<SPMV_PCG, true>;
+    hipLaunchKernelGGL((spmv_kernel<SPMV_PCG, true>), dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+  } else if (mode == SPMV_PCG) {
     const void *k = (const void *)spmv_kernel<SPMV_PCG>;
     hipLaunchKernelGGL(spmv_kernel<SPMV_PCG>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
   } else if (mode == SPMV_CG) {
@@ -1941,25 +1970,38 @@ static void launch_persistent(K kernel, hipStream_t s, const ApplyArgs &a, int p
   hipLaunchKernelGGL(kernel, dim3(grid_for_waves(a.ntiles, (const void *)kernel, per_cu_max)), dim3(256), 0, s, a);
 }
 
-template <int B, int MODE>
-static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a) {
+template <int B, int MODE, bool NT>
+static void launch_fast_bmn(int prec, hipStream_t s, const ApplyArgs &a) {
   if constexpr (B >= 32 && MODE != M_UPD) {
     if (a.map.sym) {
       switch (prec) {
-        case P64: launch_persistent(apply_fast_kernel<B, P64, MODE, true>, s, a); break;
-        case P32: launch_persistent(apply_fast_kernel<B, P32, MODE, true>, s, a); break;
-        case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE, true>, s, a); break;
-        default: launch_persistent(apply_fast_kernel<B, P16, MODE, true>, s, a); break;
+        case P64: launch_persistent(apply_fast_kernel<B, P64, MODE, true, NT>, s, a); break;
+        case P32: launch_persistent(apply_fast_kernel<B, P32, MODE, true, NT>, s, a); break;
+        case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE, true, NT>, s, a); break;
+        default: launch_persistent(apply_fast_kernel<B, P16, MODE, true, NT>, s, a); break;
       }
       return;
     }
   }
   switch (prec) {
-    case P64: launch_persistent(apply_fast_kernel<B, P64, MODE>, s, a); break;
-    case P32: launch_persistent(apply_fast_kernel<B, P32, MODE>, s, a); break;
-    case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE>, s, a); break;
-    default: launch_persistent(apply_fast_kernel<B, P16, MODE>, s, a); break;
+    case P64: launch_persistent(apply_fast_kernel<B, P64, MODE, false, NT>, s, a); break;
+    case P32: launch_persistent(apply_fast_kernel<B, P32, MODE, false, NT>, s, a); break;
+    case PBF16: launch_persistent(apply_fast_kernel<B, PBF16, MODE, false, NT>, s, a); break;
+    default: launch_persistent(apply_fast_kernel<B, P16, MODE, false, NT>, s, a); break;
   }
+}
+
+// the streaming (non-temporal) variants exist for the fused textbook
+// iteration only, the one that runs every iteration of a PCG solve
+template <int B, int MODE>
+static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a, bool nt) {
+  if constexpr (MODE == M_FUSED) {
+    if (nt) {
+      launch_fast_bmn<B, MODE, true>(prec, s, a);
+      return;
+    }
+  }
+  launch_fast_bmn<B, MODE, false>(prec, s, a);
 }
 
 template <int MODE, int B>
@@ -1997,7 +2039,7 @@ static void launch_band(const bjac_handle *h, int prec, hipStream_t s, const App
 }
 
 template <int MODE>
-static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, const ApplyArgs &a) {
+static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, const ApplyArgs &a, bool nt) {
   if constexpr (MODE != M_UPD) {
     if (m.map.w) {
       launch_band<MODE>(h, m.prec, s, a);
@@ -2009,11 +2051,13 @@ static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, co
   const int prec = MODE == M_UPD ? (int)P16 : m.prec;
   if (fast && h->uniform_b) {
     switch (h->uniform_b) {
-      case 16: launch_fast_bm<16, MODE>(prec, s, a); break;
-      case 32: launch_fast_bm<32, MODE>(prec, s, a); break;
-      case 48: launch_fast_bm<48, MODE>(prec, s, a); break;
-      default: launch_fast_bm<64, MODE>(prec, s, a); break;
+      case 16: launch_fast_bm<16, MODE>(prec, s, a, nt); break;
+      case 32: launch_fast_bm<32, MODE>(prec, s, a, nt); break;
+      case 48: launch_fast_bm<48, MODE>(prec, s, a, nt); break;
+      default: launch_fast_bm<64, MODE>(prec, s, a, nt); break;
     }
+  } else if (MODE == M_FUSED && nt) {
+    launch_persistent(apply_generic_kernel<M_FUSED, true>, s, a, kGridPerCuGeneric);
   } else {
     launch_persistent(apply_generic_kernel<MODE>, s, a, kGridPerCuGeneric);
   }
@@ -2022,7 +2066,7 @@ static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, co
 // One launch of the application kernel in the given mode and map.
 static void launch_apply(const bjac_handle *h, int mode, int want_high, const MapSel &m, double *x, double *r,
                          double *z, const double *p, const double *q, const double *rin, PcgState *st, double *part,
-                         hipStream_t s, double *pw = nullptr, double *sw = nullptr) {
+                         hipStream_t s, double *pw = nullptr, double *sw = nullptr, bool nt = false) {
   ApplyArgs a{};
   a.pw = pw;
   a.sw = sw;
@@ -2044,11 +2088,11 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
   a.st = st;
   a.part = part;
   switch (mode) {
-    case M_FUSED: launch_mode<M_FUSED>(h, m, s, a); break;
-    case M_UPD: launch_mode<M_UPD>(h, m, s, a); break;
-    case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a); break;
-    case M_CG: launch_mode<M_CG>(h, m, s, a); break;
-    default: launch_mode<M_APP>(h, m, s, a); break;
+    case M_FUSED: launch_mode<M_FUSED>(h, m, s, a, nt); break;
+    case M_UPD: launch_mode<M_UPD>(h, m, s, a, false); break;
+    case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a, false); break;
+    case M_CG: launch_mode<M_CG>(h, m, s, a, false); break;
+    default: launch_mode<M_APP>(h, m, s, a, false); break;
   }
 }
 
@@ -2091,7 +2135,7 @@ static hipStream_t capture_stream(bjac_handle *M) {
 // launch that decides the map and one application launch per map, of which
 // only the chosen one does work. Events bracket the launches when given.
 static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs &w, bool temporal, const double *p,
-                                 hipStream_t s, hipEvent_t *ev) {
+                                 hipStream_t s, hipEvent_t *ev, bool nt = false) {
   if (M->kind == 1) {
     // the x / r update on 64-row wave tiles (the update mode of the block
     // application kernels, which reads no map)
@@ -2126,7 +2170,7 @@ static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs 
     if (ev) (void)hipEventRecord(ev[2], s);
   } else {
     if (ev) (void)hipEventRecord(ev[0], s);
-    launch_apply(M, M_FUSED, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    launch_apply(M, M_FUSED, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s, nullptr, nullptr, nt);
     if (ev) (void)hipEventRecord(ev[1], s);
   }
 }
@@ -2140,6 +2184,20 @@ static void enqueue_cg_apply(const bjac_handle *M, double *x, const SolveWs &w, 
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 
+// Whether a PCG iteration streams: its SpMV and fused apply read at least the
+// matrix (8-byte values, 1-byte column codes at best, row pointers), the
+// stored inverses and 88 bytes per row of vectors. Beyond twice the 256 MiB
+// last-level cache of the MI355X nothing is left there from one iteration to
+// the next, and the kernels take the non-temporal variants (measured at
+// 192^3, FP16 map, 1.5 GB per iteration: 316.9 -> 288.7 us per iteration);
+// below it part of the data is found there again, and the hints lose it
+// (128^3, FP16 map, 0.42 GB: 87.1 -> 94.6 us).
+static bool streaming(const bjac_csr *A, const bjac_handle *M) {
+  constexpr double kLastLevelCache = 256.0 * 1024 * 1024;
+  const double bytes = (double)A->nnz * 9.0 + 4.0 * (double)(A->n + 1) + (double)M->low_bytes + 88.0 * (double)A->n;
+  return M->kind == 0 && bytes > 2.0 * kLastLevelCache;
+}
+
 // One PCG iteration: q = A p (p updated on the fly), then update + apply;
 // single-reduction form: w = A u with the three dots, then update + apply.
 static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
@@ -2150,8 +2208,9 @@ static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x
     enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr);
     return;
   }
-  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict);
-  enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr);
+  const bool nt = streaming(A, M);
+  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict, nt);
+  enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr, nt);
 }
 
 // Profile mode: the same kernels launched one by one, bracketed by HIP events
