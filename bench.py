@@ -104,8 +104,8 @@ VERIFY = 3
 # workload and kernel. Valid only for the kernel sources they were measured
 # on: reported when the digest of those sources matches, null otherwise.
 TRAFFIC = {
-    "heldout_192:apply": ("921e6c5eba8bd699af1d6a8e7db9bb220aabff4d6ea38e76a483fa9b632f3c0e", 873080704),
-    "heldout_192:spmv": ("921e6c5eba8bd699af1d6a8e7db9bb220aabff4d6ea38e76a483fa9b632f3c0e", 922992420),
+    "heldout_192:apply": ("9a6b29655ab3d2d027ca673d4d06ce90be645381ce151fcd014709987c3b9e05", 884015102),
+    "heldout_192:spmv": ("9a6b29655ab3d2d027ca673d4d06ce90be645381ce151fcd014709987c3b9e05", 900349931),
 }
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
