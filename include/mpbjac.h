@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define MPBJAC_ABI_VERSION 3
+#define MPBJAC_ABI_VERSION 4
 #define BJAC_MAX_BLOCK 64        /* largest diagonal block (rows) */
 #define BJAC_NFEAT 16            /* block features per block */
 #define BJAC_MLP_NPARAM 5443     /* W1[64,16] b1[64] W2[64,64] b2[64] W3[3,64] b3[3] */
@@ -167,7 +167,7 @@ typedef struct {
                                     restart CG (p = z), at most `verify` times
                                     (then BJAC_NOT_CONVERGED). Graph mode only. */
   int32_t variant;               /* bjac_pcg_variant                           */
-  int32_t reserved;              /* 0                                          */
+  int32_t cache_hints;           /* bjac_cache_hints (0 = AUTO)                */
 } bjac_solve_opts;
 
 /* PCG recurrences (both produce the same iterates in exact arithmetic):
@@ -185,6 +185,22 @@ typedef enum {
   BJAC_PCG_TEXTBOOK = 0,
   BJAC_PCG_SINGLE_REDUCTION = 1
 } bjac_pcg_variant;
+
+/* Cache hints of the textbook PCG's product and fused update + application
+ * (they never change a result, only which kernel variant runs):
+ * PLAIN: ordinary loads and stores. STREAM: non-temporal loads and stores of
+ * everything one launch touches once (the matrix is always read
+ * non-temporally), for solves whose iteration moves far more bytes than the
+ * last-level cache holds. AUTO: STREAM when one iteration reads more than
+ * twice the 256 MiB last-level cache of the MI355X (matrix at 9 bytes per
+ * entry, row pointers, the stored low map, 88 bytes per row of vectors),
+ * else PLAIN. Other values: BJAC_EINVAL. The single-reduction recurrence
+ * and the adaptive switch's split launches use plain accesses throughout. */
+typedef enum {
+  BJAC_HINTS_AUTO = 0,
+  BJAC_HINTS_PLAIN = 1,
+  BJAC_HINTS_STREAM = 2
+} bjac_cache_hints;
 
 typedef struct {
   int32_t iters;                 /* x updates performed                        */
@@ -360,7 +376,9 @@ int pcg_solve_noalloc(const bjac_csr *A, const bjac_handle *M, const double *b, 
  * then column. opts: tol, maxit, chunk (iterations per captured graph) are
  * used, and profile (eager launches, kernel times in stats->spmv_ms,
  * apply_ms and update_ms = the per-system reductions); relres_hist and
- * high_hist are ignored; variant must be BJAC_PCG_TEXTBOOK. */
+ * high_hist are ignored; variant must be BJAC_PCG_TEXTBOOK; cache_hints is
+ * ignored (the batched kernels always store non-temporally what only the
+ * next launch reads). */
 /* Launch shape. The matrix-vector product cuts every system into chunks of
  * floor(64 / m) rows (at most 64 (row, column) elements, one wave pass); the
  * chunks are split into 8 runs of about equal cost, one per XCD, whose waves

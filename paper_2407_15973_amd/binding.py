@@ -22,6 +22,7 @@ UNIFORM, FIXED, RULE, LEARNED, EXPLICIT = 0, 1, 2, 3, 4
 TEMPORAL_NONE, TEMPORAL_HL, TEMPORAL_LH = 0, 1, 2
 STORE_FULL, STORE_BAND, STORE_SYM = 0, 1, 2
 PCG_TEXTBOOK, PCG_SINGLE_REDUCTION = 0, 1
+HINTS_AUTO, HINTS_PLAIN, HINTS_STREAM = 0, 1, 2   # bjac_cache_hints
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, EHIP, ENOMEM = 0, 1, -1, -2, -3, -4, -5
 MLP_NPARAM = 5443
 MLP_NBLOB = MLP_NPARAM + 32
@@ -58,7 +59,7 @@ class bjac_info(C.Structure):
 class bjac_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxit", C.c_int32), ("chunk", C.c_int32),
                 ("relres_hist", C.c_void_p), ("high_hist", C.c_void_p), ("profile", C.c_int32),
-                ("verify", C.c_int32), ("variant", C.c_int32), ("reserved", C.c_int32)]
+                ("verify", C.c_int32), ("variant", C.c_int32), ("cache_hints", C.c_int32)]
 
 
 class bjac_stats(C.Structure):
@@ -334,7 +335,8 @@ class Solver:
         self.compact_index = compact_index
 
     def solve(self, A: DeviceCSR, M: BlockJacobi, b, tol=1e-10, maxit=5000, chunk=16, history=False, x=None,
-              raise_on_error=True, profile=False, verify=0, variant=PCG_TEXTBOOK) -> SolveResult:
+              raise_on_error=True, profile=False, verify=0, variant=PCG_TEXTBOOK,
+              cache_hints=HINTS_AUTO) -> SolveResult:
         torch = _torch()
         if self.compact_index:
             nbytes = C.c_size_t()
@@ -346,7 +348,7 @@ class Solver:
         hh = torch.zeros(maxit + 1, dtype=torch.uint8, device=b.device) if history else None
         opts = bjac_solve_opts(tol, maxit, chunk, rh.data_ptr() if rh is not None else None,
                                hh.data_ptr() if hh is not None else None, 1 if profile else 0, int(verify),
-                               int(variant), 0)
+                               int(variant), int(cache_hints))
         st = bjac_stats()
         rc = load().pcg_solve(C.byref(A.c), M.h, _ptr(b), _ptr(x), C.byref(opts), _ptr(self.ws),
                               self.ws.numel(), C.byref(st), _stream())
@@ -365,10 +367,10 @@ class Solver:
 
 
 def solve_noalloc(A: DeviceCSR, M: BlockJacobi, b, x, tol=1e-10, maxit=5000, chunk=16, variant=PCG_TEXTBOOK,
-                  verify=0) -> SolveResult:
+                  verify=0, cache_hints=HINTS_AUTO) -> SolveResult:
     """pcg_solve_noalloc: the solve with the library's static device
     workspace (no allocation inside the call; b and x are the caller's)."""
-    opts = bjac_solve_opts(tol, maxit, chunk, None, None, 0, int(verify), int(variant), 0)
+    opts = bjac_solve_opts(tol, maxit, chunk, None, None, 0, int(verify), int(variant), int(cache_hints))
     st = bjac_stats()
     rc = load().pcg_solve_noalloc(C.byref(A.c), M.h, _ptr(b), _ptr(x), C.byref(opts), C.byref(st), _stream())
     if rc < 0:

@@ -2195,20 +2195,19 @@ static void enqueue_cg_apply(const bjac_handle *M, double *x, const SolveWs &w, 
 static bool streaming(const bjac_csr *A, const bjac_handle *M) {
   constexpr double kLastLevelCache = 256.0 * 1024 * 1024;
   const double bytes = (double)A->nnz * 9.0 + 4.0 * (double)(A->n + 1) + (double)M->low_bytes + 88.0 * (double)A->n;
-  return M->kind == 0 && bytes > 2.0 * kLastLevelCache;
+  return bytes > 2.0 * kLastLevelCache;
 }
 
 // One PCG iteration: q = A p (p updated on the fly), then update + apply;
 // single-reduction form: w = A u with the three dots, then update + apply.
 static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
-                              const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg = false) {
+                              const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg, bool nt) {
   if (ev) (void)hipEventRecord(ev[0], s);
   if (cg) {
     launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict);
     enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr);
     return;
   }
-  const bool nt = streaming(A, M);
   launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict, nt);
   enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr, nt);
 }
@@ -2222,7 +2221,7 @@ struct Prof {
 
 static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, const SolveWs &w, bool temporal,
                         int chunk, int max_launches, hipStream_t s, PcgState &hs, int &launches, Prof &prof,
-                        bool cg) {
+                        bool cg, bool nt) {
   constexpr int EV = 4;  // events per iteration: spmv start, update/apply start, split point, end
   std::vector<hipEvent_t> ev((size_t)EV * chunk);
   // timing-only events: no system-scope cache writeback and invalidation at
@@ -2235,7 +2234,7 @@ static int profile_loop(const bjac_csr *A, const bjac_handle *M, double *x, cons
     const int it0 = hs.iter;
     for (int i = 0; i < chunk; ++i) {
       const bool even = (i & 1) == 0;
-      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, ev.data() + EV * i, cg);
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, ev.data() + EV * i, cg, nt);
     }
     ++launches;
     if (hipMemcpyAsync(&hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -2318,6 +2317,7 @@ static int check_solve(const bjac_csr *A, const bjac_handle *M, const double *b,
   if (A->n != M->n || !A->row_ptr || !A->col_idx || !A->val) return BJAC_EINVAL;
   if (!(opts->tol >= 0.0) || opts->maxit < 1) return BJAC_EINVAL;
   if (opts->variant != BJAC_PCG_TEXTBOOK && opts->variant != BJAC_PCG_SINGLE_REDUCTION) return BJAC_EINVAL;
+  if (opts->cache_hints < BJAC_HINTS_AUTO || opts->cache_hints > BJAC_HINTS_STREAM) return BJAC_EINVAL;
   // the single-reduction form serves stored-inverse maps without the
   // adaptive switch (its update has no relres of the new residual yet)
   if (opts->variant == BJAC_PCG_SINGLE_REDUCTION && (M->policy.temporal != BJAC_TEMPORAL_NONE || M->kind != 0))
@@ -2343,6 +2343,7 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
                      const SolveWs &w, const void *workspace, hipStream_t s, bool graphs, bjac_stats *stats) {
   const bool temporal = M->policy.temporal != BJAC_TEMPORAL_NONE;
   const bool cg = opts->variant == BJAC_PCG_SINGLE_REDUCTION;
+  const bool nt = opts->cache_hints == BJAC_HINTS_STREAM || (opts->cache_hints == BJAC_HINTS_AUTO && streaming(A, M));
   int chunk = opts->chunk > 0 ? opts->chunk : 16;
   chunk += chunk & 1;  // even: the p buffers return to their roles
 
@@ -2376,7 +2377,7 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
   std::vector<uintptr_t> key;
   if (graphs && !opts->profile)
     key = {(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val, (uintptr_t)A->n, (uintptr_t)x,
-           (uintptr_t)workspace, (uintptr_t)chunk, (uintptr_t)w.o16, (uintptr_t)cg};
+           (uintptr_t)workspace, (uintptr_t)chunk, (uintptr_t)w.o16, (uintptr_t)cg, (uintptr_t)nt};
   if (graphs && !opts->profile && (!M->gexec || M->gkey != key)) {
     if (M->gexec) {
       (void)hipGraphExecDestroy(M->gexec);
@@ -2387,7 +2388,7 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
     MPB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < chunk; ++i) {
       const bool even = (i & 1) == 0;
-      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, cs, nullptr, cg);
+      enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, cs, nullptr, cg, nt);
     }
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess) {
@@ -2411,7 +2412,7 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
   MPB_HIP(hipStreamSynchronize(s));
   Prof prof;
   if (opts->profile) {
-    int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof, cg);
+    int rc = profile_loop(A, M, x, w, temporal, chunk, max_launches, s, hs, launches, prof, cg, nt);
     if (rc) return rc;
   } else {
     for (;;) {
@@ -2421,7 +2422,7 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
         } else {
           for (int i = 0; i < chunk; ++i) {
             const bool even = (i & 1) == 0;
-            enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, nullptr, cg);
+            enqueue_iteration(A, M, x, w, temporal, even ? w.pa : w.pb, even ? w.pb : w.pa, s, nullptr, cg, nt);
           }
           MPB_HIP(hipGetLastError());
         }

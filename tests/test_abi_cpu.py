@@ -29,7 +29,7 @@ def test_library_loads_and_exports_all_symbols():
     L = binding.load()
     for name in _declared():
         assert hasattr(L, name), name
-    assert L.bjac_abi_version() == 3
+    assert L.bjac_abi_version() == 4
     assert L.bjac_strerror(-2).decode().startswith("a diagonal block")
 
 
