@@ -186,16 +186,17 @@ typedef enum {
   BJAC_PCG_SINGLE_REDUCTION = 1
 } bjac_pcg_variant;
 
-/* Cache hints of the textbook PCG's product and fused update + application
- * (they never change a result, only which kernel variant runs):
+/* Cache hints of the launches of a PCG iteration: the product and the update
+ * + application, in both recurrences and with the adaptive switch (they never
+ * change a result, only which kernel variant runs):
  * PLAIN: ordinary loads and stores. STREAM: non-temporal loads and stores of
  * everything one launch touches once (the matrix is always read
  * non-temporally), for solves whose iteration moves far more bytes than the
  * last-level cache holds. AUTO: STREAM when one iteration reads more than
  * twice the 256 MiB last-level cache of the MI355X (matrix at 9 bytes per
  * entry, row pointers, the stored low map, 88 bytes per row of vectors),
- * else PLAIN. Other values: BJAC_EINVAL. The single-reduction recurrence
- * and the adaptive switch's split launches use plain accesses throughout. */
+ * else PLAIN. Other values: BJAC_EINVAL. Band-stored and paper-mode
+ * applications use plain accesses throughout. */
 typedef enum {
   BJAC_HINTS_AUTO = 0,
   BJAC_HINTS_PLAIN = 1,

@@ -985,16 +985,16 @@ __device__ __forceinline__ RowIn row_load(const ApplyArgs &a, bool real, int gro
     v.q = ld_hint<NT>(a.q + gc);
     v.r = ld_hint<NT>(a.r + gc);
   } else if constexpr (ModeTraits<MODE>::CG) {
-    v.x = a.x[gc];
-    v.p = a.pw[gc];
-    v.q = a.sw[gc];
-    v.r = a.r[gc];
-    v.u = a.z[gc];
-    v.w = a.q[gc];
+    v.x = ld_hint<NT>(a.x + gc);
+    v.p = ld_hint<NT>(a.pw + gc);
+    v.q = ld_hint<NT>(a.sw + gc);
+    v.r = ld_hint<NT>(a.r + gc);
+    v.u = ld_hint<NT>(a.z + gc);
+    v.w = ld_hint<NT>(a.q + gc);
   } else if constexpr (MODE == M_APP) {
     v.r = a.rin[gc];
   } else {
-    v.r = a.r[gc];
+    v.r = ld_hint<NT>(a.r + gc);
   }
   if (!real) v = RowIn{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   return v;
@@ -1027,8 +1027,8 @@ __device__ __forceinline__ void row_store(const ApplyArgs &a, const RowHold &h) 
     st_hint<NT>(h.r, a.r + h.grow);
   }
   if constexpr (ModeTraits<MODE>::CG) {
-    a.pw[h.grow] = h.p;
-    a.sw[h.grow] = h.s;
+    st_hint<NT>(h.p, a.pw + h.grow);
+    st_hint<NT>(h.s, a.sw + h.grow);
   }
   if constexpr (ModeTraits<MODE>::APP) st_hint<NT>(h.z, a.z + h.grow);
 }
@@ -1939,6 +1939,9 @@ static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, 
   } else if (mode == SPMV_PCG) {
     const void *k = (const void *)spmv_kernel<SPMV_PCG>;
     hipLaunchKernelGGL(spmv_kernel<SPMV_PCG>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
+  } else if (mode == SPMV_CG && nt) {
+    const void *k = (const void *)spmv_kernel<SPMV_CG, true>;
+    hipLaunchKernelGGL((spmv_kernel<SPMV_CG, true>), dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
   } else if (mode == SPMV_CG) {
     const void *k = (const void *)spmv_kernel<SPMV_CG>;
     hipLaunchKernelGGL(spmv_kernel<SPMV_CG>, dim3(grid_for_waves(a.ntiles, k)), dim3(256), 0, s, a);
@@ -1991,11 +1994,11 @@ static void launch_fast_bmn(int prec, hipStream_t s, const ApplyArgs &a) {
   }
 }
 
-// the streaming (non-temporal) variants exist for the fused textbook
-// iteration only, the one that runs every iteration of a PCG solve
+// the streaming (non-temporal) variants exist for the modes of a PCG
+// iteration, not for the standalone application
 template <int B, int MODE>
 static void launch_fast_bm(int prec, hipStream_t s, const ApplyArgs &a, bool nt) {
-  if constexpr (MODE == M_FUSED) {
+  if constexpr (MODE != M_APP) {
     if (nt) {
       launch_fast_bmn<B, MODE, true>(prec, s, a);
       return;
@@ -2056,8 +2059,8 @@ static void launch_mode(const bjac_handle *h, const MapSel &m, hipStream_t s, co
       case 48: launch_fast_bm<48, MODE>(prec, s, a, nt); break;
       default: launch_fast_bm<64, MODE>(prec, s, a, nt); break;
     }
-  } else if (MODE == M_FUSED && nt) {
-    launch_persistent(apply_generic_kernel<M_FUSED, true>, s, a, kGridPerCuGeneric);
+  } else if (MODE != M_APP && nt) {
+    launch_persistent(apply_generic_kernel<MODE, true>, s, a, kGridPerCuGeneric);
   } else {
     launch_persistent(apply_generic_kernel<MODE>, s, a, kGridPerCuGeneric);
   }
@@ -2089,9 +2092,9 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
   a.part = part;
   switch (mode) {
     case M_FUSED: launch_mode<M_FUSED>(h, m, s, a, nt); break;
-    case M_UPD: launch_mode<M_UPD>(h, m, s, a, false); break;
-    case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a, false); break;
-    case M_CG: launch_mode<M_CG>(h, m, s, a, false); break;
+    case M_UPD: launch_mode<M_UPD>(h, m, s, a, nt); break;
+    case M_APPDEV: launch_mode<M_APPDEV>(h, m, s, a, nt); break;
+    case M_CG: launch_mode<M_CG>(h, m, s, a, nt); break;
     default: launch_mode<M_APP>(h, m, s, a, false); break;
   }
 }
@@ -2163,10 +2166,10 @@ static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs 
   }
   if (temporal) {
     if (ev) (void)hipEventRecord(ev[0], s);
-    launch_apply(M, M_UPD, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    launch_apply(M, M_UPD, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s, nullptr, nullptr, nt);
     if (ev) (void)hipEventRecord(ev[1], s);
-    launch_apply(M, M_APPDEV, 1, sel_hi(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
-    launch_apply(M, M_APPDEV, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s);
+    launch_apply(M, M_APPDEV, 1, sel_hi(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s, nullptr, nullptr, nt);
+    launch_apply(M, M_APPDEV, 0, sel_lo(M), x, w.r, w.z, p, w.q, nullptr, w.st, w.part2, s, nullptr, nullptr, nt);
     if (ev) (void)hipEventRecord(ev[2], s);
   } else {
     if (ev) (void)hipEventRecord(ev[0], s);
@@ -2178,9 +2181,10 @@ static void enqueue_update_apply(const bjac_handle *M, double *x, const SolveWs 
 // The single-reduction iteration's update + application: p = u + beta p,
 // s = w + beta s, x += alpha p, r -= alpha s, u = M^-1 r (u in z, w in q, p in
 // pa, s in pb; p, s and u are updated in place: each row reads only itself).
-static void enqueue_cg_apply(const bjac_handle *M, double *x, const SolveWs &w, hipStream_t s, hipEvent_t *ev) {
+static void enqueue_cg_apply(const bjac_handle *M, double *x, const SolveWs &w, hipStream_t s, hipEvent_t *ev,
+                             bool nt = false) {
   if (ev) (void)hipEventRecord(ev[0], s);
-  launch_apply(M, M_CG, 0, sel_lo(M), x, w.r, w.z, nullptr, w.q, nullptr, w.st, nullptr, s, w.pa, w.pb);
+  launch_apply(M, M_CG, 0, sel_lo(M), x, w.r, w.z, nullptr, w.q, nullptr, w.st, nullptr, s, w.pa, w.pb, nt);
   if (ev) (void)hipEventRecord(ev[1], s);
 }
 
@@ -2204,8 +2208,8 @@ static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x
                               const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg, bool nt) {
   if (ev) (void)hipEventRecord(ev[0], s);
   if (cg) {
-    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict);
-    enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr);
+    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict, nt);
+    enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr, nt);
     return;
   }
   launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict, nt);
