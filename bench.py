@@ -79,11 +79,26 @@ def index_bytes(A, codes=True):
     return 2 if far <= 32767 else 4
 
 
-def spmv_bytes(n, nnz, ib=4):
+def value_bytes(A, ib):
+    """Bytes per matrix value the PCG SpMV reads: 1 when the column offsets are
+    8-bit coded (ib == 1) and the matrix holds at most 256 distinct values
+    (bitwise; none equal to the dictionary's empty key), the solver's 8-bit
+    value codes, else 8."""
+    import numpy as np
+    if ib != 1 or not A.nnz:
+        return 8
+    bits = np.ascontiguousarray(A.val, dtype=np.float64).view(np.uint64)
+    u = np.unique(bits)
+    return 1 if len(u) <= 256 and not np.any(u == np.uint64(0x7FF4DEADBEEF0001)) else 8
+
+
+def spmv_bytes(n, nnz, ib=4, vb=8):
     """Algorithmic bytes of one SpMV launch with the folded p update: CSR values
-    and column indices (ib bytes each; 1 KiB of dictionary with 8-bit codes),
-    row pointers, z and p_old read once, p_new and q written."""
-    return (8 + ib) * nnz + 4 * (n + 1) + 32 * n + (1024 if ib == 1 else 0)
+    (vb bytes each; 2 KiB of dictionary with 8-bit value codes) and column
+    indices (ib bytes each; 1 KiB of dictionary with 8-bit codes), row
+    pointers, z and p_old read once, p_new and q written."""
+    return ((vb + ib) * nnz + 4 * (n + 1) + 32 * n + (1024 if ib == 1 else 0)
+            + (2048 if vb == 1 else 0))
 
 
 def apply_bytes(n, nb, ntiles, stored_bytes, band=False):
@@ -240,7 +255,8 @@ def bench_diff3d(args):
     _, rp16, _ = step(pol16, profile=True)
     info16 = M16.info()
     ntiles = info16["ntiles"]
-    kb = {"spmv": spmv_bytes(n, nnz, index_bytes(p.A)), "apply": apply_bytes(n, nb, ntiles, info16["low_bytes"])}
+    ib = index_bytes(p.A)
+    kb = {"spmv": spmv_bytes(n, nnz, ib, value_bytes(p.A, ib)), "apply": apply_bytes(n, nb, ntiles, info16["low_bytes"])}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp16.kernel_ms[name]
@@ -664,7 +680,7 @@ def bench_policies(args):
     M, rp, _ = step(pols[head], profile=True)
     info = M.info()
     ib = index_bytes(p.A)
-    kb = {"spmv": spmv_bytes(n, nnz, ib), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
+    kb = {"spmv": spmv_bytes(n, nnz, ib, value_bytes(p.A, ib)), "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"])}
     kern = {}
     for name in ("spmv", "apply"):
         tot, cnt = rp.kernel_ms[name]
@@ -837,6 +853,7 @@ def bench_band(args):
     S = p.A.to_scipy()
     bn = float(np.linalg.norm(p.b))
     ib = index_bytes(p.A)
+    vb = value_bytes(p.A, ib)
     rows, kern_all = {}, {}
     for name, pol in pols.items():
         for _ in range(args.warmup):
@@ -859,7 +876,7 @@ def bench_band(args):
                       "max_width": int(w.max()) if is_band else None}
         # per-kernel event timing of the same solve
         _, rp, _ = step(pol, profile=True)
-        kb = {"spmv": spmv_bytes(n, nnz, ib),
+        kb = {"spmv": spmv_bytes(n, nnz, ib, vb),
               "apply": apply_bytes(n, nb, info["ntiles"], info["low_bytes"], band=is_band)}
         kern = {}
         for kname in ("spmv", "apply"):
@@ -985,7 +1002,7 @@ def bench_paper(args):
             for pname, low in (("fMP", True), ("uniform", False)):
                 M = mb.PaperBJAC(Ad, bp, k=2, t=2, low=low)
                 rp = S.solve(Ad, M, b, tol=1e-10, maxit=2000, profile=True)
-                kb = {"spmv": spmv_bytes(A.n, A.nnz, index_bytes(A)), "apply": poly_apply_bytes(A.n, A.nnz, 2, 2, 4 if low else 8),
+                kb = {"spmv": spmv_bytes(A.n, A.nnz, index_bytes(A), value_bytes(A, index_bytes(A))), "apply": poly_apply_bytes(A.n, A.nnz, 2, 2, 4 if low else 8),
                       "update": 48 * A.n}
                 for kname in ("spmv", "apply", "update"):
                     tot, cnt = rp.kernel_ms[kname]

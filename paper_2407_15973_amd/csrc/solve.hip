@@ -283,6 +283,79 @@ __global__ __launch_bounds__(256) void idx_encode_kernel(int n, const int32_t *r
   if (!ok) __hip_atomic_store(cidx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// 8-bit codes of the matrix values (a value dictionary, as in CSR-VI, Kourtis,
+// Goumas and Koziris 2008). Matrices of PDEs with piecewise-constant
+// coefficients hold few distinct values (17 on the 192^3 held-out problem),
+// so with 8-bit column codes as well an entry takes 2 bytes instead of 9.
+// The table is keyed by the value's 64 bits (exact: +0 and -0, and every NaN
+// pattern, are distinct keys); a value equal to the empty key, or more than
+// 256 distinct values, set *overflow and the products read the 8-byte values.
+constexpr uint64_t kVDictEmpty = 0x7FF4DEADBEEF0001ull;   // a signalling NaN pattern
+
+__device__ __forceinline__ unsigned vdict_hash(uint64_t b) { return (unsigned)((b * 0x9E3779B97F4A7C15ull) >> 56); }
+
+template <bool GLOBAL>
+__device__ __forceinline__ bool vdict_insert(unsigned long long *tab, unsigned long long b) {
+  if (b == kVDictEmpty) return false;
+  unsigned h = vdict_hash(b);
+  for (int probe = 0; probe < kDictSize; ++probe, h = (h + 1) & (kDictSize - 1)) {
+    const unsigned long long cur = GLOBAL ? __hip_atomic_load(tab + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                          : __hip_atomic_load(tab + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == b) return true;
+    if (cur == kVDictEmpty) {
+      const unsigned long long old = atomicCAS(tab + h, (unsigned long long)kVDictEmpty, b);
+      if (old == kVDictEmpty || old == b) return true;
+    }
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(256) void vdict_fill_kernel(unsigned long long *gtab, int *overflow) {
+  gtab[threadIdx.x] = kVDictEmpty;
+  if (threadIdx.x == 0) *overflow = 0;
+}
+
+__global__ __launch_bounds__(256) void vdict_build_kernel(int64_t nnz, const double *v, unsigned long long *gtab,
+                                                          int *overflow) {
+  __shared__ unsigned long long tab[kDictSize];
+  __shared__ int ovf;
+  tab[threadIdx.x] = kVDictEmpty;
+  if (threadIdx.x == 0) ovf = 0;
+  __syncthreads();
+  bool ok = true;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz && ok; k += (int64_t)gridDim.x * 256)
+    ok = vdict_insert<false>(tab, (unsigned long long)__double_as_longlong(v[k]));
+  if (!ok) ovf = 1;
+  __syncthreads();
+  const unsigned long long b = tab[threadIdx.x];
+  if (!ovf && b != kVDictEmpty && !vdict_insert<true>(gtab, b)) ovf = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && ovf) __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The value codes, when the dictionary holds every value and the column
+// structure is 8-bit coded (*cidx == 2); vcode_commit_kernel then raises
+// *cidx to 3 (a launch of its own: every workgroup here reads *cidx first).
+__global__ __launch_bounds__(256) void val_encode_kernel(int64_t nnz, const double *v,
+                                                         const unsigned long long *gtab, const int *overflow,
+                                                         uint8_t *v8, const int32_t *cidx) {
+  __shared__ unsigned long long tab[kDictSize];
+  tab[threadIdx.x] = gtab[threadIdx.x];
+  __syncthreads();
+  if (*overflow != 0 || *cidx != 2) return;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * 256) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v[k]);
+    unsigned h = vdict_hash(b);
+    // present: the build inserted every value (the probe count is bounded all the same)
+    for (int probe = 0; probe < kDictSize && tab[h] != b; ++probe) h = (h + 1) & (kDictSize - 1);
+    v8[k] = (uint8_t)h;
+  }
+}
+
+__global__ void vcode_commit_kernel(const int *overflow, int32_t *cidx) {
+  if (*overflow == 0 && *cidx == 2) *cidx = 3;
+}
+
 __global__ __launch_bounds__(256) void fill_empty_kernel(double *p, int n) {
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) ((uint64_t *)p)[i] = kEmpty;
 }
@@ -305,14 +378,17 @@ struct SpmvArgs {
   const int16_t *o16;   // PCG / CG: col - row of every entry (st->cidx == 1), or its 8-bit code
                         // (st->cidx == 2: the same region read as bytes)
   const int *dict;      // the codes' dictionary: offset of code c at dict[c]
+  const uint8_t *v8;    // st->cidx == 3: the 8-bit value codes (16-byte aligned)
+  const double *vdict;  // st->cidx == 3: value of code c at vdict[c]
   int32_t nnz8;         // nnz rounded down to a multiple of 8: whole 16-byte chunks of every array
   int32_t nnz16;        // nnz rounded down to a multiple of 16 (8-bit codes: 16 per chunk)
   int32_t vec;          // values and indices 16-byte aligned: tiles may be staged in 16-byte chunks
 };
 
 // Column index modes of the SpMV tiles: the CSR's 32-bit indices, 16-bit
-// offsets col - row, 8-bit codes of col - row.
-enum IdxMode { IX32 = 0, IX16 = 1, IX8 = 2 };
+// offsets col - row, 8-bit codes of col - row; IX8V: 8-bit codes of col - row
+// and 8-bit codes of the values.
+enum IdxMode { IX32 = 0, IX16 = 1, IX8 = 2, IX8V = 3 };
 template <int IX>
 using IdxT = std::conditional_t<IX == IX32, int32_t, std::conditional_t<IX == IX16, int16_t, uint8_t>>;
 
@@ -326,9 +402,9 @@ using IdxT = std::conditional_t<IX == IX32, int32_t, std::conditional_t<IX == IX
 // when the row stores its diagonal.
 template <bool PCG, int IX, bool FIND = PCG>
 __device__ __forceinline__ double row_dot(const double *__restrict__ z, const double *__restrict__ pold,
-                                          const IdxT<IX> *__restrict__ cidx, const double *__restrict__ vals,
+                                          const IdxT<IX> *__restrict__ cidx, const void *__restrict__ vals,
                                           double beta, int base, int len, int row, double &prow, bool &found,
-                                          const int *dict) {
+                                          const int *dict, const double *vdict) {
   constexpr int U = 7;
   double acc = 0.0;
   for (int k0 = 0; k0 < len; k0 += U) {
@@ -340,7 +416,9 @@ __device__ __forceinline__ double row_dot(const double *__restrict__ z, const do
       if constexpr (IX == IX32) cs[k] = cidx[idx];
       else if constexpr (IX == IX16) cs[k] = (int)cidx[idx] + row;
       else cs[k] = dict[cidx[idx]] + row;
-      const double v = vals[idx];
+      double v;
+      if constexpr (IX == IX8V) v = vdict[((const uint8_t *)vals)[idx]];
+      else v = ((const double *)vals)[idx];
       vs[k] = (k0 + k < len) ? v : 0.0;
     }
 #pragma unroll
@@ -405,14 +483,17 @@ struct Dots3 {
 };
 
 template <int SM, int IX, bool NT>
-__device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc, const int *dict) {
+__device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, double *sv, int *sc, const int *dict,
+                                            const double *vdict) {
   constexpr bool PCG = SM == SPMV_PCG;   // p = z + beta p_old gathered, (p, q)
   constexpr bool CG = SM == SPMV_CG;     // u gathered, (r, r), (r, u), (w, u)
+  constexpr bool VC = IX == IX8V;        // 8-bit value codes in place of the values
   constexpr int SLOT = kSpmvSlot;
   using IT = IdxT<IX>;
-  constexpr int NV = SLOT * 8 / 16 / 64;                              // value chunks per lane
+  constexpr int VB = VC ? 1 : 8;                                       // bytes per value
+  constexpr int NV = (SLOT * VB + 16 * 64 - 1) / 16 / 64;             // value chunks per lane
   constexpr int NC = (SLOT * (int)sizeof(IT) + 16 * 64 - 1) / 16 / 64;  // index chunks per lane
-  constexpr int EV = 2, EC = 16 / (int)sizeof(IT);                    // entries per chunk
+  constexpr int EV = 16 / VB, EC = 16 / (int)sizeof(IT);              // entries per chunk
   constexpr int GA = EC > 8 ? EC : 8;                                 // window alignment (entries)
   const int32_t *__restrict__ rp = a.rp;
   const IT *__restrict__ cix = IX == IX32 ? (const IT *)a.ci : (const IT *)a.o16;
@@ -451,7 +532,7 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
   };
   auto stage = [&](int base, int need, u32x4 (&gv)[NV], u32x4 (&gc)[NC]) {
     const u32x4 zero = {0u, 0u, 0u, 0u};
-    const u32x4 *vp = (const u32x4 *)(vv_g + base);
+    const u32x4 *vp = VC ? (const u32x4 *)(a.v8 + base) : (const u32x4 *)(vv_g + base);
     const u32x4 *cp = (const u32x4 *)(cix + base);
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -503,10 +584,11 @@ __device__ __forceinline__ Dots3 spmv_tiles(const SpmvArgs &a, double beta, doub
         if (c * EC < need_c) ((u32x4 *)sc)[c] = gc[q];
       }
       wave_lds_sync();
-      acc = row_dot<PCG, IX, PCG || CG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, dict);
+      acc = row_dot<PCG, IX, PCG || CG>(z, pold, sci, sv, beta, s_c - base_c, len, row, prow, found, dict, vdict);
       wave_lds_sync();
     } else {
-      acc = row_dot<PCG, IX, PCG || CG>(z, pold, cix, vv_g, beta, s_c, len, row, prow, found, dict);
+      acc = row_dot<PCG, IX, PCG || CG>(z, pold, cix, VC ? (const void *)a.v8 : (const void *)vv_g, beta, s_c, len,
+                                        row, prow, found, dict, vdict);
     }
     s_has = has;
     s_row = row;
@@ -599,6 +681,7 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   __shared__ double sh[4];
   __shared__ int flag, ok;
   __shared__ int sdict[kDictSize];
+  __shared__ double svdict[kDictSize];
   // status and cidx are adjacent: one load before the early exit
   int2 sr = make_int2(ST_RUNNING, 0);
   if (PCG || CG) sr = *(const int2 *)&a.st->status;
@@ -608,17 +691,22 @@ __global__ __launch_bounds__(256) void spmv_kernel(SpmvArgs a) {
   const int ix = (PCG || CG) && a.o16 ? sr.y : IX32;   // uniform over the grid
   Dots3 dot;
   if constexpr (PCG || CG) {
-    if (ix == IX8) {
+    if (ix == IX8V) {
+      sdict[threadIdx.x] = a.dict[threadIdx.x];
+      svdict[threadIdx.x] = a.vdict[threadIdx.x];
+      __syncthreads();
+      dot = spmv_tiles<SM, IX8V, NT>(a, beta, svs[wv], scs[wv], sdict, svdict);
+    } else if (ix == IX8) {
       sdict[threadIdx.x] = a.dict[threadIdx.x];
       __syncthreads();
-      dot = spmv_tiles<SM, IX8, NT>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX8, NT>(a, beta, svs[wv], scs[wv], sdict, svdict);
     } else if (ix == IX16) {
-      dot = spmv_tiles<SM, IX16, NT>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX16, NT>(a, beta, svs[wv], scs[wv], sdict, svdict);
     } else {
-      dot = spmv_tiles<SM, IX32, NT>(a, beta, svs[wv], scs[wv], sdict);
+      dot = spmv_tiles<SM, IX32, NT>(a, beta, svs[wv], scs[wv], sdict, svdict);
     }
   } else {
-    dot = spmv_tiles<SPMV_PLAIN, IX32, NT>(a, beta, svs[wv], scs[wv], sdict);
+    dot = spmv_tiles<SPMV_PLAIN, IX32, NT>(a, beta, svs[wv], scs[wv], sdict, svdict);
   }
   if constexpr (PCG) {
     const double bs = block_sum(dot.a, sh);
@@ -1911,13 +1999,23 @@ int launch_off16(int n, const int32_t *rp, const int32_t *ci, int16_t *o, int32_
   return BJAC_OK;
 }
 
+// The 8-bit value codes live in the compact-index region after the 8-bit
+// column codes, from the first 16-byte boundary at or after nnz bytes (the
+// region holds nnz + 16 int16 slots: room for both).
+static const uint8_t *value_codes(const int16_t *o16, int64_t nnz) {
+  return (const uint8_t *)o16 + ((nnz + 15) & ~(int64_t)15);
+}
+
 static void launch_spmv(const bjac_csr *A, const double *z, const double *pold, double *pnew, double *q,
                         PcgState *st, double *part, int mode, hipStream_t s, const int16_t *o16 = nullptr,
-                        const double *rv = nullptr, const int *dict = nullptr, bool nt = false) {
+                        const double *rv = nullptr, const int *dict = nullptr, bool nt = false,
+                        const double *vdict = nullptr) {
   SpmvArgs a{};
   a.rv = rv;
   a.o16 = o16;
   a.dict = dict;
+  a.v8 = o16 ? value_codes(o16, A->nnz) : nullptr;
+  a.vdict = vdict;
   a.n = (int32_t)A->n;
   a.ntiles = (int)((A->n + kSpmvRows - 1) / kSpmvRows);
   a.rp = A->row_ptr;
@@ -2102,8 +2200,9 @@ static void launch_apply(const bjac_handle *h, int mode, int want_high, const Ma
 struct SolveWs {
   double *r, *z, *pa, *pb, *q, *part1, *part2, *part3;
   PcgState *st;
-  int16_t *o16;   // [nnz] row-relative column indices (or their 8-bit codes), or null
+  int16_t *o16;   // [nnz + 16] row-relative column indices (or their 8-bit codes, then the value codes), or null
   int *dict;      // [256] the codes' dictionary, then the overflow flag
+  double *vdict;  // [256] the value codes' dictionary, then the overflow flag (as int)
   size_t bytes;
 };
 
@@ -2119,8 +2218,9 @@ static SolveWs carve_solve(void *ws, int64_t n, int64_t nnz16 = 0) {
   w.part2 = w.part1 + kMaxGrid;
   w.part3 = c.take<double>(kMaxGrid);      // true-residual partials
   w.st = c.take<PcgState>(1);
-  w.o16 = nnz16 > 0 ? c.take<int16_t>(nnz16) : nullptr;
+  w.o16 = nnz16 > 0 ? c.take<int16_t>(nnz16 + 16) : nullptr;
   w.dict = nnz16 > 0 ? c.take<int>(kDictSize + 64) : nullptr;
+  w.vdict = nnz16 > 0 ? c.take<double>(kDictSize + 8) : nullptr;
   w.bytes = c.used;
   return w;
 }
@@ -2208,11 +2308,11 @@ static void enqueue_iteration(const bjac_csr *A, const bjac_handle *M, double *x
                               const double *pold, double *pnew, hipStream_t s, hipEvent_t *ev, bool cg, bool nt) {
   if (ev) (void)hipEventRecord(ev[0], s);
   if (cg) {
-    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict, nt);
+    launch_spmv(A, w.z, nullptr, nullptr, w.q, w.st, w.part1, SPMV_CG, s, w.o16, w.r, w.dict, nt, w.vdict);
     enqueue_cg_apply(M, x, w, s, ev ? ev + 1 : nullptr, nt);
     return;
   }
-  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict, nt);
+  launch_spmv(A, w.z, pold, pnew, w.q, w.st, w.part1, SPMV_PCG, s, w.o16, nullptr, w.dict, nt, w.vdict);
   enqueue_update_apply(M, x, w, temporal, pnew, s, ev ? ev + 1 : nullptr, nt);
 }
 
@@ -2368,6 +2468,14 @@ static int solve_run(const bjac_csr *A, bjac_handle *M, const double *b, double 
                        w.dict + kDictSize);
     hipLaunchKernelGGL(idx_encode_kernel, dim3(G), dim3(256), 0, s, n, A->row_ptr, A->col_idx, (const int *)w.dict,
                        (const int *)(w.dict + kDictSize), (uint8_t *)w.o16, w.o16, &w.st->cidx);
+    // the value codes, after the 8-bit column codes, in the same region
+    unsigned long long *vtab = (unsigned long long *)w.vdict;
+    int *vovf = (int *)(w.vdict + kDictSize);
+    hipLaunchKernelGGL(vdict_fill_kernel, dim3(1), dim3(kDictSize), 0, s, vtab, vovf);
+    hipLaunchKernelGGL(vdict_build_kernel, dim3(G), dim3(256), 0, s, A->nnz, A->val, vtab, vovf);
+    hipLaunchKernelGGL(val_encode_kernel, dim3(G), dim3(256), 0, s, A->nnz, A->val, (const unsigned long long *)vtab,
+                       (const int *)vovf, (uint8_t *)value_codes(w.o16, A->nnz), (const int32_t *)&w.st->cidx);
+    hipLaunchKernelGGL(vcode_commit_kernel, dim3(1), dim3(1), 0, s, (const int *)vovf, &w.st->cidx);
   }
   hipLaunchKernelGGL(pcg_fill_kernel, dim3(1024), dim3(256), 0, s, A->n, x, w.r, b, w.pa, w.q,
                      cg ? w.z : nullptr, cg ? w.pb : nullptr);

@@ -277,14 +277,37 @@ def test_compact_column_index_gives_identical_iterates():
     assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
 
 
-def test_unaligned_matrix_arrays_read_unstaged_with_identical_iterates():
+def _piecewise_constant(shape):
+    # two coefficient values on two slabs: a handful of distinct matrix values
+    k = np.ones(shape)
+    k[: shape[0] // 2] = 100.0
+    return gen.diffusion3d(k)
+
+
+def test_value_codes_give_identical_iterates():
+    # piecewise-constant coefficients: few distinct values, so the SpMV reads
+    # 8-bit value codes beside the 8-bit column codes; against the CSR's own
+    # arrays: the same products in the same order, identical iterates
+    A = _piecewise_constant((14, 12, 10))
+    assert len(np.unique(A.val)) <= 256
+    b = np.random.default_rng(31).uniform(-1, 1, A.n)
+    r1, r2 = _solve_pair(A, gen.uniform_blocks(A.n, 32), b, 2000)
+    assert r1.status == mb.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.relres_hist, r2.relres_hist)
+    assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
+
+
+@pytest.mark.parametrize("coef", ["loguniform", "piecewise"])
+def test_unaligned_matrix_arrays_read_unstaged_with_identical_iterates(coef):
     # values and indices not 16-byte aligned: the SpMV reads every tile's rows
-    # straight from memory instead of staging 16-byte chunks; the same products
-    # in the same order, identical iterates
+    # straight from memory instead of staging 16-byte chunks (with 8-bit
+    # value codes too for the piecewise-constant coefficients); the same
+    # products in the same order, identical iterates
     import copy
     import torch
     rng = np.random.default_rng(29)
-    A = gen.diffusion3d(gen.kappa_loguniform((13, 11, 9), rng))
+    A = (gen.diffusion3d(gen.kappa_loguniform((13, 11, 9), rng)) if coef == "loguniform"
+         else _piecewise_constant((13, 11, 9)))
     b = rng.uniform(-1, 1, A.n)
     bp = gen.uniform_blocks(A.n, 32)
     Ad = mb.DeviceCSR(A, dev())
