@@ -119,8 +119,8 @@ VERIFY = 3
 # workload and kernel. Valid only for the kernel sources they were measured
 # on: reported when the digest of those sources matches, null otherwise.
 TRAFFIC = {
-    "heldout_192:apply": ("9a6b29655ab3d2d027ca673d4d06ce90be645381ce151fcd014709987c3b9e05", 884015102),
-    "heldout_192:spmv": ("9a6b29655ab3d2d027ca673d4d06ce90be645381ce151fcd014709987c3b9e05", 900349931),
+    "heldout_192:apply": ("54bc83f21c0e63765b996224c9206b9d97d045b6fd4c2f506a7dd90b3d44f951", 885363386),
+    "heldout_192:spmv": ("54bc83f21c0e63765b996224c9206b9d97d045b6fd4c2f506a7dd90b3d44f951", 539915313),
 }
 TRAFFIC_SOURCES = ("solve.hip", "device_util.hpp", "internal.hpp")
 
