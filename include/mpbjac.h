@@ -311,12 +311,15 @@ int bjac_round(const double *in, void *out, int64_t count, int32_t prec, double 
 
 /* ---- PCG (Sec. 3.2; Sec. 4.2 stopping test, x0 = 0) ---------------------
  * pcg_workspace_query: bytes of the solver workspace for n rows.
- * pcg_workspace_query_csr: the same plus room for a 16-bit copy of A's
- * column structure (2 bytes per non-zero). Given a workspace that large,
- * pcg_solve writes col - row of every entry into it at the start of the call
- * and its matrix-vector products read those 2 bytes instead of the 4-byte
- * column index (when some entry lies more than 32767 rows from its row they
- * keep the 4-byte indices); the iterates are the same either way.
+ * pcg_workspace_query_csr: the same plus room for a compact copy of A
+ * (2 bytes per non-zero, 32 bytes and two 256-entry dictionaries more).
+ * Given a workspace that large, pcg_solve encodes A at the start of the
+ * call and its matrix-vector products read the compact copy: with at most
+ * 256 distinct offsets col - row, a 1-byte code per column, and then with at
+ * most 256 distinct values (bitwise) a 1-byte code per value as well (CSR-VI
+ * value indexing); else the 2-byte offsets col - row when every entry lies
+ * within 32767 rows of its row; else the 4-byte indices and 8-byte values.
+ * The iterates are the same either way.
  * pcg_solve: solves A x = b; b, x device FP64 [n] (x is overwritten). The
  * iterations run as captured HIP graphs of opts->chunk iterations with all
  * scalars on the device; the host reads one status word per graph launch.

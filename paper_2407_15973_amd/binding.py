@@ -323,8 +323,9 @@ class SolveResult:
 
 class Solver:
     """Reusable PCG workspace for one matrix size. ``compact_index`` (default)
-    grows it to hold the 16-bit copy of the matrix's column structure that the
-    SpMV reads (pcg_workspace_query_csr)."""
+    grows it to hold the compact copy of the matrix the SpMV reads
+    (pcg_workspace_query_csr: 8-bit column and value codes, or 16-bit column
+    offsets)."""
 
     def __init__(self, n: int, device="cuda", compact_index=True):
         torch = _torch()
