@@ -297,6 +297,42 @@ def test_value_codes_give_identical_iterates():
     assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
 
 
+def _cycled_values_matrix(n, k):
+    # symmetric 5-band matrix (offsets 0, +-1, +-2): the couplings cycle
+    # through k distinct values, the diagonal is constant and dominant, and
+    # two explicit zeros per 100 rows (stored +0.0 and -0.0, distinct keys of
+    # the value dictionary); k + 3 distinct value patterns in all
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [np.full(n, 6.0)]
+    e = 0
+    for off in (1, 2):
+        i = np.arange(n - off)
+        v = -(1.0 + ((e + i) % k) / 1024.0)
+        e += n
+        rows += [i, i + off]
+        cols += [i + off, i]
+        vals += [v, v]
+    z = np.arange(0, n - 3, 50)
+    rows += [z, z + 3]
+    cols += [z + 3, z]
+    vals += [np.where(z % 100 == 0, 0.0, -0.0)] * 2
+    return gen._csr_from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals))
+
+
+@pytest.mark.parametrize("k", [253, 254])
+def test_value_codes_at_the_dictionary_limit(k):
+    # k = 253: 256 distinct values (bitwise), the dictionary's limit, so the
+    # SpMV reads value codes; k = 254: 257, so it keeps the 8-byte values
+    # (with the 8-bit column codes). Either way the iterates equal those of
+    # the CSR's own arrays
+    A = _cycled_values_matrix(3000, k)
+    assert len(np.unique(A.val.view(np.uint64))) == k + 3
+    b = np.random.default_rng(37).uniform(-1, 1, A.n)
+    r1, r2 = _solve_pair(A, gen.uniform_blocks(A.n, 32), b, 2000)
+    assert r1.status == mb.OK and r1.iters == r2.iters
+    assert np.array_equal(r1.relres_hist, r2.relres_hist)
+    assert np.array_equal(r1.x.cpu().numpy(), r2.x.cpu().numpy())
+
+
 @pytest.mark.parametrize("coef", ["loguniform", "piecewise"])
 def test_unaligned_matrix_arrays_read_unstaged_with_identical_iterates(coef):
     # values and indices not 16-byte aligned: the SpMV reads every tile's rows
